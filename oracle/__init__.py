@@ -1,0 +1,238 @@
+"""Plain FP64 CPU oracle of the improved two-stream flux solve (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  The oracle exists to check the GPU library: only
+the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the GPU library and never
+imports it.
+
+The arithmetic lives in ``rt_oracle.c`` (each function cites the part of the
+paper it follows: Deitrick et al., arXiv 2203.02293, Section 2.2 and
+Appendix B).  This module only builds that file with gcc, marshals numpy
+arrays and exposes:
+
+  planck_bin(T, lam1, lam2)            bin-integrated Planck radiance
+  efit(w0, g0, opts)                   E of Section 2.2.4
+  layer_coeffs(dtau, w0, g0, mu, opts) Appendix B coefficients of one layer
+  assemble(...)/block_thomas(...)      the block system of Section 2.2.2
+  column_bin(...)                      one (column, bin) solve
+  solve(work, opts, ...)               the whole problem (bin sums, heating)
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import dataclasses
+import os
+import pathlib
+import subprocess
+
+import numpy as np
+
+HERE = pathlib.Path(__file__).resolve().parent
+SRC = HERE / "rt_oracle.c"
+LIB = HERE / "liborc_rt.so"
+
+F_GUARD, F_ECLAMP, F_ETAU, F_EDOMAIN, F_INVALID, F_NONFIN = 1, 2, 4, 8, 16, 32
+
+
+def build(force: bool = True) -> pathlib.Path:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP for timing)."""
+    if force or not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+        tmp = LIB.with_suffix(".so.tmp")
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-fopenmp", "-Wall", "-o", str(tmp), str(SRC), "-lm"],
+            check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Opts(ct.Structure):
+    _fields_ = [("improved", ct.c_int32), ("noniso", ct.c_int32), ("e_clamp", ct.c_int32),
+                ("pad_", ct.c_int32), ("eps2", ct.c_double), ("e_tau", ct.c_double),
+                ("g_guard", ct.c_double), ("gravity", ct.c_double), ("cp", ct.c_double)]
+
+
+class Layer(ct.Structure):
+    _fields_ = [(n, ct.c_double) for n in
+                ("E", "zp", "zm", "Tr", "chi", "xi", "psi", "Pi", "Gp", "Gm", "D")] + \
+               [("flags", ct.c_uint32)]
+
+
+_dp = ct.POINTER(ct.c_double)
+_up = ct.POINTER(ct.c_uint32)
+
+
+class Problem(ct.Structure):
+    _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("n_bins", ct.c_int32),
+                ("col_begin", ct.c_int32), ("col_end", ct.c_int32),
+                ("lambda_edges", _dp), ("F_star", _dp), ("p_iface", _dp), ("T_iface", _dp),
+                ("dtau", _dp), ("w0", _dp), ("g0", _dp), ("mu_star", _dp), ("T_int", _dp),
+                ("F_toa", _dp), ("F_up", _dp), ("F_dn", _dp), ("F_beam", _dp), ("F_net", _dp),
+                ("heating", _dp), ("dTdt", _dp), ("F_up_toa_bin", _dp), ("F_up_bin", _dp),
+                ("F_dn_bin", _dp), ("F_beam_bin", _dp), ("flags", _up)]
+
+
+@dataclasses.dataclass
+class Options:
+    """Solver switches (defaults: improved, non-isothermal, Table 3 values)."""
+
+    improved: int = 1
+    noniso: int = 1
+    e_clamp: int = 1
+    eps2: float = 2.0 / 3.0
+    e_tau: float = 1.0e-4
+    g_guard: float = 1.0e-5
+    gravity: float = 47.0
+    cp: float = 12436.0
+
+    def c(self) -> Opts:
+        return Opts(self.improved, self.noniso, self.e_clamp, 0, self.eps2, self.e_tau,
+                    self.g_guard, self.gravity, self.cp)
+
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    global _lib
+    if _lib is None:
+        if not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+            build(force=True)
+        L = ct.CDLL(str(LIB))
+        L.orc_planck_bin.restype = ct.c_double
+        L.orc_planck_bin.argtypes = [ct.c_double, ct.c_double, ct.c_double]
+        L.orc_efit.restype = ct.c_double
+        L.orc_efit.argtypes = [ct.c_double, ct.c_double, ct.POINTER(Opts), _up]
+        L.orc_layer_coeffs.restype = None
+        L.orc_layer_coeffs.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                       ct.POINTER(Opts), ct.POINTER(Layer)]
+        L.orc_assemble.restype = ct.c_int
+        L.orc_assemble.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
+                                   ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
+                                   _dp, _dp, _dp, _dp, _dp, _up]
+        L.orc_block_thomas.restype = ct.c_int
+        L.orc_block_thomas.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_column_bin.restype = ct.c_int
+        L.orc_column_bin.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
+                                     ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
+                                     _dp, _dp, _dp, _up]
+        L.orc_solve.restype = ct.c_int
+        L.orc_solve.argtypes = [ct.POINTER(Problem), ct.POINTER(Opts), ct.c_int]
+        L.orc_max_threads.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray | None):
+    if a is None:
+        return ct.cast(None, _dp)
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- scalar API
+def planck_bin(T: float, lam1: float, lam2: float) -> float:
+    return lib().orc_planck_bin(float(T), float(lam1), float(lam2))
+
+
+def efit(w0: float, g0: float, opts: Options | None = None) -> tuple[float, int]:
+    o = (opts or Options()).c()
+    fl = ct.c_uint32(0)
+    E = lib().orc_efit(float(w0), float(g0), ct.byref(o), ct.byref(fl))
+    return E, fl.value
+
+
+def layer_coeffs(dtau: float, w0: float, g0: float, mu: float,
+                 opts: Options | None = None) -> dict:
+    o = (opts or Options()).c()
+    L = Layer()
+    lib().orc_layer_coeffs(float(dtau), float(w0), float(g0), float(mu), ct.byref(o),
+                           ct.byref(L))
+    return {n: getattr(L, n) for n, _ in Layer._fields_}
+
+
+# ------------------------------------------------------------ one (col, bin)
+def assemble(B, dtau, w0, g0, mu, Fstar, F_boa=0.0, F_toa=0.0, opts: Options | None = None):
+    """Block matrices of one (column, bin): A, B, C [N+1,2,2], D [N+1,2], beam [N+1]."""
+    B, dtau, w0, g0 = map(_f64, (B, dtau, w0, g0))
+    N = dtau.size
+    A, Bm, Cm = (np.zeros((N + 1, 2, 2)) for _ in range(3))
+    D, Fb = np.zeros((N + 1, 2)), np.zeros(N + 1)
+    fl = ct.c_uint32(0)
+    o = (opts or Options()).c()
+    lib().orc_assemble(N, _p(B), _p(dtau), _p(w0), _p(g0), 1, float(mu), float(Fstar),
+                       float(F_boa), float(F_toa), ct.byref(o), _p(A), _p(Bm), _p(Cm),
+                       _p(D), _p(Fb), ct.byref(fl))
+    return A, Bm, Cm, D, Fb, fl.value
+
+
+def block_thomas(A, Bm, Cm, D) -> np.ndarray:
+    A, Bm, Cm, D = map(_f64, (A, Bm, Cm, D))
+    N = A.shape[0] - 1
+    X = np.zeros((N + 1, 2))
+    rc = lib().orc_block_thomas(N, _p(A), _p(Bm), _p(Cm), _p(D), _p(X))
+    if rc:
+        raise ArithmeticError("singular pivot block")
+    return X
+
+
+def column_bin(B, dtau, w0, g0, mu, Fstar, F_boa=0.0, F_toa=0.0,
+               opts: Options | None = None):
+    """Fluxes of one (column, bin) from interface Planck values B[N+1].
+
+    Returns (F_up, F_dn, F_beam, flags), arrays over interfaces 0 (BOA)..N (TOA).
+    """
+    B, dtau, w0, g0 = map(_f64, (B, dtau, w0, g0))
+    N = dtau.size
+    fu, fd, fb = np.zeros(N + 1), np.zeros(N + 1), np.zeros(N + 1)
+    fl = ct.c_uint32(0)
+    o = (opts or Options()).c()
+    rc = lib().orc_column_bin(N, _p(B), _p(dtau), _p(w0), _p(g0), 1, float(mu), float(Fstar),
+                              float(F_boa), float(F_toa), ct.byref(o), _p(fu), _p(fd), _p(fb),
+                              ct.byref(fl))
+    if rc:
+        raise ArithmeticError("singular pivot block")
+    return fu, fd, fb, fl.value
+
+
+# ----------------------------------------------------------------- problem
+def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
+          cols: tuple[int, int] | None = None, n_threads: int = 0,
+          F_toa: np.ndarray | None = None) -> dict:
+    """Solve every (column, bin) of a workload dict (layouts as in ``synth``).
+
+    ``cols`` restricts the solve to a column range (other outputs stay zero).
+    ``n_threads`` = 0 uses OpenMP's default.
+    """
+    C, N, NB = int(work["n_cols"]), int(work["n_layers"]), int(work["n_bins"])
+    c0, c1 = cols if cols is not None else (0, C)
+    arr = {k: _f64(work[k]) for k in ("lambda_edges", "F_star", "p_iface", "T_iface",
+                                        "dtau", "w0", "g0", "mu_star", "T_int")}
+    Ft = None if F_toa is None else _f64(F_toa)
+    out = {k: np.zeros((N + 1, C)) for k in ("F_up", "F_dn", "F_beam", "F_net")}
+    out["heating"] = np.zeros((N, C))
+    out["dTdt"] = np.zeros((N, C))
+    out["F_up_toa_bin"] = np.zeros((C, NB))
+    out["flags"] = np.zeros(C, dtype=np.uint32)
+    if per_bin:
+        for k in ("F_up_bin", "F_dn_bin", "F_beam_bin"):
+            out[k] = np.zeros((N + 1, C, NB))
+    P = Problem(C, N, NB, c0, c1, _p(arr["lambda_edges"]), _p(arr["F_star"]),
+                _p(arr["p_iface"]), _p(arr["T_iface"]), _p(arr["dtau"]), _p(arr["w0"]),
+                _p(arr["g0"]), _p(arr["mu_star"]), _p(arr["T_int"]), _p(Ft),
+                _p(out["F_up"]), _p(out["F_dn"]), _p(out["F_beam"]), _p(out["F_net"]),
+                _p(out["heating"]), _p(out["dTdt"]), _p(out["F_up_toa_bin"]),
+                _p(out.get("F_up_bin")), _p(out.get("F_dn_bin")), _p(out.get("F_beam_bin")),
+                out["flags"].ctypes.data_as(_up))
+    o = (opts or Options()).c()
+    rc = lib().orc_solve(ct.byref(P), ct.byref(o), int(n_threads))
+    out["rc"] = rc
+    return out
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()

@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs for the improved two-stream solve.
+
+This module only draws numbers: grid points, pressure and temperature
+profiles, per-layer per-bin optical depth, single-scattering albedo and
+asymmetry parameter, bin edges and a stellar spectrum.  It holds none of the
+radiative-transfer arithmetic (no coefficients, no Planck bin integrals, no
+solve) and is the one module that both the CPU oracle side and the GPU side
+of the tests and benchmark draw their inputs from.
+
+The shapes and value ranges stand in for the WASP-43b set-up of the paper
+(icosahedral grid, 40 levels, 30 k-table bins; Sections 2.1.1, 2.1.3 and
+4.2).  The real k-tables, chemistry, cloud optics and stellar template are
+not available, so every array is synthetic; the recipe is fixed by a seed
+(``numpy.random.Generator(PCG64)``, one stream per array).
+
+Layouts (all C-contiguous float64):
+  p_iface, T_iface : [N+1][C]   interface 0 = bottom of atmosphere (BOA)
+  dtau, w0, g0     : [N][C][NB] layer j lies between interfaces j and j+1
+  mu_star          : [C]        cosine of the stellar zenith angle (<=0: night)
+  T_int            : [C]        interior temperature for the bottom flux
+  lambda_edges     : [NB+1]     metres, ascending
+  F_star           : [NB]       stellar flux at TOA, W m^-2, per bin
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+import math
+
+import numpy as np
+
+BAR = 1.0e5  # Pa
+
+# SI 2019 constants used only to shape the synthetic stellar spectrum.
+_H = 6.62607015e-34
+_C = 299792458.0
+_K = 1.380649e-23
+
+
+# --------------------------------------------------------------------------
+# grid
+# --------------------------------------------------------------------------
+@functools.lru_cache(maxsize=8)
+def icosahedral_points(g_level: int) -> tuple[np.ndarray, np.ndarray]:
+    """Vertices of a recursively bisected icosahedron on the unit sphere.
+
+    Returns (lat, lon) in radians; there are 10*4**g_level + 2 points
+    (162 / 2562 / 10242 for g_level 2 / 4 / 5, the grids of Section 2.1.1).
+    """
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    verts = []
+    for a in (-1.0, 1.0):
+        for b in (-phi, phi):
+            verts += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
+    v = np.array(verts, dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    # faces: triples of mutually adjacent vertices (edge = minimal distance)
+    d = np.linalg.norm(v[:, None, :] - v[None, :, :], axis=2)
+    edge = d[d > 1e-9].min()
+    adj = np.abs(d - edge) < 1e-9
+    faces = []
+    for i in range(12):
+        for j in range(i + 1, 12):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, 12):
+                if adj[i, k] and adj[j, k]:
+                    faces.append((i, j, k))
+    assert len(faces) == 20
+    pts = [tuple(p) for p in v]
+    for _ in range(g_level):
+        cache: dict[tuple[int, int], int] = {}
+
+        def mid(i: int, j: int) -> int:
+            key = (i, j) if i < j else (j, i)
+            if key not in cache:
+                m = np.add(pts[i], pts[j])
+                m /= np.linalg.norm(m)
+                cache[key] = len(pts)
+                pts.append(tuple(m))
+            return cache[key]
+
+        new_faces = []
+        for (a, b, c) in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new_faces += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = new_faces
+    xyz = np.array(pts)
+    assert xyz.shape[0] == 10 * 4 ** g_level + 2
+    lat = np.arcsin(np.clip(xyz[:, 2], -1.0, 1.0))
+    lon = np.arctan2(xyz[:, 1], xyz[:, 0])
+    return lat, lon
+
+
+# --------------------------------------------------------------------------
+# workload description
+# --------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class Spec:
+    """Recipe of one synthetic workload (sizes and value distributions)."""
+
+    name: str
+    g_level: int = 4            # icosahedral refinement -> columns
+    n_cols: int | None = None   # explicit column count (first n points)
+    n_layers: int = 40
+    n_bins: int = 30
+    lam_min_um: float = 0.3
+    lam_max_um: float = 30.0
+    p_bot_bar: float = 100.0
+    p_top_bar: float = 1.0e-6
+    t_base: float = 700.0
+    t_day: float = 1100.0
+    t_noise: float = 20.0
+    dtau_lo: float = 1.0e-6
+    dtau_hi: float = 1.0e2
+    w0_lo: float = 0.0
+    w0_hi: float = 0.3
+    cloud: str = "none"         # "none" | "night" | "fraction"
+    cloud_fraction: float = 0.0
+    cloud_p_lo_bar: float = 1.0e-3
+    cloud_p_hi_bar: float = 1.0e-1
+    cloud_w0_lo: float = 0.9
+    cloud_w0_hi: float = 0.999
+    cloud_g0_lo: float = 0.5
+    cloud_g0_hi: float = 0.95
+    t_star: float = 4400.0
+    f_bol: float = 9.0e5
+    t_int: float = 100.0
+    seed: int = 1000
+
+
+#: The paper-shaped workloads.  cfg1 is the GCM size of Section 4.2
+#: (2562 columns x 40 levels x 30 bins); cfg2 reuses cfg1's inputs.
+SPECS: dict[str, Spec] = {
+    "cfg0": Spec(name="cfg0", g_level=2, seed=1000),
+    "cfg1": Spec(name="cfg1", g_level=4, cloud="night", seed=1001),
+    "cfg4": Spec(name="cfg4", g_level=5, n_layers=80, n_bins=300, dtau_lo=1e-8,
+                 dtau_hi=1e3, cloud="night", cloud_w0_hi=0.9999,
+                 cloud_g0_hi=0.98, seed=1004),
+}
+SPECS["cfg2"] = dataclasses.replace(SPECS["cfg1"], name="cfg2")
+
+
+def stellar_spectrum(lam_edges: np.ndarray, t_star: float, f_bol: float) -> np.ndarray:
+    """Synthetic per-bin stellar flux at TOA (W m^-2), stand-in for the stellar template.
+
+    Each bin holds the blackbody share of ``f_bol`` estimated by the spectral
+    density at the bin's geometric centre times its width.  This is input data
+    only; the solver takes the per-bin vector as given.
+    """
+    lo, hi = lam_edges[:-1], lam_edges[1:]
+    lam = np.sqrt(lo * hi)
+    x = _H * _C / (lam * _K * t_star)
+    spec_density = 2.0 * _H * _C ** 2 / lam ** 5 / np.expm1(x)   # W m^-3 sr^-1
+    sigma = 2.0 * math.pi ** 5 * _K ** 4 / (15.0 * _H ** 3 * _C ** 2)
+    return f_bol * math.pi * spec_density * (hi - lo) / (sigma * t_star ** 4)
+
+
+def _streams(seed: int, n: int) -> list[np.random.Generator]:
+    return [np.random.Generator(np.random.PCG64(s))
+            for s in np.random.SeedSequence(seed).spawn(n)]
+
+
+def columns_from_points(lat: np.ndarray, lon: np.ndarray) -> np.ndarray:
+    """Cosine of the stellar zenith angle, substellar point at (0, 0)."""
+    return np.cos(lat) * np.cos(lon)
+
+
+def make(spec: Spec | str, n_cols: int | None = None, mu_star: np.ndarray | None = None,
+         seed: int | None = None) -> dict:
+    """Draw one workload.  Returns a dict of numpy arrays plus ``spec``/sizes."""
+    if isinstance(spec, str):
+        spec = SPECS[spec]
+    lat, lon = icosahedral_points(spec.g_level)
+    mu_all = columns_from_points(lat, lon)
+    C = n_cols if n_cols is not None else (spec.n_cols or mu_all.size)
+    if mu_star is None:
+        if C <= mu_all.size:
+            mu = mu_all[:C].copy()
+        else:
+            mu = np.resize(mu_all, C)
+    else:
+        mu = np.asarray(mu_star, dtype=np.float64).copy()
+        C = mu.size
+    N, NB = spec.n_layers, spec.n_bins
+    rs = _streams(spec.seed if seed is None else seed, 8)
+
+    p1 = np.logspace(math.log10(spec.p_bot_bar * BAR), math.log10(spec.p_top_bar * BAR), N + 1)
+    p_iface = np.repeat(p1[:, None], C, axis=1)
+    T_iface = (spec.t_base + spec.t_day * np.maximum(mu, 0.0)[None, :] ** 0.25
+               + spec.t_noise * rs[0].standard_normal((N + 1, C)))
+
+    dp = p1[:-1] - p1[1:]
+    scale = dp / dp.max()
+    logu = rs[1].uniform(math.log(spec.dtau_lo), math.log(spec.dtau_hi), size=(N, C, NB))
+    dtau = np.exp(logu) * scale[:, None, None]
+    w0 = rs[2].uniform(spec.w0_lo, spec.w0_hi, size=(N, C, NB))
+    g0 = np.zeros((N, C, NB))
+
+    if spec.cloud != "none":
+        if spec.cloud == "night":
+            cloudy_col = mu <= 0.0
+        else:
+            cloudy_col = rs[3].uniform(size=C) < spec.cloud_fraction
+        pm = np.sqrt(p1[:-1] * p1[1:])
+        cloud_layer = (pm >= spec.cloud_p_lo_bar * BAR) & (pm <= spec.cloud_p_hi_bar * BAR)
+        mask = cloud_layer[:, None] & cloudy_col[None, :]
+        cw = rs[4].uniform(spec.cloud_w0_lo, spec.cloud_w0_hi, size=(N, C, NB))
+        cg = rs[5].uniform(spec.cloud_g0_lo, spec.cloud_g0_hi, size=(N, C, NB))
+        w0 = np.where(mask[:, :, None], cw, w0)
+        g0 = np.where(mask[:, :, None], cg, g0)
+
+    lam = np.logspace(math.log10(spec.lam_min_um), math.log10(spec.lam_max_um), NB + 1) * 1e-6
+    return dict(
+        spec=spec, n_cols=C, n_layers=N, n_bins=NB,
+        p_iface=np.ascontiguousarray(p_iface), T_iface=np.ascontiguousarray(T_iface),
+        dtau=np.ascontiguousarray(dtau), w0=np.ascontiguousarray(w0),
+        g0=np.ascontiguousarray(g0), mu_star=mu,
+        T_int=np.full(C, spec.t_int), lambda_edges=lam,
+        F_star=stellar_spectrum(lam, spec.t_star, spec.f_bol),
+    )
+
+
+# --------------------------------------------------------------------------
+# serving mix (uneven requests, Poisson arrivals)
+# --------------------------------------------------------------------------
+def serving_requests(n_requests: int, seed: int = 1003, max_cols: int = 4096,
+                     layers=(20, 120), bins=(30, 100, 300)) -> list[dict]:
+    """Request shapes for the serving mix: columns U{1..max_cols}, layers
+    U{layers}, bins drawn from ``bins``, cloud fraction U[0, 0.5]; the values
+    follow the cfg1 generators."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n_requests):
+        out.append(dict(
+            n_cols=int(r.integers(1, max_cols + 1)),
+            n_layers=int(r.integers(layers[0], layers[1] + 1)),
+            n_bins=int(r.choice(bins)),
+            cloud_fraction=float(r.uniform(0.0, 0.5)),
+            seed=int(seed * 1000 + k),
+        ))
+    return out
+
+
+def make_request(shape: dict, precision: str = "fp64") -> dict:
+    """Draw the arrays of one serving request described by ``shape``."""
+    spec = dataclasses.replace(
+        SPECS["cfg1"], name="serve", n_layers=shape["n_layers"], n_bins=shape["n_bins"],
+        cloud="fraction", cloud_fraction=shape["cloud_fraction"], seed=shape["seed"])
+    lat, lon = icosahedral_points(5)
+    r = np.random.Generator(np.random.PCG64(shape["seed"]))
+    idx = r.choice(lat.size, size=shape["n_cols"], replace=False)
+    mu = columns_from_points(lat[idx], lon[idx])
+    w = make(spec, mu_star=mu)
+    w["precision"] = precision
+    return w
+
+
+def poisson_arrivals(n: int, rate_hz: float, seed: int = 77) -> np.ndarray:
+    """Arrival times (s) of a Poisson process at ``rate_hz``."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(r.exponential(1.0 / rate_hz, size=n))

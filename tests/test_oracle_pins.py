@@ -1,0 +1,384 @@
+"""Pins of the oracle's coefficients, layer relations, assembly and solver.
+
+Each test ties the oracle to something other than itself: a closed form, a
+textbook special case, an invariant of the exact solution, an independent
+numerical solution of the underlying ODE, a library solve, or the paper's
+own limiting statements.  Paper: Deitrick et al. (arXiv 2203.02293),
+Section 2.2 and Appendix B.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad, solve_ivp
+
+import oracle as O
+
+PI = math.pi
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------- E and coefficients
+def test_efit_threshold_and_modes():
+    """Section 2.2.4: E = 1 for w0 <= 0.1 (tie included) and in regular mode."""
+    assert O.efit(0.1, 0.7)[0] == 1.0
+    assert O.efit(0.05, 0.2)[0] == 1.0
+    assert O.efit(0.5, 0.5, O.Options(improved=0))[0] == 1.0
+    assert O.efit(np.nextafter(0.1, 1.0), 0.0)[0] > 1.2
+
+
+@pytest.mark.parametrize("w0,g0,expect", [
+    # hand-evaluated from the printed coefficients in exact decimal arithmetic
+    (0.5, 0.5, 1.0832075),
+    (0.9, 0.0, 1.0198558),
+    (0.3, 0.0, 1.225 - 0.05331 - 0.005023800),
+])
+def test_efit_hand_values(w0, g0, expect):
+    assert O.efit(w0, g0)[0] == pytest.approx(expect, rel=1e-14)
+
+
+def test_efit_clamp_and_strict():
+    """Cloud-like (0.999, 0.95): the fit gives 0.9972293... < w0.  Clamp raises
+    it to 1 (flag); strict mode keeps it and flags the domain error."""
+    E, fl = O.efit(0.999, 0.95)
+    assert E == 1.0 and fl == O.F_ECLAMP
+    E, fl = O.efit(0.999, 0.95, O.Options(e_clamp=0))
+    assert E == pytest.approx(0.99722931418, rel=1e-10) and fl == O.F_EDOMAIN
+
+
+@pytest.mark.parametrize("dtau", [1e-3, 0.3, 2.0, 40.0])
+def test_pure_absorber_coefficients(dtau):
+    """w0 = 0: zeta+ = 1, zeta- = 0, T = exp(-2 dtau), chi = -1, xi = 0,
+    psi = -T, Pi = pi and no beam coupling (Section 2.2.4 limit)."""
+    L = O.layer_coeffs(dtau, 0.0, 0.0, 0.6)
+    assert (L["E"], L["zp"], L["zm"]) == (1.0, 1.0, 0.0)
+    assert L["Tr"] == pytest.approx(math.exp(-2 * dtau), rel=1e-15)
+    assert L["chi"] == pytest.approx(-1.0, rel=1e-15) and L["xi"] == 0.0
+    assert L["psi"] == pytest.approx(-math.exp(-2 * dtau), rel=1e-15)
+    assert L["Pi"] == pytest.approx(PI, rel=1e-15)
+    assert L["Gp"] == 0.0 and L["Gm"] == 0.0
+
+
+def test_opaque_absorbing_layer_emits_piB():
+    """Section 2.2.4: an opaque, purely absorbing, isothermal layer emits pi*B."""
+    B = 3.7
+    fu, fd, fb, _ = O.column_bin([B, B], [60.0], [0.0], [0.3], 0.0, 0.0)
+    assert fu[1] == pytest.approx(PI * B, rel=1e-13)
+    assert fd[0] == pytest.approx(PI * B, rel=1e-13)
+
+
+def test_guard_replaces_denominator():
+    """Resonance guard: |D| < 1e-5 -> D = 2*mu_star with mu_star = -mu."""
+    w0, g0 = 0.0, 0.0      # E = 1, lambda = 2, so D = 4 mu^2 - 1
+    L = O.layer_coeffs(1.0, w0, g0, 0.5 + 1e-7)
+    assert L["flags"] & O.F_GUARD and L["D"] == pytest.approx(-2 * (0.5 + 1e-7))
+    L = O.layer_coeffs(1.0, w0, g0, 0.5 + 1e-5)
+    assert not (L["flags"] & O.F_GUARD)
+    assert L["D"] == pytest.approx(4 * (0.5 + 1e-5) ** 2 - 1, rel=1e-9)
+
+
+# ---------------------------------------------------------------- pure absorption
+def formal_solution(B, dtau, mu, Fstar, F_boa, F_toa):
+    """Pure absorption, hemispheric two-stream (dF/dtau = +-2(F - pi B)),
+    B linear in tau inside each layer, reflective BOA with the beam and F_BOA.
+    Integrals by adaptive quadrature, independent of the oracle's formulas."""
+    N = len(dtau)
+    tau = np.zeros(N + 1)
+    for j in range(N - 1, -1, -1):
+        tau[j] = tau[j + 1] + dtau[j]
+    Bt = lambda j, t: B[j + 1] + (B[j] - B[j + 1]) * (t - tau[j + 1]) / dtau[j]
+    fd = np.zeros(N + 1)
+    fd[N] = F_toa
+    for j in range(N - 1, -1, -1):
+        a, b = tau[j + 1], tau[j]
+        I = quad(lambda t: 2 * PI * Bt(j, t) * math.exp(-2 * (b - t)), a, b,
+                 epsabs=0, epsrel=1e-13, limit=200)[0]
+        fd[j] = fd[j + 1] * math.exp(-2 * (b - a)) + I
+    fb = mu * Fstar * np.exp(-tau / mu) if mu > 0 else np.zeros(N + 1)
+    fu = np.zeros(N + 1)
+    fu[0] = fd[0] + fb[0] + F_boa
+    for j in range(N):
+        a, b = tau[j + 1], tau[j]
+        I = quad(lambda t: 2 * PI * Bt(j, t) * math.exp(-2 * (t - a)), a, b,
+                 epsabs=0, epsrel=1e-13, limit=200)[0]
+        fu[j + 1] = fu[j] * math.exp(-2 * (b - a)) + I
+    return fu, fd, fb
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_pure_absorption_matches_formal_solution(seed):
+    r = rng(seed)
+    N = 7
+    dtau = np.exp(r.uniform(np.log(2e-4), np.log(3.0), N))
+    B = r.uniform(1.0, 50.0, N + 1)
+    mu, Fstar, F_boa, F_toa = 0.63, 400.0, 2.5, 1.5
+    fu, fd, fb, fl = O.column_bin(B, dtau, np.zeros(N), np.zeros(N), mu, Fstar, F_boa, F_toa,
+                                  O.Options(e_tau=1e-30))
+    ru, rd, rb = formal_solution(B, dtau, mu, Fstar, F_boa, F_toa)
+    S = np.max(ru + rd + rb)
+    np.testing.assert_allclose(fb, rb, rtol=1e-14)
+    assert np.max(np.abs(fu - ru)) < 1e-12 * S
+    assert np.max(np.abs(fd - rd)) < 1e-12 * S
+
+
+# ---------------------------------------------------------------- ODE consistency
+def ode_rhs(E, w0, g0, mu, eps2, Bfun, Fb_top):
+    """Two-stream ODE implied by the coefficients (tau downward from the layer top):
+    g1 = 2E - w0 - E w0 g0, g2 = w0 (1 - E g0); thermal source 2 pi (1-w0) B;
+    beam sources w0 (1 -+ g0 mu/eps2)/2 * F* exp(-tau/mu).  With E = 1 this is
+    the hemispheric-mean two-stream of Toon et al. (1989) with the Eddington
+    type beam closure gamma3 = (1 - g0 mu / eps2)/2."""
+    g1 = 2 * E - w0 - E * w0 * g0
+    g2 = w0 * (1 - E * g0)
+    g3 = 0.5 * (1 - g0 * mu / eps2)
+    g4 = 1 - g3
+
+    def f(t, y):
+        th = 2 * PI * (1 - w0) * Bfun(t)
+        s = Fb_top * math.exp(-t / mu) / mu if mu > 0 else 0.0
+        return [g1 * y[0] - g2 * y[1] - th - w0 * g3 * s,
+                g2 * y[0] - g1 * y[1] + th + w0 * g4 * s]
+    return f
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_layer_relations_solve_the_ode(seed):
+    """Any ODE solution across one slab satisfies the paper's upward and
+    downward relations (Section 2.2.1 / Appendix B), including the
+    non-isothermal gradient term and both G+- beam terms."""
+    r = rng(100 + seed)
+    improved = seed % 2
+    w0 = r.uniform(0.0, 0.98) if seed != 0 else 0.0
+    g0 = r.uniform(0.0, 0.9) if seed > 1 else 0.0
+    dtau = r.uniform(0.05, 2.5)
+    mu = r.uniform(0.2, 0.95)
+    Blo, Bup = r.uniform(1, 30), r.uniform(1, 30)
+    Fstar = r.uniform(100, 1000)
+    opts = O.Options(improved=improved, e_tau=1e-30)
+    L = O.layer_coeffs(dtau, w0, g0, mu, opts)
+    assert not (L["flags"] & O.F_GUARD)
+    # one-layer column, its top is the TOA so F_beam_top = mu * F*
+    A, Bm, Cm, D, Fb, _ = O.assemble([Blo, Bup], [dtau], [w0], [g0], mu, Fstar, 0.0, 0.0, opts)
+    Bfun = lambda t: Bup + (Blo - Bup) * t / dtau
+    f = ode_rhs(L["E"], w0, g0, mu, opts.eps2, Bfun, mu * Fstar)
+    y0 = [r.uniform(0, 50), r.uniform(0, 50)]            # F_up, F_dn at the top
+    sol = solve_ivp(f, (0.0, dtau), y0, method="DOP853", rtol=1e-13, atol=1e-12)
+    up_top, dn_top = y0
+    up_bot, dn_bot = sol.y[:, -1]
+    X0, X1 = np.array([up_bot, dn_bot]), np.array([up_top, dn_top])
+    # upward relation: row 0 of block row 1; downward relation: row 1 of block row 0
+    res_up = A[1, 0] @ X0 + Bm[1, 0] @ X1 - D[1, 0]
+    res_dn = Bm[0, 1] @ X0 + Cm[0, 1] @ X1 - D[0, 1]
+    scale = np.max(np.abs(np.concatenate([A[1, 0] * X0, Bm[1, 0] * X1, Bm[0, 1] * X0,
+                                          Cm[0, 1] * X1, D[:, :].ravel()])))
+    assert abs(res_up) < 1e-10 * scale
+    assert abs(res_dn) < 1e-10 * scale
+
+
+# ---------------------------------------------------------------- solver pins
+def random_column(seed, N=6, cloudy=True):
+    r = rng(seed)
+    dtau = np.exp(r.uniform(np.log(1e-3), np.log(5.0), N))
+    w0 = r.uniform(0.0, 0.99 if cloudy else 0.3, N)
+    g0 = r.uniform(0.0, 0.9, N) if cloudy else np.zeros(N)
+    B = r.uniform(1.0, 40.0, N + 1)
+    return B, dtau, w0, g0
+
+
+def full_matrix(A, Bm, Cm, D):
+    N = A.shape[0] - 1
+    M = np.zeros((2 * N + 2, 2 * N + 2))
+    for i in range(N + 1):
+        M[2 * i:2 * i + 2, 2 * i:2 * i + 2] = Bm[i]
+        if i > 0:
+            M[2 * i:2 * i + 2, 2 * i - 2:2 * i] = A[i]
+        if i < N:
+            M[2 * i:2 * i + 2, 2 * i + 2:2 * i + 4] = Cm[i]
+    return M, D.ravel()
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("improved", [0, 1])
+def test_block_thomas_matches_dense_solve(seed, improved):
+    """Thomas (Section 2.2.2) vs LAPACK gesv with partial pivoting."""
+    B, dtau, w0, g0 = random_column(seed, N=9)
+    opts = O.Options(improved=improved)
+    A, Bm, Cm, D, Fb, _ = O.assemble(B, dtau, w0, g0, 0.7, 500.0, 3.0, 0.5, opts)
+    X = O.block_thomas(A, Bm, Cm, D)
+    M, rhs = full_matrix(A, Bm, Cm, D)
+    ref = np.linalg.solve(M, rhs).reshape(-1, 2)
+    S = np.max(np.abs(ref[:, 0]) + np.abs(ref[:, 1]) + Fb)
+    assert np.max(np.abs(X - ref)) < 1e-12 * S
+
+
+def iterate_pairwise(A, Bm, Cm, D, tol=1e-15, max_iter=200000):
+    """The iterative multiple-scattering scheme of Section 2.2.2: alternate an
+    upward sweep of the upward relations (starting from the BOA condition) and
+    a downward sweep of the downward relations (starting from F_TOA)."""
+    N = A.shape[0] - 1
+    up, dn = np.zeros(N + 1), np.zeros(N + 1)
+    for it in range(max_iter):
+        old = np.concatenate([up, dn])
+        up[0] = D[0, 0] + dn[0]
+        for i in range(1, N + 1):   # chi up_i + xi dn_i - psi up_{i-1} = src
+            up[i] = (D[i, 0] - A[i, 0, 0] * up[i - 1] - Bm[i, 0, 1] * dn[i]) / Bm[i, 0, 0]
+        dn[N] = D[N, 1]
+        for i in range(N - 1, -1, -1):
+            dn[i] = (D[i, 1] - Bm[i, 1, 0] * up[i] - Cm[i, 1, 1] * dn[i + 1]) / Bm[i, 1, 1]
+        new = np.concatenate([up, dn])
+        if np.max(np.abs(new - old)) <= tol * np.max(np.abs(new)):
+            return up, dn, it
+    raise RuntimeError("no convergence")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_iterative_scheme_converges_to_thomas(seed):
+    B, dtau, w0, g0 = random_column(seed, N=8)
+    A, Bm, Cm, D, Fb, _ = O.assemble(B, dtau, w0 * 0.9, g0, 0.5, 300.0, 1.0, 0.0)
+    X = O.block_thomas(A, Bm, Cm, D)
+    up, dn, it = iterate_pairwise(A, Bm, Cm, D)
+    S = np.max(np.abs(X).sum(1) + Fb)
+    assert np.max(np.abs(up - X[:, 0])) < 1e-12 * S
+    assert np.max(np.abs(dn - X[:, 1])) < 1e-12 * S
+
+
+@pytest.mark.parametrize("w0", [0.0, 0.05, 0.5, 0.95])
+def test_isothermal_enclosure(w0):
+    """E = 1 (regular mode), uniform T, no beam, F_TOA = pi B, F_BOA = 0:
+    F_up = F_dn = pi B everywhere and the net flux vanishes."""
+    N, Bv = 8, 12.5
+    r = rng(5)
+    dtau = np.exp(r.uniform(np.log(1e-3), np.log(10), N))
+    opts = O.Options(improved=0)
+    fu, fd, fb, _ = O.column_bin(np.full(N + 1, Bv), dtau, np.full(N, w0), r.uniform(0, .9, N),
+                                 -1.0, 0.0, 0.0, PI * Bv, opts)
+    np.testing.assert_allclose(fu, PI * Bv, rtol=1e-13)
+    np.testing.assert_allclose(fd, PI * Bv, rtol=1e-13)
+
+
+@pytest.mark.parametrize("mu", [0.3, 0.8])
+def test_conservative_scattering_keeps_net_flux_zero(mu):
+    """Regular mode, w0 -> 1, no thermal sources, reflective BOA: every
+    interface carries zero net flux (F_up - F_dn - F_beam) to O((1-w0) tau)."""
+    N = 8
+    r = rng(9)
+    dtau = np.exp(r.uniform(np.log(1e-2), np.log(3), N))
+    delta = 1e-9
+    opts = O.Options(improved=0)
+    fu, fd, fb, _ = O.column_bin(np.zeros(N + 1), dtau, np.full(N, 1 - delta),
+                                 r.uniform(0, 0.8, N), mu, 1000.0, 0.0, 0.0, opts)
+    net = fu - fd - fb
+    assert np.max(np.abs(net)) < 50 * delta * dtau.sum() * 1000.0 * mu
+
+
+def test_superposition():
+    """The system is linear: thermal + beam + F_BOA + F_TOA parts add up."""
+    B, dtau, w0, g0 = random_column(11, N=10)
+    args = dict(B=B, dtau=dtau, w0=w0, g0=g0, mu=0.55)
+    full = O.column_bin(Fstar=700.0, F_boa=4.0, F_toa=2.0, **args)
+    z = np.zeros_like(B)
+    parts = [O.column_bin(Fstar=0.0, F_boa=0.0, F_toa=0.0, **args),
+             O.column_bin(**{**args, "B": z}, Fstar=700.0, F_boa=0.0, F_toa=0.0),
+             O.column_bin(**{**args, "B": z}, Fstar=0.0, F_boa=4.0, F_toa=0.0),
+             O.column_bin(**{**args, "B": z}, Fstar=0.0, F_boa=0.0, F_toa=2.0)]
+    for k in range(3):
+        s = sum(p[k] for p in parts)
+        assert np.max(np.abs(s - full[k])) < 1e-12 * np.max(np.abs(full[0]) + np.abs(full[1]))
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+@pytest.mark.parametrize("k", [2, 3])
+def test_layer_splitting_invariance(improved, k):
+    """Splitting each slab into k equal sub-slabs with B interpolated linearly
+    in tau leaves the fluxes at the original interfaces unchanged (exact for the
+    linear-in-tau source).  Pins the gradient term and the G+- beam terms."""
+    B, dtau, w0, g0 = random_column(21 + k, N=5)
+    mu = 0.77
+    opts = O.Options(improved=improved, e_tau=1e-30)
+    fu, fd, fb, fl = O.column_bin(B, dtau, w0, g0, mu, 800.0, 3.0, 1.0, opts)
+    assert not (fl & O.F_GUARD)
+    Bs, ds, ws, gs = [B[0]], [], [], []
+    for j in range(len(dtau)):
+        for m in range(1, k + 1):
+            Bs.append(B[j] + (B[j + 1] - B[j]) * m / k)
+            ds.append(dtau[j] / k)
+            ws.append(w0[j])
+            gs.append(g0[j])
+    su, sd, sb, fl2 = O.column_bin(Bs, ds, ws, gs, mu, 800.0, 3.0, 1.0, opts)
+    assert not (fl2 & O.F_GUARD)
+    S = np.max(fu + fd + fb)
+    assert np.max(np.abs(su[::k] - fu)) < 1e-11 * S
+    assert np.max(np.abs(sd[::k] - fd)) < 1e-11 * S
+    assert np.max(np.abs(sb[::k] - fb)) < 1e-12 * S
+
+
+def test_noniso_tends_to_isothermal():
+    """As the temperature gradient vanishes the non-isothermal fluxes converge
+    continuously (linearly in the Planck difference) to the isothermal ones."""
+    _, dtau, w0, g0 = random_column(31, N=6)
+    dtau = np.maximum(dtau, 1e-2)
+    base = 10.0 + np.zeros(7)
+    ramp = np.linspace(0.0, 1.0, 7)
+    iso = O.column_bin(base, dtau, w0, g0, 0.4, 100.0, 1.0, 0.0, O.Options(noniso=0))
+    errs = []
+    for d in (1e-2, 1e-4, 1e-6):
+        non = O.column_bin(base + d * ramp, dtau, w0, g0, 0.4, 100.0, 1.0, 0.0)
+        errs.append(np.max(np.abs(non[0] - iso[0])))
+    assert errs[1] < 2e-2 * errs[0] and errs[2] < 2e-2 * errs[1]
+
+
+def test_etau_fallback_jump_is_second_order():
+    """Crossing e_tau switches the gradient term off; the jump in the emitted
+    flux of a thin slab is O(pi dB dtau^2) (Section 2.2.1 rule)."""
+    e = 1e-4
+    Bl, Bu = 20.0, 10.0
+    below = O.column_bin([Bl, Bu], [np.nextafter(e, 0)], [0.2], [0.0], 0.0, 0.0)
+    above = O.column_bin([Bl, Bu], [e], [0.2], [0.0], 0.0, 0.0)
+    assert below[3] & O.F_ETAU and not (above[3] & O.F_ETAU)
+    jump = abs(below[0][1] - above[0][1])
+    assert jump < 10 * PI * (Bl - Bu) * e * e
+
+
+# ---------------------------------------------------------------- whole problem
+def small_workload(seed=3, C=4, N=6, NB=5):
+    from paper_2203_02293_amd import synth
+    w = synth.make(synth.Spec(name="t", g_level=1, n_layers=N, n_bins=NB, cloud="night",
+                              seed=seed), n_cols=C)
+    return w
+
+
+def test_solve_matches_per_bin_and_heating_telescopes():
+    w = small_workload()
+    out = O.solve(w, per_bin=True)
+    assert out["rc"] == 0
+    C, N, NB = w["n_cols"], w["n_layers"], w["n_bins"]
+    np.testing.assert_allclose(out["F_up"], out["F_up_bin"].sum(2), rtol=1e-14)
+    np.testing.assert_allclose(out["F_net"], out["F_up"] - out["F_dn"] - out["F_beam"],
+                               rtol=1e-14, atol=1e-14 * np.abs(out["F_up"]).max())
+    np.testing.assert_array_equal(out["F_up_toa_bin"], out["F_up_bin"][N])
+    p = w["p_iface"]
+    tel = (out["heating"] * (p[:-1] - p[1:]) / 47.0).sum(0)
+    np.testing.assert_allclose(tel, out["F_net"][0] - out["F_net"][N], rtol=1e-10,
+                               atol=1e-12 * np.abs(out["F_up"]).max())
+    # one (column, bin) reproduced through the per-bin entry point
+    c, b = 1, 2
+    Bv = [O.planck_bin(w["T_iface"][i, c], w["lambda_edges"][b], w["lambda_edges"][b + 1])
+          for i in range(N + 1)]
+    Fboa = PI * O.planck_bin(w["T_int"][c], w["lambda_edges"][b], w["lambda_edges"][b + 1])
+    fu, fd, fb, _ = O.column_bin(Bv, w["dtau"][:, c, b], w["w0"][:, c, b], w["g0"][:, c, b],
+                                 w["mu_star"][c], w["F_star"][b], Fboa, 0.0)
+    np.testing.assert_array_equal(fu, out["F_up_bin"][:, c, b])
+
+
+def test_invalid_inputs_flagged():
+    w = small_workload()
+    w["w0"] = w["w0"].copy()
+    w["w0"][2, 1, 0] = 1.5
+    w["T_iface"] = w["T_iface"].copy()
+    w["T_iface"][3, 2] = -5.0
+    out = O.solve(w)
+    assert out["flags"][1] & O.F_INVALID and out["flags"][2] & O.F_INVALID
+    assert not out["flags"][0] & O.F_INVALID
