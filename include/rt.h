@@ -1,0 +1,165 @@
+/*
+ * rt.h -- C-ABI of the MI355X improved two-stream radiative-transfer library.
+ *
+ * The library computes, for every atmospheric column and every k-table bin,
+ * the improved two-stream fluxes of Deitrick et al., "The THOR+HELIOS general
+ * circulation model" (arXiv 2203.02293): layer coefficients (Appendix B),
+ * linear-in-tau Planck sources and the attenuated stellar beam (Section 2.2.1),
+ * a Thomas-algorithm solve of the interface fluxes (Section 2.2.2), and the
+ * bin sums into net fluxes and heating rates (Section 2.2.5: fluxes are
+ * integrated over wavelength to obtain heating and cooling rates).
+ *
+ * Grid conventions (Section 2.2.1): interface i = 0 is the bottom of the
+ * atmosphere (BOA) and i = N the top (TOA); layer j lies between interfaces j
+ * (lower) and j+1 (upper).  Optical depth grows downward from the TOA.
+ *
+ * Memory: every array in rt_request is a DEVICE pointer owned by the caller,
+ * 8-byte aligned, C-contiguous, in the layouts stated below.  The library owns
+ * only its resident tables (bin edges, stellar flux, series coefficients) and
+ * its own work buffers.  No function throws or aborts; all report an rt_status.
+ * A handle is not thread-safe: use one handle per host thread or lock around it.
+ */
+#ifndef RT_MI355X_H
+#define RT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+#define RT_OK          0   /* success (rt_poll: request finished)                */
+#define RT_PENDING     1   /* rt_poll: request still queued or running           */
+#define RT_EINVAL    (-1)  /* bad argument, shape or layout; nothing was launched */
+#define RT_ENOMEM    (-2)  /* device allocation failed or request exceeds budget  */
+#define RT_EDEVICE   (-3)  /* HIP runtime error (launch, copy, event)             */
+#define RT_EDOMAIN   (-4)  /* strict E mode met E <= w0 (see flags)               */
+#define RT_EBUSY     (-5)  /* serving queue full (max_inflight reached)           */
+#define RT_ENOTFOUND (-6)  /* rt_poll/rt_wait on an unknown or retired ticket     */
+
+/* precision of a solve */
+#define RT_FP64  0   /* every step in FP64                                         */
+#define RT_MIXED 1   /* FP32 coefficients, exponentials and Planck integrals; FP64
+                        predicates, optical-depth sums and Thomas elimination     */
+
+/* per-column condition bits written to rt_request.flags */
+#define RT_FLAG_GUARD    1u  /* G+- resonance guard (Section 2.2.1) replaced D by 2 mu_star */
+#define RT_FLAG_ECLAMP   2u  /* E fit below 1 raised to 1 (e_clamp mode)                */
+#define RT_FLAG_ETAU     4u  /* dtau < e_tau: layer treated as isothermal (Section 2.2.1) */
+#define RT_FLAG_EDOMAIN  8u  /* strict mode: E <= w0, coefficients undefined            */
+#define RT_FLAG_INVALID 16u  /* an input value is outside its documented domain         */
+#define RT_FLAG_NONFIN  32u  /* a non-finite bin-summed output was produced             */
+
+typedef struct rt_handle rt_handle;
+
+/*
+ * Static configuration, copied by rt_create (the host arrays may be freed
+ * afterwards).  Defaults (rt_config_default) follow Table 3 of the paper.
+ */
+typedef struct {
+    int32_t n_bins;               /* number of k-table bins NB, 1 <= NB <= 512       */
+    int32_t improved;             /* 1: E from the fit of Section 2.2.4; 0: E = 1    */
+    int32_t noniso;               /* 1: Planck linear in tau within a layer
+                                     (non-isothermal layers); 0: isothermal layers,
+                                     B = mean of the two interface values           */
+    int32_t e_clamp;              /* 1: E = max(E_fit, 1) where the fit applies
+                                     (no layer emits more than pi B); 0: strict,
+                                     E <= w0 sets RT_FLAG_EDOMAIN                    */
+    const double *lambda_edges;   /* HOST [NB+1] bin edges in metres, ascending      */
+    const double *stellar_flux;   /* HOST [NB] stellar flux at TOA per bin, W m^-2,
+                                     at normal incidence                             */
+    double eps2;                  /* second Eddington coefficient of the beam (2/3)  */
+    double e_tau;                 /* isothermal fallback threshold on dtau (1e-4)    */
+    double g_guard;               /* |D| threshold of the G+- resonance guard (1e-5) */
+    double gravity;               /* m s^-2 for the heating rate (47)                */
+    double cp;                    /* J kg^-1 K^-1 for dT/dt (12436)                  */
+    int64_t hbm_budget_bytes;     /* serving: cap on library-owned device memory used
+                                     by in-flight requests (0: 8 GiB)                */
+    int32_t max_inflight;         /* serving: max queued + running requests (0: 64)  */
+    int32_t device;               /* HIP device ordinal                              */
+} rt_config;
+
+/* Fill *cfg with the defaults (NB = 0 and NULL tables: the caller sets them). */
+void rt_config_default(rt_config *cfg);
+
+/*
+ * Create a handle on cfg->device: validates cfg (RT_EINVAL), copies the bin
+ * tables to the device and builds the resident series tables (RT_ENOMEM,
+ * RT_EDEVICE).  *out is set only on RT_OK.
+ */
+rt_status rt_create(const rt_config *cfg, rt_handle **out);
+
+/* Wait for the handle's own work, release everything it owns.  NULL is a no-op. */
+rt_status rt_destroy(rt_handle *h);
+
+/*
+ * One solve.  Shapes: C = n_cols >= 1, N = n_layers in [1, 4096], NB from the
+ * handle.  Inputs (device, read only):
+ *   p_iface, T_iface  [N+1][C]   Pa, K; p strictly decreasing with i, T > 0
+ *   dtau, w0, g0      [N][C][NB] layer optical depth (>= 0), single-scattering
+ *                                albedo in [0,1], asymmetry in (-1,1)
+ *   mu_star           [C]        cosine of the stellar zenith angle; <= 0: no beam
+ *   T_int             [C]        interior temperature, F_BOA = pi B_b(T_int) (K, >= 0)
+ *   F_toa             [C][NB]    diffuse downward flux at TOA (W m^-2) or NULL = 0
+ * Outputs (device, written):
+ *   F_up, F_dn, F_beam, F_net [N+1][C]  bin sums, W m^-2; F_net = F_up - F_dn - F_beam
+ *   heating           [N][C]     W kg^-1, g (F_net_j - F_net_{j+1}) / (p_j - p_{j+1})
+ *   dTdt              [N][C]     K s^-1 = heating / cp, or NULL
+ *   F_up_toa_bin      [C][NB]    upward flux at TOA per bin (spectrum), or NULL
+ *   F_up_bin, F_dn_bin [N+1][C][NB] per-bin fluxes, or NULL
+ *   flags             [C]        RT_FLAG_* bits per column, or NULL
+ * Values outside their domain do not stop the solve: the column's outputs are
+ * then unspecified and its flags carry RT_FLAG_INVALID.
+ */
+typedef struct {
+    int32_t n_cols, n_layers;
+    int32_t precision;            /* RT_FP64 or RT_MIXED */
+    int32_t reserved_;            /* must be 0 */
+    const double *p_iface, *T_iface;
+    const double *dtau, *w0, *g0;
+    const double *mu_star, *T_int;
+    const double *F_toa;
+    double *F_up, *F_dn, *F_beam, *F_net;
+    double *heating, *dTdt;
+    double *F_up_toa_bin;
+    double *F_up_bin, *F_dn_bin;
+    uint32_t *flags;
+} rt_request;
+
+/*
+ * Stream-ordered solve on hip_stream (a hipStream_t; NULL = the null stream).
+ * Argument and shape errors return RT_EINVAL before any launch; a failed
+ * launch returns RT_EDEVICE.  The buffers must stay valid until the stream's
+ * work completes.  Solves on one handle share its work buffers: issue them on
+ * one stream, or synchronise between streams.
+ */
+rt_status rt_solve_fluxes(rt_handle *h, const rt_request *req, void *hip_stream);
+
+/*
+ * Serving path: enqueue a request and return at once with *ticket.  The
+ * library admits queued requests onto the device when slots and its memory
+ * budget allow, runs admitted requests concurrently, and retires them in any
+ * order.  The request's buffers must stay valid, and must not be touched,
+ * until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:
+ * RT_EINVAL (bad request), RT_EBUSY (max_inflight reached), RT_ENOMEM (the
+ * request alone exceeds the memory budget).
+ */
+rt_status rt_submit(rt_handle *h, const rt_request *req, uint64_t *ticket);
+
+/* Non-blocking: RT_PENDING, RT_OK (done, ticket retired) or an error status. */
+rt_status rt_poll(rt_handle *h, uint64_t ticket);
+
+/* Blocking variant of rt_poll. */
+rt_status rt_wait(rt_handle *h, uint64_t ticket);
+
+/* Latest error message of the handle (never NULL; "" if none). */
+const char *rt_last_error(const rt_handle *h);
+
+/* Static description of a status code. */
+const char *rt_status_string(rt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -30,19 +30,24 @@ import numpy as np
 HERE = pathlib.Path(__file__).resolve().parent
 SRC = HERE / "rt_oracle.c"
 LIB = HERE / "liborc_rt.so"
+LIB_LD = HERE / "liborc_rt_ld.so"   # same source, 80-bit long double arithmetic
 
 F_GUARD, F_ECLAMP, F_ETAU, F_EDOMAIN, F_INVALID, F_NONFIN = 1, 2, 4, 8, 16, 32
 
 
 def build(force: bool = True) -> pathlib.Path:
-    """Compile the oracle with gcc (no FMA contraction, OpenMP for timing)."""
-    if force or not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
-        tmp = LIB.with_suffix(".so.tmp")
-        subprocess.run(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-             "-shared", "-fopenmp", "-Wall", "-o", str(tmp), str(SRC), "-lm"],
-            check=True)
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (no FMA contraction, OpenMP for timing).
+
+    Two builds of the same source: FP64 (the oracle) and 80-bit long double
+    (used only to measure the rounding error of FP64 evaluations)."""
+    for out, extra in ((LIB, []), (LIB_LD, ["-DORC_LONG=1"])):
+        if force or not out.exists() or out.stat().st_mtime < SRC.stat().st_mtime:
+            tmp = out.with_suffix(".so.tmp")
+            subprocess.run(
+                ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                 "-shared", "-fopenmp", "-Wall", "-Wno-maybe-uninitialized", *extra, "-o", str(tmp), str(SRC), "-lm"],
+                check=True)
+            os.replace(tmp, out)
     return LIB
 
 
@@ -90,37 +95,47 @@ class Options:
                     self.g_guard, self.gravity, self.cp)
 
 
-_lib = None
+_libs: dict = {}
 
 
-def lib() -> ct.CDLL:
-    global _lib
-    if _lib is None:
-        if not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+def load(path) -> ct.CDLL:
+    """Load a build of the oracle source and declare its C signatures."""
+    L = ct.CDLL(str(path))
+    _declare(L)
+    return L
+
+
+def lib(extended: bool = False) -> ct.CDLL:
+    """The FP64 oracle library, or its long-double build if ``extended``."""
+    path = LIB_LD if extended else LIB
+    if path not in _libs:
+        if not path.exists() or path.stat().st_mtime < SRC.stat().st_mtime:
             build(force=True)
-        L = ct.CDLL(str(LIB))
-        L.orc_planck_bin.restype = ct.c_double
-        L.orc_planck_bin.argtypes = [ct.c_double, ct.c_double, ct.c_double]
-        L.orc_efit.restype = ct.c_double
-        L.orc_efit.argtypes = [ct.c_double, ct.c_double, ct.POINTER(Opts), _up]
-        L.orc_layer_coeffs.restype = None
-        L.orc_layer_coeffs.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double,
-                                       ct.POINTER(Opts), ct.POINTER(Layer)]
-        L.orc_assemble.restype = ct.c_int
-        L.orc_assemble.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
-                                   ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
-                                   _dp, _dp, _dp, _dp, _dp, _up]
-        L.orc_block_thomas.restype = ct.c_int
-        L.orc_block_thomas.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, _dp]
-        L.orc_column_bin.restype = ct.c_int
-        L.orc_column_bin.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
-                                     ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
-                                     _dp, _dp, _dp, _up]
-        L.orc_solve.restype = ct.c_int
-        L.orc_solve.argtypes = [ct.POINTER(Problem), ct.POINTER(Opts), ct.c_int]
-        L.orc_max_threads.restype = ct.c_int
-        _lib = L
-    return _lib
+        _libs[path] = load(path)
+    return _libs[path]
+
+
+def _declare(L: ct.CDLL) -> None:
+    L.orc_planck_bin.restype = ct.c_double
+    L.orc_planck_bin.argtypes = [ct.c_double, ct.c_double, ct.c_double]
+    L.orc_efit.restype = ct.c_double
+    L.orc_efit.argtypes = [ct.c_double, ct.c_double, ct.POINTER(Opts), _up]
+    L.orc_layer_coeffs.restype = None
+    L.orc_layer_coeffs.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                   ct.POINTER(Opts), ct.POINTER(Layer)]
+    L.orc_assemble.restype = ct.c_int
+    L.orc_assemble.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
+                               ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
+                               _dp, _dp, _dp, _dp, _dp, _up]
+    L.orc_block_thomas.restype = ct.c_int
+    L.orc_block_thomas.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.orc_column_bin.restype = ct.c_int
+    L.orc_column_bin.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, ct.c_long, ct.c_double,
+                                 ct.c_double, ct.c_double, ct.c_double, ct.POINTER(Opts),
+                                 _dp, _dp, _dp, _up]
+    L.orc_solve.restype = ct.c_int
+    L.orc_solve.argtypes = [ct.POINTER(Problem), ct.POINTER(Opts), ct.c_int]
+    L.orc_max_threads.restype = ct.c_int
 
 
 def _p(a: np.ndarray | None):
@@ -202,11 +217,12 @@ def column_bin(B, dtau, w0, g0, mu, Fstar, F_boa=0.0, F_toa=0.0,
 # ----------------------------------------------------------------- problem
 def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
           cols: tuple[int, int] | None = None, n_threads: int = 0,
-          F_toa: np.ndarray | None = None) -> dict:
+          F_toa: np.ndarray | None = None, extended: bool = False) -> dict:
     """Solve every (column, bin) of a workload dict (layouts as in ``synth``).
 
     ``cols`` restricts the solve to a column range (other outputs stay zero).
-    ``n_threads`` = 0 uses OpenMP's default.
+    ``n_threads`` = 0 uses OpenMP's default.  ``extended`` runs the same code
+    in 80-bit long double (error analysis only; results rounded to FP64).
     """
     C, N, NB = int(work["n_cols"]), int(work["n_layers"]), int(work["n_bins"])
     c0, c1 = cols if cols is not None else (0, C)
@@ -229,7 +245,7 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
                 _p(out.get("F_up_bin")), _p(out.get("F_dn_bin")), _p(out.get("F_beam_bin")),
                 out["flags"].ctypes.data_as(_up))
     o = (opts or Options()).c()
-    rc = lib().orc_solve(ct.byref(P), ct.byref(o), int(n_threads))
+    rc = lib(extended).orc_solve(ct.byref(P), ct.byref(o), int(n_threads))
     out["rc"] = rc
     return out
 

@@ -1,0 +1,439 @@
+// rt_api.hip -- host side of the C-ABI declared in include/rt.h.
+//
+// Validation, resident tables, work buffers and launches of the solve kernel
+// (stream-ordered path), plus the serving path: a request queue, admission by
+// device-memory footprint against a fixed arena, concurrent execution on a
+// small pool of streams, and completion tracking with events.
+#include "rt.h"
+#include "rt_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr double kH = 6.62607015e-34, kC = 299792458.0, kKB = 1.380649e-23;
+constexpr int kMaxBins = 512;
+constexpr int kMaxLayers = 4096;
+constexpr int kStreams = 4;
+constexpr size_t kAlign = 256;
+
+// First-fit sub-allocator over one device arena (serving work buffers).
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+
+    void reset(char *p, size_t n)
+    {
+        base = p;
+        size = n;
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = (n + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                size_t rest = it->second - n, o = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = (n + kAlign - 1) / kAlign * kAlign;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Job {
+    uint64_t ticket;
+    rt_request req;
+    size_t bytes = 0, off = 0;
+    int stream = -1;
+    hipEvent_t done = nullptr;
+    rt_status status = RT_PENDING;
+};
+
+}  // namespace
+
+struct rt_handle {
+    rt_config cfg{};
+    int NB = 0;
+    double *d_c2lam = nullptr;
+    float *d_c2lam_f = nullptr;
+    double *d_fstar = nullptr;
+    double *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::string err;
+    // serving
+    hipStream_t streams[kStreams] = {};
+    int next_stream = 0;
+    void *arena_mem = nullptr;
+    Arena arena;
+    uint64_t next_ticket = 1;
+    std::deque<Job> queued;
+    std::map<uint64_t, Job> running;
+    std::map<uint64_t, rt_status> finished;   // retired on first poll
+};
+
+static rt_status fail(rt_handle *h, rt_status s, const char *fmt, ...)
+{
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->err = buf;
+    }
+    return s;
+}
+
+static rt_status hip_fail(rt_handle *h, hipError_t e, const char *what)
+{
+    return fail(h, RT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" void rt_config_default(rt_config *c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->improved = 1;
+    c->noniso = 1;
+    c->e_clamp = 1;
+    c->eps2 = 2.0 / 3.0;
+    c->e_tau = 1e-4;
+    c->g_guard = 1e-5;
+    c->gravity = 47.0;
+    c->cp = 12436.0;
+    c->hbm_budget_bytes = 0;
+    c->max_inflight = 0;
+    c->device = 0;
+}
+
+extern "C" const char *rt_status_string(rt_status s)
+{
+    switch (s) {
+    case RT_OK: return "ok";
+    case RT_PENDING: return "pending";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ENOMEM: return "out of device memory or over budget";
+    case RT_EDEVICE: return "HIP runtime error";
+    case RT_EDOMAIN: return "E <= w0 in strict mode";
+    case RT_EBUSY: return "serving queue full";
+    case RT_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *rt_last_error(const rt_handle *h)
+{
+    return h ? h->err.c_str() : "null handle";
+}
+
+extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
+{
+    if (!cfg || !out) return RT_EINVAL;
+    const int NB = cfg->n_bins;
+    if (NB < 1 || NB > kMaxBins || !cfg->lambda_edges || !cfg->stellar_flux) return RT_EINVAL;
+    for (int e = 0; e <= NB; ++e) {
+        double l = cfg->lambda_edges[e];
+        if (!(l > 0.0) || !std::isfinite(l)) return RT_EINVAL;
+        if (e > 0 && !(l > cfg->lambda_edges[e - 1])) return RT_EINVAL;
+    }
+    for (int b = 0; b < NB; ++b)
+        if (!(cfg->stellar_flux[b] >= 0.0) || !std::isfinite(cfg->stellar_flux[b])) return RT_EINVAL;
+    if (!(cfg->eps2 > 0.0) || !(cfg->e_tau >= 0.0) || !(cfg->g_guard >= 0.0) ||
+        !(cfg->gravity > 0.0) || !(cfg->cp > 0.0) || cfg->hbm_budget_bytes < 0 ||
+        cfg->max_inflight < 0)
+        return RT_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+        return RT_EDEVICE;
+    if (hipSetDevice(cfg->device) != hipSuccess) return RT_EDEVICE;
+
+    rt_handle *h = new (std::nothrow) rt_handle();
+    if (!h) return RT_ENOMEM;
+    h->cfg = *cfg;
+    h->cfg.lambda_edges = nullptr;
+    h->cfg.stellar_flux = nullptr;
+    if (h->cfg.hbm_budget_bytes == 0) h->cfg.hbm_budget_bytes = 8ll << 30;
+    if (h->cfg.max_inflight == 0) h->cfg.max_inflight = 64;
+    h->NB = NB;
+
+    std::vector<double> c2(NB + 1);
+    std::vector<float> c2f(NB + 1);
+    const double c2rad = kH * kC / kKB;
+    for (int e = 0; e <= NB; ++e) {
+        c2[e] = c2rad / cfg->lambda_edges[e];
+        c2f[e] = float(c2[e]);
+    }
+    hipError_t err;
+    if ((err = hipMalloc(&h->d_c2lam, sizeof(double) * (NB + 1))) != hipSuccess ||
+        (err = hipMalloc(&h->d_c2lam_f, sizeof(float) * (NB + 1))) != hipSuccess ||
+        (err = hipMalloc(&h->d_fstar, sizeof(double) * NB)) != hipSuccess) {
+        rt_destroy(h);
+        return RT_ENOMEM;
+    }
+    if (hipMemcpy(h->d_c2lam, c2.data(), sizeof(double) * (NB + 1), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->d_c2lam_f, c2f.data(), sizeof(float) * (NB + 1), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->d_fstar, cfg->stellar_flux, sizeof(double) * NB, hipMemcpyHostToDevice)) {
+        rt_destroy(h);
+        return RT_EDEVICE;
+    }
+    *out = h;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_destroy(rt_handle *h)
+{
+    if (!h) return RT_OK;
+    (void)hipSetDevice(h->cfg.device);
+    for (auto &s : h->streams)
+        if (s) (void)hipStreamSynchronize(s);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : h->running)
+        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    for (auto &s : h->streams)
+        if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(h->d_c2lam);
+    (void)hipFree(h->d_c2lam_f);
+    (void)hipFree(h->d_fstar);
+    (void)hipFree(h->d_scratch);
+    (void)hipFree(h->arena_mem);
+    delete h;
+    return RT_OK;
+}
+
+static rt_status validate(rt_handle *h, const rt_request *r)
+{
+    if (!r) return fail(h, RT_EINVAL, "request is NULL");
+    if (r->n_cols < 1) return fail(h, RT_EINVAL, "n_cols must be >= 1 (got %d)", r->n_cols);
+    if (r->n_layers < 1 || r->n_layers > kMaxLayers)
+        return fail(h, RT_EINVAL, "n_layers must be in [1, %d] (got %d)", kMaxLayers, r->n_layers);
+    if (r->precision != RT_FP64 && r->precision != RT_MIXED)
+        return fail(h, RT_EINVAL, "precision must be RT_FP64 or RT_MIXED");
+    if (r->reserved_ != 0) return fail(h, RT_EINVAL, "reserved_ must be 0");
+    const void *req_in[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int};
+    const char *names_in[] = {"p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"};
+    for (int k = 0; k < 7; ++k)
+        if (!req_in[k]) return fail(h, RT_EINVAL, "%s is NULL", names_in[k]);
+    const void *req_out[] = {r->F_up, r->F_dn, r->F_beam, r->F_net, r->heating};
+    const char *names_out[] = {"F_up", "F_dn", "F_beam", "F_net", "heating"};
+    for (int k = 0; k < 5; ++k)
+        if (!req_out[k]) return fail(h, RT_EINVAL, "%s is NULL", names_out[k]);
+    const void *all[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int,
+                         r->F_toa, r->F_up, r->F_dn, r->F_beam, r->F_net, r->heating, r->dTdt,
+                         r->F_up_toa_bin, r->F_up_bin, r->F_dn_bin, r->flags};
+    for (const void *p : all)
+        if (p && (reinterpret_cast<uintptr_t>(p) % (p == r->flags ? 4 : 8)))
+            return fail(h, RT_EINVAL, "misaligned pointer %p", p);
+    const long long lanes = (long long)r->n_cols * h->NB;
+    if (lanes * (r->n_layers + 1) > (1ll << 40))
+        return fail(h, RT_EINVAL, "problem too large");
+    return RT_OK;
+}
+
+static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double *scratch)
+{
+    rtk::SolveArgs a{};
+    a.C = r->n_cols;
+    a.N = r->n_layers;
+    a.NB = h->NB;
+    a.c2_over_lam = h->d_c2lam;
+    a.c2_over_lam_f = h->d_c2lam_f;
+    a.F_star = h->d_fstar;
+    a.p = r->p_iface;
+    a.T = r->T_iface;
+    a.dtau = r->dtau;
+    a.w0 = r->w0;
+    a.g0 = r->g0;
+    a.mu = r->mu_star;
+    a.Tint = r->T_int;
+    a.Ftoa = r->F_toa;
+    a.F_up = r->F_up;
+    a.F_dn = r->F_dn;
+    a.F_beam = r->F_beam;
+    a.F_net = r->F_net;
+    a.heat = r->heating;
+    a.dTdt = r->dTdt;
+    a.F_up_toa_bin = r->F_up_toa_bin;
+    a.F_up_bin = r->F_up_bin;
+    a.F_dn_bin = r->F_dn_bin;
+    a.flags = r->flags;
+    a.scratch = scratch;
+    a.o.improved = h->cfg.improved;
+    a.o.noniso = h->cfg.noniso;
+    a.o.e_clamp = h->cfg.e_clamp;
+    a.o.eps2 = h->cfg.eps2;
+    a.o.e_tau = h->cfg.e_tau;
+    a.o.g_guard = h->cfg.g_guard;
+    a.o.gravity = h->cfg.gravity;
+    a.o.cp = h->cfg.cp;
+    return a;
+}
+
+extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *stream)
+{
+    if (!h) return RT_EINVAL;
+    rt_status st = validate(h, r);
+    if (st != RT_OK) return st;
+    (void)hipSetDevice(h->cfg.device);
+    const size_t need = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB);
+    if (need > h->scratch_bytes) {
+        // growth waits for the device: earlier solves may still use the old buffer
+        (void)hipDeviceSynchronize();
+        (void)hipFree(h->d_scratch);
+        h->d_scratch = nullptr;
+        h->scratch_bytes = 0;
+        if (hipMalloc(&h->d_scratch, need) != hipSuccess)
+            return fail(h, RT_ENOMEM, "work buffer of %zu bytes", need);
+        h->scratch_bytes = need;
+    }
+    rtk::SolveArgs a = make_args(h, r, h->d_scratch);
+    hipError_t e = rtk::launch_solve(a, r->precision, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "solve launch");
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- serving
+static rt_status ensure_serving(rt_handle *h)
+{
+    if (h->arena_mem) return RT_OK;
+    for (auto &s : h->streams)
+        if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return fail(h, RT_EDEVICE, "stream creation failed");
+    size_t bytes = (size_t)h->cfg.hbm_budget_bytes;
+    if (hipMalloc(&h->arena_mem, bytes) != hipSuccess) {
+        h->arena_mem = nullptr;
+        return fail(h, RT_ENOMEM, "serving arena of %zu bytes", bytes);
+    }
+    h->arena.reset((char *)h->arena_mem, bytes);
+    return RT_OK;
+}
+
+// Admit queued requests in arrival order while memory and slots allow.
+static void pump(rt_handle *h)
+{
+    // retire finished work first so its memory can be reused
+    for (auto it = h->running.begin(); it != h->running.end();) {
+        hipError_t q = hipEventQuery(it->second.done);
+        if (q == hipErrorNotReady) {
+            ++it;
+            continue;
+        }
+        rt_status s = (q == hipSuccess) ? RT_OK : RT_EDEVICE;
+        h->arena.release(it->second.off, it->second.bytes);
+        (void)hipEventDestroy(it->second.done);
+        h->finished[it->first] = s;
+        it = h->running.erase(it);
+    }
+    while (!h->queued.empty()) {
+        Job &j = h->queued.front();
+        size_t off;
+        if (!h->arena.alloc(j.bytes, &off)) break;   // wait for memory: keep arrival order
+        j.off = off;
+        j.stream = h->next_stream;
+        h->next_stream = (h->next_stream + 1) % kStreams;
+        hipStream_t s = h->streams[j.stream];
+        rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
+        hipError_t e = rtk::launch_solve(a, j.req.precision, s);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&j.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(j.done, s);
+        if (e != hipSuccess) {
+            hip_fail(h, e, "serving launch");
+            h->arena.release(off, j.bytes);
+            if (j.done) (void)hipEventDestroy(j.done);
+            h->finished[j.ticket] = RT_EDEVICE;
+            h->queued.pop_front();
+            continue;
+        }
+        h->running.emplace(j.ticket, j);
+        h->queued.pop_front();
+    }
+}
+
+extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *ticket)
+{
+    if (!h || !ticket) return RT_EINVAL;
+    rt_status st = validate(h, r);
+    if (st != RT_OK) return st;
+    (void)hipSetDevice(h->cfg.device);
+    if ((st = ensure_serving(h)) != RT_OK) return st;
+    if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight) {
+        pump(h);
+        if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight)
+            return fail(h, RT_EBUSY, "%d requests in flight", h->cfg.max_inflight);
+    }
+    Job j;
+    j.ticket = h->next_ticket++;
+    j.req = *r;
+    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB);
+    if (j.bytes > h->arena.size)
+        return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);
+    h->queued.push_back(j);
+    *ticket = j.ticket;
+    pump(h);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_poll(rt_handle *h, uint64_t ticket)
+{
+    if (!h) return RT_EINVAL;
+    (void)hipSetDevice(h->cfg.device);
+    pump(h);
+    auto f = h->finished.find(ticket);
+    if (f != h->finished.end()) {
+        rt_status s = f->second;
+        h->finished.erase(f);
+        return s;
+    }
+    if (h->running.count(ticket)) return RT_PENDING;
+    for (const Job &j : h->queued)
+        if (j.ticket == ticket) return RT_PENDING;
+    return fail(h, RT_ENOTFOUND, "ticket %llu", (unsigned long long)ticket);
+}
+
+extern "C" rt_status rt_wait(rt_handle *h, uint64_t ticket)
+{
+    if (!h) return RT_EINVAL;
+    for (;;) {
+        rt_status s = rt_poll(h, ticket);
+        if (s != RT_PENDING) return s;
+        auto it = h->running.find(ticket);
+        if (it != h->running.end()) {
+            (void)hipEventSynchronize(it->second.done);
+        } else if (!h->running.empty()) {
+            // queued behind memory: wait for the oldest running request
+            (void)hipEventSynchronize(h->running.begin()->second.done);
+        }
+    }
+}

@@ -1,0 +1,232 @@
+"""ctypes binding of the C-ABI in ``include/rt.h`` (argument marshalling only).
+
+Every function here forwards to ``librt_mi355x.so``; there is no other
+compute path.  If the library is missing the import-time loader raises, so a
+caller can never silently run without the GPU kernels.  PyTorch is used only
+to hold device memory and to supply the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import pathlib
+
+import numpy as np
+
+LIB_PATH = pathlib.Path(__file__).resolve().parent / "librt_mi355x.so"
+
+RT_OK, RT_PENDING = 0, 1
+RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EDOMAIN, RT_EBUSY, RT_ENOTFOUND = -1, -2, -3, -4, -5, -6
+RT_FP64, RT_MIXED = 0, 1
+FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
+
+#: every symbol include/rt.h declares
+SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes", "rt_submit",
+           "rt_poll", "rt_wait", "rt_last_error", "rt_status_string")
+
+
+class RtConfig(ct.Structure):
+    _fields_ = [("n_bins", ct.c_int32), ("improved", ct.c_int32), ("noniso", ct.c_int32),
+                ("e_clamp", ct.c_int32), ("lambda_edges", ct.POINTER(ct.c_double)),
+                ("stellar_flux", ct.POINTER(ct.c_double)), ("eps2", ct.c_double),
+                ("e_tau", ct.c_double), ("g_guard", ct.c_double), ("gravity", ct.c_double),
+                ("cp", ct.c_double), ("hbm_budget_bytes", ct.c_int64),
+                ("max_inflight", ct.c_int32), ("device", ct.c_int32)]
+
+
+class RtRequest(ct.Structure):
+    _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("precision", ct.c_int32),
+                ("reserved_", ct.c_int32)] + [
+        (n, ct.c_void_p) for n in (
+            "p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "F_toa",
+            "F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
+            "F_up_bin", "F_dn_bin", "flags")]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_2203_02293_amd.build.build() (no CPU fallback exists)")
+        L = ct.CDLL(str(LIB_PATH))
+        L.rt_config_default.argtypes = [ct.POINTER(RtConfig)]
+        L.rt_config_default.restype = None
+        L.rt_create.argtypes = [ct.POINTER(RtConfig), ct.POINTER(ct.c_void_p)]
+        L.rt_create.restype = ct.c_int32
+        L.rt_destroy.argtypes = [ct.c_void_p]
+        L.rt_destroy.restype = ct.c_int32
+        L.rt_solve_fluxes.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.c_void_p]
+        L.rt_solve_fluxes.restype = ct.c_int32
+        L.rt_submit.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.POINTER(ct.c_uint64)]
+        L.rt_submit.restype = ct.c_int32
+        L.rt_poll.argtypes = [ct.c_void_p, ct.c_uint64]
+        L.rt_poll.restype = ct.c_int32
+        L.rt_wait.argtypes = [ct.c_void_p, ct.c_uint64]
+        L.rt_wait.restype = ct.c_int32
+        L.rt_last_error.argtypes = [ct.c_void_p]
+        L.rt_last_error.restype = ct.c_char_p
+        L.rt_status_string.argtypes = [ct.c_int32]
+        L.rt_status_string.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------- thin wrappers
+def rt_config_default() -> RtConfig:
+    c = RtConfig()
+    lib().rt_config_default(ct.byref(c))
+    return c
+
+
+def rt_create(cfg: RtConfig) -> int:
+    h = ct.c_void_p()
+    st = lib().rt_create(ct.byref(cfg), ct.byref(h))
+    if st != RT_OK:
+        raise RtError(st, "rt_create: " + lib().rt_status_string(st).decode())
+    return h.value
+
+
+def rt_destroy(h: int) -> int:
+    return lib().rt_destroy(h)
+
+
+def rt_last_error(h: int) -> str:
+    return lib().rt_last_error(h).decode()
+
+
+def _check(h, st, what):
+    if st not in (RT_OK, RT_PENDING):
+        raise RtError(st, f"{what}: {lib().rt_status_string(st).decode()}: {rt_last_error(h)}")
+    return st
+
+
+def rt_solve_fluxes(h: int, req: RtRequest, stream: int | None) -> int:
+    return _check(h, lib().rt_solve_fluxes(h, ct.byref(req), stream), "rt_solve_fluxes")
+
+
+def rt_submit(h: int, req: RtRequest) -> int:
+    t = ct.c_uint64()
+    _check(h, lib().rt_submit(h, ct.byref(req), ct.byref(t)), "rt_submit")
+    return t.value
+
+
+def rt_poll(h: int, ticket: int) -> int:
+    return _check(h, lib().rt_poll(h, ticket), "rt_poll")
+
+
+def rt_wait(h: int, ticket: int) -> int:
+    return _check(h, lib().rt_wait(h, ticket), "rt_wait")
+
+
+# ------------------------------------------------------------ torch plumbing
+OUT_NAMES = ("F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin", "flags")
+
+
+class Solver:
+    """A handle plus torch-tensor marshalling for one spectral set-up."""
+
+    def __init__(self, lambda_edges, stellar_flux, improved=1, noniso=1, e_clamp=1,
+                 eps2=2.0 / 3.0, e_tau=1e-4, g_guard=1e-5, gravity=47.0, cp=12436.0,
+                 hbm_budget_bytes=0, max_inflight=0, device=0):
+        self._lam = np.ascontiguousarray(lambda_edges, dtype=np.float64)
+        self._fs = np.ascontiguousarray(stellar_flux, dtype=np.float64)
+        cfg = rt_config_default()
+        cfg.n_bins = self._fs.size
+        cfg.improved, cfg.noniso, cfg.e_clamp = improved, noniso, e_clamp
+        cfg.lambda_edges = self._lam.ctypes.data_as(ct.POINTER(ct.c_double))
+        cfg.stellar_flux = self._fs.ctypes.data_as(ct.POINTER(ct.c_double))
+        cfg.eps2, cfg.e_tau, cfg.g_guard = eps2, e_tau, g_guard
+        cfg.gravity, cfg.cp = gravity, cp
+        cfg.hbm_budget_bytes, cfg.max_inflight, cfg.device = hbm_budget_bytes, max_inflight, device
+        self.n_bins = cfg.n_bins
+        self.device = device
+        self.h = rt_create(cfg)
+
+    def close(self):
+        if self.h:
+            rt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- requests
+    def outputs(self, n_cols: int, n_layers: int, per_bin: bool = False):
+        import torch
+        dev = torch.device("cuda", self.device)
+        f = dict(dtype=torch.float64, device=dev)
+        C, N, NB = n_cols, n_layers, self.n_bins
+        out = {k: torch.empty((N + 1, C), **f) for k in ("F_up", "F_dn", "F_beam", "F_net")}
+        out["heating"] = torch.empty((N, C), **f)
+        out["dTdt"] = torch.empty((N, C), **f)
+        out["F_up_toa_bin"] = torch.empty((C, NB), **f)
+        out["flags"] = torch.zeros(C, dtype=torch.int32, device=dev)
+        if per_bin:
+            out["F_up_bin"] = torch.empty((N + 1, C, NB), **f)
+            out["F_dn_bin"] = torch.empty((N + 1, C, NB), **f)
+        return out
+
+    def request(self, inp: dict, out: dict, precision: int = RT_FP64) -> RtRequest:
+        """Build an rt_request from device tensors (shapes as in include/rt.h)."""
+        C = int(inp["mu_star"].shape[0])
+        N = int(inp["dtau"].shape[0])
+        r = RtRequest()
+        r.n_cols, r.n_layers, r.precision, r.reserved_ = C, N, precision, 0
+
+        def ptr(t):
+            if t is None:
+                return None
+            assert t.is_cuda and t.is_contiguous(), "inputs must be contiguous device tensors"
+            return t.data_ptr()
+        for k in ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"):
+            setattr(r, k, ptr(inp[k]))
+        r.F_toa = ptr(inp.get("F_toa"))
+        for k in ("F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
+                  "F_up_bin", "F_dn_bin", "flags"):
+            setattr(r, k, ptr(out.get(k)))
+        return r
+
+    def solve(self, inp: dict, precision: int = RT_FP64, per_bin: bool = False,
+              out: dict | None = None, stream=None) -> dict:
+        """Stream-ordered solve on the current (or given) torch stream."""
+        import torch
+        C, N = int(inp["mu_star"].shape[0]), int(inp["dtau"].shape[0])
+        if out is None:
+            out = self.outputs(C, N, per_bin)
+        req = self.request(inp, out, precision)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rt_solve_fluxes(self.h, req, s.cuda_stream)
+        return out
+
+    def submit(self, inp: dict, out: dict, precision: int = RT_FP64) -> int:
+        return rt_submit(self.h, self.request(inp, out, precision))
+
+    def poll(self, ticket: int) -> int:
+        return rt_poll(self.h, ticket)
+
+    def wait(self, ticket: int) -> int:
+        return rt_wait(self.h, ticket)
+
+
+def to_device(work: dict, device: int = 0) -> dict:
+    """Copy the arrays of a ``synth`` workload to device tensors."""
+    import torch
+    dev = torch.device("cuda", device)
+    keys = ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int")
+    d = {k: torch.from_numpy(np.ascontiguousarray(work[k])).to(dev) for k in keys}
+    if work.get("F_toa") is not None:
+        d["F_toa"] = torch.from_numpy(np.ascontiguousarray(work["F_toa"])).to(dev)
+    return d

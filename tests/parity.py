@@ -1,0 +1,71 @@
+"""Shared helpers of the GPU parity tests: error metrics and sub-sampling.
+
+Error metric (stated once, used everywhere).  Net fluxes cross zero, deep net
+fluxes are a small fraction of the gross fluxes and cold short-wave bins
+underflow, so each comparison is scaled by S, the largest gross flux
+(F_up + F_dn + F_beam) of that column (bin-summed quantities) or of that
+(column, bin) (per-bin quantities):
+  F_up, F_dn, F_beam:  |x - x_ref| <= tol * max(|x_ref|, floor * S)
+  F_net:               |x - x_ref| <= tol * S
+  heating:             |Q - Q_ref| (p_j - p_{j+1}) / g <= tol * S
+The reference is the oracle's extended-precision build (same code, 80-bit
+arithmetic), whose own rounding error is far below these bars.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GRAV = 47.0
+
+
+def subset(work: dict, cols) -> dict:
+    """The same workload restricted to a list of columns (columns are independent)."""
+    cols = np.asarray(cols)
+    w = dict(work)
+    w["n_cols"] = cols.size
+    for k in ("p_iface", "T_iface"):
+        w[k] = np.ascontiguousarray(work[k][:, cols])
+    for k in ("dtau", "w0", "g0"):
+        w[k] = np.ascontiguousarray(work[k][:, cols, :])
+    for k in ("mu_star", "T_int"):
+        w[k] = np.ascontiguousarray(work[k][cols])
+    if work.get("F_toa") is not None:
+        w["F_toa"] = np.ascontiguousarray(work["F_toa"][cols])
+    return w
+
+
+def errors(out: dict, ref: dict, p_iface: np.ndarray, floor: float = 1e-3,
+           cols=None, gravity: float = GRAV) -> dict:
+    """Scaled errors of the bin-summed outputs (and per-bin ones if present)."""
+    def host(x):
+        return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+    o = {k: host(v) for k, v in out.items()}
+    if cols is not None:
+        cols = np.asarray(cols)
+        o = {k: (v[:, cols] if v.ndim == 2 and k not in ("F_up_toa_bin",) else
+                 v[cols] if k in ("flags", "F_up_toa_bin") else
+                 v[:, cols, :] if v.ndim == 3 else v) for k, v in o.items()}
+    S = (ref["F_up"] + ref["F_dn"] + ref["F_beam"]).max(axis=0)
+    e = {}
+    for k in ("F_up", "F_dn", "F_beam"):
+        e[k] = (np.abs(o[k] - ref[k]) / np.maximum(np.abs(ref[k]), floor * S)).max()
+    e["F_net"] = (np.abs(o["F_net"] - ref["F_net"]) / S).max()
+    dp = p_iface[:-1] - p_iface[1:]
+    e["heating"] = (np.abs(o["heating"] - ref["heating"]) * dp / gravity / S).max()
+    if "F_up_bin" in o and "F_up_bin" in ref:
+        Sb = (ref["F_up_bin"] + ref["F_dn_bin"] + ref["F_beam_bin"]).max(axis=0)
+        Sb = np.maximum(Sb, 1e-300)
+        for k in ("F_up_bin", "F_dn_bin"):
+            e[k] = (np.abs(o[k] - ref[k]) / np.maximum(np.abs(ref[k]), floor * Sb)).max()
+    if "F_up_toa_bin" in o and "F_up_toa_bin" in ref:
+        Sb = (ref["F_up"] + ref["F_dn"] + ref["F_beam"]).max(axis=0)[:, None]
+        e["F_up_toa_bin"] = (np.abs(o["F_up_toa_bin"] - ref["F_up_toa_bin"]) /
+                             np.maximum(np.abs(ref["F_up_toa_bin"]), floor * Sb)).max()
+    return e
+
+
+def assert_close(out, ref, p_iface, tol, floor=1e-3, cols=None, keys=None):
+    e = errors(out, ref, p_iface, floor=floor, cols=cols)
+    bad = {k: v for k, v in e.items() if (keys is None or k in keys) and not (v <= tol)}
+    assert not bad, f"errors above {tol}: {bad} (all: {e})"
+    return e
