@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many bytes (calibrates "
+                         "the HBM byte counters against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solve has no "
@@ -121,6 +124,16 @@ def main():
 
     import torch
     from paper_2203_02293_amd import rt, synth
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "read": n * 8, "written": n * 8}))
+        return
 
     work = synth.make(WORKLOAD)
     C, N, NB = work["n_cols"], work["n_layers"], work["n_bins"]

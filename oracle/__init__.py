@@ -30,7 +30,7 @@ import numpy as np
 HERE = pathlib.Path(__file__).resolve().parent
 SRC = HERE / "rt_oracle.c"
 LIB = HERE / "liborc_rt.so"
-LIB_LD = HERE / "liborc_rt_ld.so"   # same source, 80-bit long double arithmetic
+LIB_X = HERE / "liborc_rt_q.so"    # same source, binary128 arithmetic
 
 F_GUARD, F_ECLAMP, F_ETAU, F_EDOMAIN, F_INVALID, F_NONFIN = 1, 2, 4, 8, 16, 32
 
@@ -38,14 +38,15 @@ F_GUARD, F_ECLAMP, F_ETAU, F_EDOMAIN, F_INVALID, F_NONFIN = 1, 2, 4, 8, 16, 32
 def build(force: bool = True) -> pathlib.Path:
     """Compile the oracle with gcc (no FMA contraction, OpenMP for timing).
 
-    Two builds of the same source: FP64 (the oracle) and 80-bit long double
-    (used only to measure the rounding error of FP64 evaluations)."""
-    for out, extra in ((LIB, []), (LIB_LD, ["-DORC_LONG=1"])):
+    Two builds of the same source: FP64 (the oracle) and binary128 (used to
+    measure the rounding error of FP64 evaluations; the parity reference)."""
+    for out, extra in ((LIB, []), (LIB_X, ["-DORC_QUAD=1"])):
         if force or not out.exists() or out.stat().st_mtime < SRC.stat().st_mtime:
             tmp = out.with_suffix(".so.tmp")
             subprocess.run(
                 ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                 "-shared", "-fopenmp", "-Wall", "-Wno-maybe-uninitialized", *extra, "-o", str(tmp), str(SRC), "-lm"],
+                 "-shared", "-fopenmp", "-Wall", "-Wno-maybe-uninitialized", *extra, "-o", str(tmp),
+                 str(SRC), "-lquadmath", "-lm"],
                 check=True)
             os.replace(tmp, out)
     return LIB
@@ -106,8 +107,8 @@ def load(path) -> ct.CDLL:
 
 
 def lib(extended: bool = False) -> ct.CDLL:
-    """The FP64 oracle library, or its long-double build if ``extended``."""
-    path = LIB_LD if extended else LIB
+    """The FP64 oracle library, or its binary128 build if ``extended``."""
+    path = LIB_X if extended else LIB
     if path not in _libs:
         if not path.exists() or path.stat().st_mtime < SRC.stat().st_mtime:
             build(force=True)
@@ -222,7 +223,7 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
 
     ``cols`` restricts the solve to a column range (other outputs stay zero).
     ``n_threads`` = 0 uses OpenMP's default.  ``extended`` runs the same code
-    in 80-bit long double (error analysis only; results rounded to FP64).
+    in binary128 (parity reference; results rounded to FP64).
     """
     C, N, NB = int(work["n_cols"]), int(work["n_layers"]), int(work["n_bins"])
     c0, c1 = cols if cols is not None else (0, C)

@@ -38,14 +38,17 @@
 #endif
 
 /*
- * Arithmetic type.  The oracle is FP64 (ORC_LONG undefined).  The same source
- * compiled with -DORC_LONG=1 evaluates every step in 80-bit long double; that
- * build is used only to measure the rounding error of FP64 evaluations.
+ * Arithmetic type.  The oracle is FP64 (ORC_QUAD undefined).  The same source
+ * compiled with -DORC_QUAD=1 evaluates every step in IEEE binary128
+ * (__float128, libquadmath); that build measures the rounding error of FP64
+ * evaluations of the printed formulas, which cancel badly for thin layers and
+ * near the G+- resonance, and serves as the reference of the parity tests.
  */
-#ifdef ORC_LONG
-typedef long double real;
-#define RF(f) f##l
-#define K_(x) x##L
+#ifdef ORC_QUAD
+#include <quadmath.h>
+typedef __float128 real;
+#define RF(f) f##q
+#define K_(x) x##Q
 #else
 typedef double real;
 #define RF(f) f
@@ -80,7 +83,7 @@ static void orc_gauss_legendre(void)
             dp = n * (z * p0 - p1) / (z * z - 1);
             real dz = p0 / dp;
             z -= dz;
-            if (RF(fabs)(dz) < K_(1e-19)) break;
+            if (RF(fabs)(dz) < K_(1e-32)) break;
         }
         gl_x[i] = z;
         gl_w[i] = 2 / ((1 - z * z) * dp * dp);
@@ -128,15 +131,26 @@ double orc_planck_bin(double T, double lam1, double lam2)
     return (double)orc_planck_bin_r(T, lam1, lam2);
 }
 
-/* Ratio of first Eddington coefficients, Section 2.2.4. */
-static real orc_efit_r(real w0, real g0, const orc_opts *o, uint32_t *flags)
+/*
+ * Ratio of first Eddington coefficients, Section 2.2.4.  The branch decisions
+ * (w0 > 0.1, E_fit < 1, E <= w0) are always taken on the FP64 values, so the
+ * extended build follows exactly the branches of the FP64 definition.
+ */
+static double orc_efit_double(double w0, double g0)
 {
-    if (!o->improved || !(w0 > K_(0.1))) return 1;
+    return 1.225 - 0.1582 * g0 - 0.1777 * w0 - 0.07465 * g0 * g0
+         + 0.2351 * w0 * g0 - 0.05582 * w0 * w0;
+}
+
+static real orc_efit_r(double w0, double g0, const orc_opts *o, uint32_t *flags)
+{
+    if (!o->improved || !(w0 > 0.1)) return 1;
+    double Ed = orc_efit_double(w0, g0);
     real E = K_(1.225) - K_(0.1582) * g0 - K_(0.1777) * w0 - K_(0.07465) * g0 * g0
            + K_(0.2351) * w0 * g0 - K_(0.05582) * w0 * w0;
     if (o->e_clamp) {
-        if (E < 1) { E = 1; *flags |= ORC_F_ECLAMP; }
-    } else if (E <= w0) {
+        if (Ed < 1.0) { E = 1; *flags |= ORC_F_ECLAMP; }
+    } else if (Ed <= w0) {
         *flags |= ORC_F_EDOMAIN;
     }
     return E;
@@ -149,11 +163,16 @@ double orc_efit(double w0, double g0, const orc_opts *o, uint32_t *flags)
 
 typedef struct { real E, zp, zm, Tr, chi, xi, psi, Pi, Gp, Gm, D; uint32_t flags; } lyr;
 
-/* Appendix B: coupling coefficients, transmission, chi/xi/psi, Pi and G+-. */
-static void orc_layer_r(real dtau, real w0, real g0, real mu, const orc_opts *o, lyr *L)
+/*
+ * Appendix B: coupling coefficients, transmission, chi/xi/psi, Pi and G+-.
+ * The resonance guard decides on D evaluated in FP64 (see orc_efit_r).
+ */
+static void orc_layer_r(double dtau_d, double w0_d, double g0_d, double mu_d,
+                        const orc_opts *o, lyr *L)
 {
     memset(L, 0, sizeof(*L));
-    real E = orc_efit_r(w0, g0, o, &L->flags);
+    real dtau = dtau_d, w0 = w0_d, g0 = g0_d, mu = mu_d;
+    real E = orc_efit_r(w0_d, g0_d, o, &L->flags);
     real zp = (1 + RF(sqrt)((E - w0) / (E * (1 - w0 * g0)))) / 2;
     real zm = (1 - RF(sqrt)((E - w0) / (E * (1 - w0 * g0)))) / 2;
     real Tr = RF(exp)(-2 * RF(sqrt)(E * (E - w0) * (1 - w0 * g0)) * dtau);
@@ -168,7 +187,9 @@ static void orc_layer_r(real dtau, real w0, real g0, real mu, const orc_opts *o,
     if (mu > 0) {
         real ms = -mu;   /* paper's negative zenith cosine */
         real D = 4 * E * ms * ms * (E - w0) * (1 - w0 * g0) - 1;
-        if (RF(fabs)(D) < o->g_guard) {
+        double Ed = (double)E, msd = -mu_d;
+        double Dd = 4.0 * Ed * msd * msd * (Ed - w0_d) * (1.0 - w0_d * g0_d) - 1.0;
+        if (fabs(Dd) < o->g_guard) {
             D = 2 * ms;
             L->flags |= ORC_F_GUARD;
         }
@@ -228,13 +249,14 @@ static void orc_assemble_r(int N, const real *B, const double *dtau, const doubl
     D[2 * N + 1] = F_toa;
 
     for (int j = 0; j < N; ++j) {
-        real dt = dtau[(long)j * stride];
+        double dt_d = dtau[(long)j * stride];
+        real dt = dt_d;
         real w = w0[(long)j * stride], g = g0[(long)j * stride];
         lyr L;
-        orc_layer_r(dt, w, g, mu, o, &L);
+        orc_layer_r(dt_d, w0[(long)j * stride], g0[(long)j * stride], (double)mu, o, &L);
         *flags |= L.flags;
         real Blo = B[j], Bup = B[j + 1], Bp = 0, Theta = 0;
-        if (!o->noniso || dt < o->e_tau) {
+        if (!o->noniso || dt_d < o->e_tau) {
             /* constant Planck function within the layer */
             if (o->noniso) *flags |= ORC_F_ETAU;
             Blo = Bup = (B[j] + B[j + 1]) / 2;

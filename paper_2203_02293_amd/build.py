@@ -10,7 +10,8 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "librt_mi355x.so"
 SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_api.hip"]
-HEADERS = [CSRC / "rt_internal.hpp", ROOT / "include" / "rt.h"]
+HEADERS = [CSRC / "rt_internal.hpp", CSRC / "rt_math.hpp", CSRC / "rt_physics.hpp",
+           ROOT / "include" / "rt.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -28,249 +28,14 @@
 //   (f = beam at the layer top, beta = exp(-dtau/mu), G+- with mu_star = -mu);
 //   near it the same quantity regularised by dividing out (mu lambda - 1).
 #include "rt_internal.hpp"
+#include "rt_math.hpp"
+#include "rt_physics.hpp"
 
 #include <math.h>
 #include <type_traits>
 
 namespace rtk {
 namespace {
-
-constexpr double kPI = 3.141592653589793238462643383279502884;
-constexpr double kH = 6.62607015e-34;   // SI 2019, exact
-constexpr double kC = 299792458.0;
-constexpr double kKB = 1.380649e-23;
-constexpr double kPref = 2.0 * kKB * kKB * kKB * kKB / (kH * kH * kH * kC * kC);
-constexpr double kPI4_15 = kPI * kPI * kPI * kPI / 15.0;
-
-enum : uint32_t {
-    F_GUARD = 1u, F_ECLAMP = 2u, F_ETAU = 4u, F_EDOMAIN = 8u, F_INVALID = 16u, F_NONFIN = 32u
-};
-
-// ---------------------------------------------------------------------------
-// Planck bin integrals.  With x = c2/(lambda T):
-//   B_b(T) = (2 k^4 T^4 / (h^3 c^2)) * int_{x_a}^{x_b} t^3/(e^t - 1) dt.
-// Small x: Q(x) = int_0^x = x^3/3 - x^4/8 + sum_k B_2k x^(2k+3)/((2k+3)(2k)!)
-// (Bernoulli series, converges for x < 2 pi).  Large x: P(x) = int_x^inf =
-// sum_n e^{-nx} (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4).  Series coefficients are
-// compile-time constants: B_2k/(2k)! = (-1)^{k+1} 2 zeta(2k)/(2 pi)^{2k}.
-// ---------------------------------------------------------------------------
-constexpr double zeta_even(int s)
-{
-    constexpr int M = 64;
-    double sum = 0.0;
-    for (int n = M - 1; n >= 1; --n) {
-        double inv = 1.0 / n, t = 1.0;
-        for (int i = 0; i < s; ++i) t *= inv;
-        sum += t;
-    }
-    double Mi = 1.0 / M, Ms = 1.0, ds = s;
-    for (int i = 0; i < s; ++i) Ms *= Mi;
-    double tail = Ms * M / (ds - 1.0) + 0.5 * Ms + ds * Ms * Mi / 12.0
-                - ds * (ds + 1) * (ds + 2) * Ms * Mi * Mi * Mi / 720.0
-                + ds * (ds + 1) * (ds + 2) * (ds + 3) * (ds + 4) * Ms * Mi * Mi * Mi * Mi * Mi
-                      / 30240.0;
-    return sum + tail;
-}
-
-constexpr double bern_coef(int k)   // B_2k / ((2k+3) (2k)!)
-{
-    double tp = 1.0;
-    for (int i = 0; i < 2 * k; ++i) tp *= 2.0 * kPI;
-    double v = 2.0 * zeta_even(2 * k) / (tp * (2.0 * k + 3.0));
-    return (k % 2 == 1) ? v : -v;
-}
-
-template <class R> struct PCfg;
-template <> struct PCfg<double> {
-    static constexpr double XS = 3.0;   // series switch
-    static constexpr int NQ = 28;       // Bernoulli terms: (3/2pi)^56 < 1e-18
-    static constexpr int NP = 13;       // exponential terms: e^-39 < 1e-16
-};
-template <> struct PCfg<float> {
-    static constexpr float XS = 2.5f;
-    static constexpr int NQ = 10;
-    static constexpr int NP = 8;
-};
-
-template <class R, int K, int NQ>
-__device__ __forceinline__ R bern_horner(R x2)
-{
-    if constexpr (K == NQ) {
-        return R(bern_coef(NQ));
-    } else {
-        return fma(bern_horner<R, K + 1, NQ>(x2), x2, R(bern_coef(K)));
-    }
-}
-
-// +Q(x) for x <= XS, -P(x) otherwise: the sign bit records which tail it is.
-template <class R>
-__device__ __forceinline__ R planck_edge(R x)
-{
-    using Cfg = PCfg<R>;
-    if (x <= Cfg::XS) {
-        R x2 = x * x;
-        R poly = bern_horner<R, 1, Cfg::NQ>(x2);
-        return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + poly * x2);
-    }
-    R y = exp(-x), yn = y, sum = R(0);
-#pragma unroll
-    for (int n = 1; n <= Cfg::NP; ++n) {
-        const R in = R(1) / R(n);
-        R poly = ((x * in + R(3) * in * in) * x + R(6) * in * in * in) * x
-               + R(6) * in * in * in * in;
-        sum = fma(yn, poly, sum);
-        yn *= y;
-    }
-    return -sum;
-}
-
-// int_{x_a}^{x_b} t^3/(e^t-1) dt from the two edge values (x_b > x_a):
-// same tail on both sides: difference; straddling XS: pi^4/15 - P(x_b) - Q(x_a).
-template <class R>
-__device__ __forceinline__ R planck_combine(R vb, R va)
-{
-    R d = vb - va;
-    if (signbit(vb) && !signbit(va)) d += R(kPI4_15);
-    return d;
-}
-
-// ---------------------------------------------------------------------------
-// Predicates in FP64, rounded exactly as the printed formulas read left to
-// right (no contraction), so that both precisions take the paper's branch
-// decisions on the same values.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double efit_exact(double w0, double g0, const Opts &o, uint32_t &fl)
-{
-#pragma clang fp contract(off)
-    if (!o.improved || !(w0 > 0.1)) return 1.0;
-    double E = 1.225 - 0.1582 * g0 - 0.1777 * w0 - 0.07465 * g0 * g0
-             + 0.2351 * w0 * g0 - 0.05582 * w0 * w0;
-    if (o.e_clamp) {
-        if (E < 1.0) {
-            E = 1.0;
-            fl |= F_ECLAMP;
-        }
-    } else if (E <= w0) {
-        fl |= F_EDOMAIN;
-    }
-    return E;
-}
-
-__device__ __forceinline__ double resonance_D(double E, double w0, double g0, double mu)
-{
-#pragma clang fp contract(off)
-    double ms = -mu;
-    return 4.0 * E * ms * ms * (E - w0) * (1.0 - w0 * g0) - 1.0;
-}
-
-// ---------------------------------------------------------------------------
-// helper functions of u
-// ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ R phi1(R x)   // (1 - e^-x)/x, x >= 0
-{
-    return (x > R(0)) ? -expm1(-x) / x : R(1);
-}
-
-template <class R> struct ShCfg;
-template <> struct ShCfg<double> { static constexpr int N = 12; };
-template <> struct ShCfg<float> { static constexpr int N = 7; };
-
-// e^-u (sinh u - u)/u^2, u >= 0, given T = e^-u
-template <class R>
-__device__ __forceinline__ R hfun(R u, R T)
-{
-    if (u < R(2)) {
-        // (sinh u - u)/u^2 = u sum_{k>=1} u^{2(k-1)} / (2k+1)!
-        R u2 = u * u, acc = R(0);
-#pragma unroll
-        for (int k = ShCfg<R>::N; k >= 1; --k) {
-            double f = 1.0;
-            for (int m = 2; m <= 2 * k + 1; ++m) f *= m;
-            acc = fma(acc, u2, R(1.0 / f));
-        }
-        return T * u * acc;
-    }
-    return (R(0.5) * (R(1) - T * T) - u * T) / (u * u);
-}
-
-template <class R>
-struct Layer {
-    R t, r, omr, A, Sup, Sdn;
-};
-
-// Coefficients and normalised sources of one layer (see the file header).
-template <class R>
-__device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, bool day, R mu, R Dres,
-                                            bool guard, R f, R beta, R Blo, R Bup, bool iso,
-                                            R eps2, Layer<R> &L)
-{
-    const R one = R(1), half = R(0.5);
-    R om = one - w0 * g0;
-    R Ew = E - w0;
-    R kap = R(2) * E * om;
-    R s = sqrt(Ew / (E * om));
-    R lam = kap * s;
-    R u = lam * dtau;
-    R Tr = exp(-u);
-    R omT = -expm1(-u);
-    R zp = half * (one + s), zm = half * (one - s);
-    R p = (s > R(0)) ? omT / s : kap * dtau;
-    R q = p * (one + Tr);
-    R den = fma(zm * zm, q, one);
-    R id = one / den;
-    R t = Tr * id;
-    R r = zp * zm * q * id;
-    R A = omT * (zp - zm * Tr) * id;
-    L.t = t;
-    L.r = r;
-    L.A = A;
-    L.omr = (zp + zm * Tr * Tr) * id;
-    R Pi = (E == one) ? R(kPI) : R(kPI) * (one - w0) / Ew;
-    R Sup, Sdn;
-    if (iso) {
-        R Bm = half * (Blo + Bup);
-        Sup = Pi * A * Bm;
-        Sdn = Sup;
-    } else {
-        R ph = (u > R(0)) ? omT / u : one;
-        R Gd = u * (hfun(u, Tr) + half * s * ph * ph) * id;
-        R dB = Blo - Bup;
-        Sup = Pi * (A * Bup + dB * Gd);
-        Sdn = Pi * (A * Blo - dB * Gd);
-    }
-    if (day) {
-        R c1 = w0 * (kap + g0 / eps2);
-        R Qc = w0 * g0 / (eps2 * kap);
-        R lm = lam * mu;
-        R sb_up, sb_dn;
-        if (guard || fabs(lm - one) >= R(0.25)) {
-            R Dd = guard ? R(-2) * mu : Dres;
-            R P = c1 / Dd;
-            R ik = one / kap;
-            R Gp = half * (P * (ik - mu) + Qc);
-            R Gm = -half * (P * (ik + mu) + Qc);
-            sb_up = f * (r * Gm - Gp * (one - t * beta));
-            sb_dn = f * (r * beta * Gp - Gm * (beta - t));
-        } else {
-            // resonance-regularised: X, Yh = Y (a - lambda) are finite at mu lambda = 1
-            R a = one / mu;
-            R X = (Qc - c1 / (kap * (one + lm))) / (one + s);
-            R Yh = (Qc * (a - lam) - c1 * a / kap) / (one + s);
-            R dq = (a >= lam) ? Tr * phi1((a - lam) * dtau) : beta * phi1((lam - a) * dtau);
-            R Z = Yh * dq * dtau;
-            R rho = zm / zp;
-            R iom = (zp * zp) / (s * den);          // 1 / (1 - rho^2 T^2)
-            R obt = -expm1(-(a + lam) * dtau);      // 1 - beta T
-            sb_up = f * (rho * Tr * Z - X * obt) * iom;
-            sb_dn = f * (rho * Tr * X * obt - Z) * iom;
-        }
-        Sup += sb_up;
-        Sdn += sb_dn;
-    }
-    L.Sup = Sup;
-    L.Sdn = Sdn;
-}
 
 // LDS chunk of interfaces reduced at once over bins
 __host__ __device__ constexpr int lds_budget() { return 60 * 1024; }
@@ -313,8 +78,10 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
     // Planck radiance of this lane's bin at one level; all threads take part.
     auto planck_level = [&](const double *Tsrc, long long off) -> R {
         __syncthreads();
+        // edge-major: a wavefront takes one edge of many columns, so its lanes
+        // mostly sit in the same series regime
         for (int e = tid; e < nedge; e += bd) {
-            int kk = e / (NB + 1), ee = e - kk * (NB + 1);
+            int ee = e / K, kk = e - ee * K;
             int cc = blockIdx.x * K + kk;
             R v = R(0);
             if (cc < C) {
@@ -324,15 +91,20 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
                 else x = a.c2_over_lam[ee] / T;
                 v = planck_edge<R>(x);
             }
-            s_edge[e] = v;
+            s_edge[kk * (NB + 1) + ee] = v;
         }
         __syncthreads();
         R B = R(0);
         if (active) {
             R T = R(Tsrc[off + c]);
             R T2 = T * T;
-            B = R(kPref) * T2 * T2
-              * planck_combine<R>(s_edge[kloc * (NB + 1) + b], s_edge[kloc * (NB + 1) + b + 1]);
+            R I = planck_combine<R>(s_edge[kloc * (NB + 1) + b], s_edge[kloc * (NB + 1) + b + 1]);
+            if constexpr (MIXED) {
+                const R iT = rcp(T);
+                const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
+                if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
+            }
+            B = R(kPref) * T2 * T2 * I;
         }
         return B;
     };
@@ -353,17 +125,14 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
         if (!(T > 0.0) || !isfinite(T)) fl |= F_INVALID;
     }
 
-    double cc_ = 0.0, eps = 1.0, d = 0.0;
-    double Fb = 0.0, tau = 0.0;
-    R Fstar = R(0);
+    LaneState st;
+    double Fstar_b = 0.0;
     if (active) {
-        if (a.Ftoa) d = a.Ftoa[(long long)c * NB + b];
-        if (day) {
-            Fb = mu * a.F_star[b];
-            Fstar = R(a.F_star[b]);
-        }
+        Fstar_b = a.F_star[b];
+        st = lane_top(day, mu, Fstar_b, a.Ftoa ? a.Ftoa[(long long)c * NB + b] : 0.0);
     }
     const double inv_mu = day ? 1.0 / mu : 0.0;
+    const double inv_eps2 = 1.0 / a.o.eps2;
     const long long LB = (long long)C * NB;
     const long long L = a.L;
 
@@ -371,55 +140,15 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
         R Blo = planck_level(a.T, (long long)j * C);
         if (active) {
             const long long idx = (long long)j * LB + (long long)c * NB + b;
-            const double dt = a.dtau[idx], w = a.w0[idx], g = a.g0[idx];
-            const double Tl = a.T[(long long)j * C + c];
-            if (!(dt >= 0.0) || !isfinite(dt) || !(w >= 0.0 && w <= 1.0) || !(g > -1.0 && g < 1.0)
-                || !(Tl > 0.0) || !isfinite(Tl))
-                fl |= F_INVALID;
-            const double E = efit_exact(w, g, a.o, fl);
-            bool guard = false;
-            double D = 0.0;
-            if (day) {
-                D = resonance_D(E, w, g, mu);
-                guard = fabs(D) < a.o.g_guard;
-                if (guard) fl |= F_GUARD;
-            }
-            const bool iso = !a.o.noniso || dt < a.o.e_tau;
-            if (a.o.noniso && dt < a.o.e_tau) fl |= F_ETAU;
-
-            double Fb_lo = 0.0;
-            R beta = R(0);
-            if (day) {
-                if constexpr (MIXED) {
-                    tau += dt;
-                    Fb_lo = mu * double(a.F_star[b]) * double(expf(float(-tau * inv_mu)));
-                    beta = expf(float(-dt * inv_mu));
-                } else {
-                    beta = exp(-dt * inv_mu);
-                    Fb_lo = Fb * beta;
-                }
-            }
-            Layer<R> Ly;
-            layer_terms<R>(R(dt), R(w), R(g), R(E), day, R(mu), R(D), guard, R(Fb), beta, Blo,
-                           Bup, iso, R(a.o.eps2), Ly);
-            const double t = Ly.t, r = Ly.r, omr = Ly.omr, A = Ly.A;
-            const double Sup = Ly.Sup, Sdn = Ly.Sdn;
-            // Thomas forward elimination (FP64): F_dn_i = c_i F_up_i + d_i,
-            // eps_i = 1 - c_i carried without subtraction.
-            const double inv = 1.0 / (omr + r * eps);
+            const BackRec rec = lane_layer<MIXED>(st, a.dtau[idx], a.w0[idx], a.g0[idx],
+                                                  a.T[(long long)j * C + c], day, mu, inv_mu,
+                                                  Fstar_b, Blo, Bup, a.o, inv_eps2, fl);
             double *sp = a.scratch + (long long)j * 5 * L + gl;
-            sp[0] = t * inv;                  // G_j: F_up_{j+1} = G_j F_up_j + H_j
-            sp[L] = (r * d + Sup) * inv;      // H_j
-            sp[2 * L] = cc_;                  // c_{j+1}
-            sp[3 * L] = d;                    // d_{j+1}
-            sp[4 * L] = Fb;                   // beam at interface j+1
-            const double cn = r + t * t * cc_ * inv;
-            const double en = (A * (omr + t) + eps * (r * omr + t * t)) * inv;
-            const double dn = Sdn + t * (d + cc_ * Sup) * inv;
-            cc_ = cn;
-            eps = en;
-            d = dn;
-            Fb = Fb_lo;
+            sp[0] = rec.G;
+            sp[L] = rec.H;
+            sp[2 * L] = rec.c;
+            sp[3 * L] = rec.d;
+            sp[4 * L] = rec.Fb;
         }
         Bup = Blo;
     }
@@ -427,9 +156,7 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
     // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0, with F_dn_0 = c_0 F_up_0 + d_0
     double Fu = 0.0, Fd = 0.0, Fbi = 0.0;
     if (active) {
-        Fu = (Fboa + Fb + d) / eps;
-        Fd = cc_ * Fu + d;
-        Fbi = Fb;
+        lane_boa(st, Fboa, Fu, Fd, Fbi);
         if (fl) atomicOr(&s_flag[kloc], fl);
     }
 
@@ -441,8 +168,7 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
             if (active) {
                 if (i > 0) {
                     const double *sp = a.scratch + (long long)(i - 1) * 5 * L + gl;
-                    Fu = sp[0] * Fu + sp[L];
-                    Fd = sp[2 * L] * Fu + sp[3 * L];
+                    lane_up(sp[0], sp[L], sp[2 * L], sp[3 * L], Fu, Fd);
                     Fbi = sp[4 * L];
                 }
                 const long long k = ((long long)i * C + c) * NB + b;

@@ -1,0 +1,103 @@
+// rt_math.hpp -- small math kernels of the solve, host- and device-callable.
+//
+// exp_em1(x): e^x and e^x - 1 from one argument reduction (Cody-Waite
+// reduction x = k ln2 + r with |r| <= ln2/2, Taylor polynomial of e^r - 1,
+// scaling by 2^k; Tang, ACM TOMS 15 (1989) describes the same structure).
+// The expm1 value keeps full relative accuracy near x = 0 because the
+// polynomial carries e^r - 1 without its leading 1, and e^x - 1 is rebuilt
+// as 2^k (e^r - 1) + (2^k - 1), where 2^k - 1 is exact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace rtk {
+
+template <class R> struct ExpCfg;
+template <> struct ExpCfg<double> {
+    static constexpr int DEG = 12;   // |r|^13/13! < 2e-16 for |r| <= ln2/2
+    static constexpr double LN2_HI = 6.93147180369123816490e-01;  // 32 leading bits of ln 2
+    static constexpr double LN2_LO = 1.90821492927058770002e-10;  // ln 2 - LN2_HI
+    static constexpr double LOG2E = 1.44269504088896338700e+00;
+    static constexpr double XMAX = 709.0, XMIN = -745.0;
+};
+template <> struct ExpCfg<float> {
+    static constexpr int DEG = 7;    // |r|^8/8! < 2e-8
+    static constexpr float LN2_HI = 0.693145751953125f;          // 16 leading bits of ln 2
+    static constexpr float LN2_LO = 1.428606765330187045e-06f;
+    static constexpr float LOG2E = 1.44269504088896338700f;
+    static constexpr float XMAX = 88.0f, XMIN = -104.0f;
+};
+
+constexpr double inv_fact(int n)
+{
+    double f = 1.0;
+    for (int m = 2; m <= n; ++m) f *= m;
+    return 1.0 / f;
+}
+
+template <class R, int K, int DEG>
+__host__ __device__ __forceinline__ R taylor_em1_tail(R r)
+{
+    // 1/K! + r/(K+1)! + ... + r^(DEG-K)/DEG!, coefficients folded at compile time
+    constexpr double ck = inv_fact(K);
+    if constexpr (K == DEG) {
+        return R(ck);
+    } else {
+        return fma(taylor_em1_tail<R, K + 1, DEG>(r), r, R(ck));
+    }
+}
+
+template <class R>
+struct ExpEm1 {
+    R e;     // e^x
+    R em1;   // e^x - 1
+};
+
+template <class R>
+__host__ __device__ __forceinline__ ExpEm1<R> exp_em1(R x)
+{
+    using Cfg = ExpCfg<R>;
+    ExpEm1<R> out;
+    if (!(x > Cfg::XMIN)) {          // underflow (and -inf): e^x = 0
+        out.e = R(0);
+        out.em1 = R(-1);
+        return out;
+    }
+    if (x > Cfg::XMAX) x = Cfg::XMAX;
+    R k = rint(x * Cfg::LOG2E);
+    R r = fma(-k, R(Cfg::LN2_HI), x);
+    r = fma(-k, R(Cfg::LN2_LO), r);
+    // q = e^r - 1 = r (1 + r/2 + r^2/6 + ...)
+    R q = r * taylor_em1_tail<R, 1, Cfg::DEG>(r);
+    int ki = int(k);
+    out.e = ldexp(R(1) + q, ki);
+    out.em1 = ldexp(q, ki) + (ldexp(R(1), ki) - R(1));
+    return out;
+}
+
+// 1/x to about one ulp: hardware reciprocal refined by Newton steps.
+__host__ __device__ __forceinline__ double rcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+#else
+    return 1.0 / x;
+#endif
+}
+
+__host__ __device__ __forceinline__ float rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    float y = __builtin_amdgcn_rcpf(x);
+    return fma(y, fma(-x, y, 1.0f), y);
+#else
+    return 1.0f / x;
+#endif
+}
+
+}  // namespace rtk

@@ -1,0 +1,394 @@
+// rt_physics.hpp -- per-lane arithmetic of the improved two-stream solve.
+//
+// Host- and device-callable so the same code can be unit-tested on a CPU.
+// Paper: Deitrick et al., "The THOR+HELIOS general circulation model"
+// (arXiv 2203.02293): Section 2.2.1 (layer relations, beam, boundary
+// conditions, resonance guard), Section 2.2.4 (E fit), Appendix B
+// (coefficients and source terms).  The coefficient forms used here are the
+// paper's, rewritten without cancellation (see rt_kernels.hip).
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#include "rt_internal.hpp"
+#include "rt_math.hpp"
+
+namespace rtk {
+
+constexpr double kPI = 3.141592653589793238462643383279502884;
+constexpr double kH = 6.62607015e-34;   // SI 2019, exact
+constexpr double kC = 299792458.0;
+constexpr double kKB = 1.380649e-23;
+constexpr double kPref = 2.0 * kKB * kKB * kKB * kKB / (kH * kH * kH * kC * kC);
+constexpr double kPI4_15 = kPI * kPI * kPI * kPI / 15.0;
+
+enum : uint32_t {
+    F_GUARD = 1u, F_ECLAMP = 2u, F_ETAU = 4u, F_EDOMAIN = 8u, F_INVALID = 16u, F_NONFIN = 32u
+};
+
+// ---------------------------------------------------------------------------
+// Planck bin integrals.  With x = c2/(lambda T):
+//   B_b(T) = (2 k^4 T^4 / (h^3 c^2)) * int_{x_a}^{x_b} t^3/(e^t - 1) dt.
+// Small x: Q(x) = int_0^x = x^3/3 - x^4/8 + sum_k B_2k x^(2k+3)/((2k+3)(2k)!)
+// (Bernoulli series, converges for x < 2 pi).  Large x: P(x) = int_x^inf =
+// sum_n e^{-nx} (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4).  Series coefficients are
+// compile-time constants: B_2k/(2k)! = (-1)^{k+1} 2 zeta(2k)/(2 pi)^{2k}.
+// ---------------------------------------------------------------------------
+constexpr double zeta_even(int s)
+{
+    constexpr int M = 64;
+    double sum = 0.0;
+    for (int n = M - 1; n >= 1; --n) {
+        double inv = 1.0 / n, t = 1.0;
+        for (int i = 0; i < s; ++i) t *= inv;
+        sum += t;
+    }
+    double Mi = 1.0 / M, Ms = 1.0, ds = s;
+    for (int i = 0; i < s; ++i) Ms *= Mi;
+    double tail = Ms * M / (ds - 1.0) + 0.5 * Ms + ds * Ms * Mi / 12.0
+                - ds * (ds + 1) * (ds + 2) * Ms * Mi * Mi * Mi / 720.0
+                + ds * (ds + 1) * (ds + 2) * (ds + 3) * (ds + 4) * Ms * Mi * Mi * Mi * Mi * Mi
+                      / 30240.0;
+    return sum + tail;
+}
+
+constexpr double bern_coef(int k)   // B_2k / ((2k+3) (2k)!)
+{
+    double tp = 1.0;
+    for (int i = 0; i < 2 * k; ++i) tp *= 2.0 * kPI;
+    double v = 2.0 * zeta_even(2 * k) / (tp * (2.0 * k + 3.0));
+    return (k % 2 == 1) ? v : -v;
+}
+
+template <class R> struct PCfg;
+template <> struct PCfg<double> {
+    static constexpr double XS = 3.0;   // series switch
+    static constexpr int NQ = 28;       // Bernoulli terms: (3/2pi)^56 < 1e-18
+    static constexpr int NP = 13;       // exponential terms: e^-39 < 1e-16
+    static constexpr double TAIL = 1e-17;
+};
+template <> struct PCfg<float> {
+    static constexpr float XS = 2.5f;
+    static constexpr int NQ = 10;
+    static constexpr int NP = 8;
+    static constexpr float TAIL = 1e-8f;
+};
+
+template <class R, int K, int NQ>
+__host__ __device__ __forceinline__ R bern_horner(R x2)
+{
+    constexpr double cK = bern_coef(K);   // forced compile-time evaluation
+    if constexpr (K == NQ) {
+        return R(cK);
+    } else {
+        return fma(bern_horner<R, K + 1, NQ>(x2), x2, R(cK));
+    }
+}
+
+constexpr double inv_factorial(int n)
+{
+    double f = 1.0;
+    for (int m = 2; m <= n; ++m) f *= m;
+    return 1.0 / f;
+}
+
+template <class R, int K, int N>
+__host__ __device__ __forceinline__ R sinhc_horner(R u2)
+{
+    // sum_{k=K..N} u^{2(k-K)} / (2k+1)!, Horner in u^2, coefficients folded
+    constexpr double ck = inv_factorial(2 * K + 1);
+    if constexpr (K == N) {
+        return R(ck);
+    } else {
+        return fma(sinhc_horner<R, K + 1, N>(u2), u2, R(ck));
+    }
+}
+
+// +Q(x) for x <= XS, -P(x) otherwise: the sign bit records which tail it is.
+template <class R>
+__host__ __device__ __forceinline__ R planck_edge(R x)
+{
+    using Cfg = PCfg<R>;
+    if (x <= Cfg::XS) {
+        R x2 = x * x;
+        R poly = bern_horner<R, 1, Cfg::NQ>(x2);
+        return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + poly * x2);
+    }
+    // term n+1 over term 1 is about e^{-nx}: stop once that is below the last bit
+    R y = exp_em1(-x).e, yn = y, sum = R(0);
+#pragma unroll
+    for (int n = 1; n <= Cfg::NP; ++n) {
+        const R in = R(1) / R(n);
+        R poly = ((x * in + R(3) * in * in) * x + R(6) * in * in * in) * x
+               + R(6) * in * in * in * in;
+        sum = fma(yn, poly, sum);
+        yn *= y;
+        if (yn < Cfg::TAIL * y) break;   // next term relative to the first
+    }
+    return -sum;
+}
+
+// int_{x_a}^{x_b} t^3/(e^t-1) dt from the two edge values (x_b > x_a):
+// same tail on both sides: difference; straddling XS: pi^4/15 - P(x_b) - Q(x_a).
+template <class R>
+__host__ __device__ __forceinline__ R planck_combine(R vb, R va)
+{
+    R d = vb - va;
+    if (signbit(vb) && !signbit(va)) d += R(kPI4_15);
+    return d;
+}
+
+// int_{xa}^{xb} t^3/(e^t-1) dt by 3-point Gauss-Legendre: used for narrow
+// bins in FP32, where the difference of two nearly equal edge integrals would
+// lose digits.  The rule's relative error is below (xb-xa)^6 * 5e-7.
+template <class R>
+__host__ __device__ __forceinline__ R planck_gl3(R xa, R xb)
+{
+    const R h = R(0.5) * (xb - xa), m = R(0.5) * (xb + xa);
+    const R d = R(0.7745966692414834) * h;   // sqrt(3/5) h
+    R acc = R(0);
+    const R xs[3] = {m - d, m, m + d};
+    const R ws[3] = {R(5.0 / 9.0), R(8.0 / 9.0), R(5.0 / 9.0)};
+    for (int i = 0; i < 3; ++i) {
+        ExpEm1<R> e = exp_em1(-xs[i]);            // t^3 e^-t / (1 - e^-t)
+        acc += ws[i] * xs[i] * xs[i] * xs[i] * e.e * rcp(-e.em1);
+    }
+    return h * acc;
+}
+
+// ---------------------------------------------------------------------------
+// Predicates in FP64, rounded exactly as the printed formulas read left to
+// right (no contraction), so that both precisions take the paper's branch
+// decisions on the same values.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ double efit_exact(double w0, double g0, const Opts &o, uint32_t &fl)
+{
+#pragma clang fp contract(off)
+    if (!o.improved || !(w0 > 0.1)) return 1.0;
+    double E = 1.225 - 0.1582 * g0 - 0.1777 * w0 - 0.07465 * g0 * g0
+             + 0.2351 * w0 * g0 - 0.05582 * w0 * w0;
+    if (o.e_clamp) {
+        if (E < 1.0) {
+            E = 1.0;
+            fl |= F_ECLAMP;
+        }
+    } else if (E <= w0) {
+        fl |= F_EDOMAIN;
+    }
+    return E;
+}
+
+__host__ __device__ __forceinline__ double resonance_D(double E, double w0, double g0, double mu)
+{
+#pragma clang fp contract(off)
+    double ms = -mu;
+    return 4.0 * E * ms * ms * (E - w0) * (1.0 - w0 * g0) - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// helper functions of u
+// ---------------------------------------------------------------------------
+template <class R>
+__host__ __device__ __forceinline__ R phi1(R x)   // (1 - e^-x)/x, x >= 0
+{
+    return (x > R(0)) ? -exp_em1(-x).em1 * rcp(x) : R(1);
+}
+
+template <class R> struct ShCfg;
+template <> struct ShCfg<double> { static constexpr int N = 12; };
+template <> struct ShCfg<float> { static constexpr int N = 7; };
+
+// e^-u (sinh u - u)/u^2, u >= 0, given T = e^-u
+template <class R>
+__host__ __device__ __forceinline__ R hfun(R u, R T)
+{
+    if (u < R(2)) {
+        // (sinh u - u)/u^2 = u sum_{k>=1} u^{2(k-1)} / (2k+1)!
+        return T * u * sinhc_horner<R, 1, ShCfg<R>::N>(u * u);
+    }
+    return (R(0.5) * (R(1) - T * T) - u * T) / (u * u);
+}
+
+template <class R>
+struct Layer {
+    R t, r, omr, A, Sup, Sdn;
+};
+
+// Coefficients and normalised sources of one layer (see the file header).
+// Differences near 1 (1 - w0, E - w0, 1 - w0 g0) arrive already formed in
+// FP64 by the caller: in FP32 they would lose up to ~2 digits for cloud layers.
+template <class R>
+__host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R omw, R Ew, R om,
+                                                     bool day, R mu, R inv_mu, R Dres,
+                                                     bool guard, R f, R beta, R Blo, R Bup,
+                                                     bool iso, R inv_eps2, Layer<R> &L)
+{
+    const R one = R(1), half = R(0.5);
+    R kap = R(2) * E * om;
+    R ik = rcp(kap);
+    R s = sqrt(Ew * rcp(E * om));
+    R lam = kap * s;
+    R u = lam * dtau;
+    ExpEm1<R> ex = exp_em1(-u);
+    R Tr = ex.e, omT = -ex.em1;
+    R zp = half * (one + s), zm = half * (one - s);
+    R p = (s > R(0)) ? omT * rcp(s) : kap * dtau;
+    R q = p * (one + Tr);
+    R den = fma(zm * zm, q, one);
+    R id = rcp(den);
+    R t = Tr * id;
+    R r = zp * zm * q * id;
+    R A = omT * (zp - zm * Tr) * id;
+    L.t = t;
+    L.r = r;
+    L.A = A;
+    L.omr = (zp + zm * Tr * Tr) * id;
+    R Pi = (E == one) ? R(kPI) : R(kPI) * omw * rcp(Ew);
+    R Sup, Sdn;
+    if (iso) {
+        R Bm = half * (Blo + Bup);
+        Sup = Pi * A * Bm;
+        Sdn = Sup;
+    } else {
+        R ph = (u > R(0)) ? omT * rcp(u) : one;
+        R Gd = u * (hfun(u, Tr) + half * s * ph * ph) * id;
+        R dB = Blo - Bup;
+        Sup = Pi * (A * Bup + dB * Gd);
+        Sdn = Pi * (A * Blo - dB * Gd);
+    }
+    if (day) {
+        R c1 = w0 * (kap + g0 * inv_eps2);
+        R Qc = w0 * g0 * inv_eps2 * ik;
+        R lm = lam * mu;
+        R sb_up, sb_dn;
+        if (guard || fabs(lm - one) >= R(0.25)) {
+            R Dd = guard ? R(-2) * mu : Dres;
+            R P = c1 * rcp(Dd);
+            R Gp = half * (P * (ik - mu) + Qc);
+            R Gm = -half * (P * (ik + mu) + Qc);
+            sb_up = f * (r * Gm - Gp * (one - t * beta));
+            sb_dn = f * (r * beta * Gp - Gm * (beta - t));
+        } else {
+            // resonance-regularised: X, Yh = Y (a - lambda) are finite at mu lambda = 1
+            R a = inv_mu;
+            R i1s = rcp(one + s);
+            R X = (Qc - c1 * ik * rcp(one + lm)) * i1s;
+            R Yh = (Qc * (a - lam) - c1 * a * ik) * i1s;
+            R dq = (a >= lam) ? Tr * phi1((a - lam) * dtau) : beta * phi1((lam - a) * dtau);
+            R Z = Yh * dq * dtau;
+            R rho = zm * rcp(zp);
+            R iom = (zp * zp) * rcp(s * den);       // 1 / (1 - rho^2 T^2)
+            R obt = -exp_em1(-(a + lam) * dtau).em1; // 1 - beta T
+            sb_up = f * (rho * Tr * Z - X * obt) * iom;
+            sb_dn = f * (rho * Tr * X * obt - Z) * iom;
+        }
+        Sup += sb_up;
+        Sdn += sb_dn;
+    }
+    L.Sup = Sup;
+    L.Sdn = Sdn;
+}
+
+// ---------------------------------------------------------------------------
+// One lane's sweep: state carried from the TOA down, one layer per call.
+// ---------------------------------------------------------------------------
+struct LaneState {
+    double c, eps, d;   // F_dn_i = c F_up_i + d, eps = 1 - c (no subtraction)
+    double Fb, tau;     // direct beam and optical depth at the current interface
+};
+
+// What the back-substitution needs of layer j: F_up_{j+1} = G F_up_j + H,
+// F_dn_{j+1} = c F_up_{j+1} + d, beam at interface j+1.
+struct BackRec {
+    double G, H, c, d, Fb;
+};
+
+__host__ __device__ __forceinline__ LaneState lane_top(bool day, double mu, double Fstar_b,
+                                                       double F_toa)
+{
+    LaneState s;
+    s.c = 0.0;          // nothing above the TOA reflects
+    s.eps = 1.0;
+    s.d = F_toa;        // F_dn_N = F_TOA (Fig. 5 caption)
+    s.Fb = day ? mu * Fstar_b : 0.0;
+    s.tau = 0.0;
+    return s;
+}
+
+// Layer j between interfaces j and j+1, given B at both ends (Section 2.2.1,
+// Appendix B), then one step of Thomas forward elimination in FP64 (Section 2.2.2).
+template <bool MIXED, class R>
+__host__ __device__ __forceinline__ BackRec lane_layer(LaneState &st, double dt, double w,
+                                                       double g, double Tl, bool day, double mu,
+                                                       double inv_mu, double Fstar_b, R Blo,
+                                                       R Bup, const Opts &o, double inv_eps2,
+                                                       uint32_t &fl)
+{
+    if (!(dt >= 0.0) || !isfinite(dt) || !(w >= 0.0 && w <= 1.0) || !(g > -1.0 && g < 1.0) ||
+        !(Tl > 0.0) || !isfinite(Tl))
+        fl |= F_INVALID;
+    const double E = efit_exact(w, g, o, fl);
+    bool guard = false;
+    double D = 0.0;
+    if (day) {
+        D = resonance_D(E, w, g, mu);
+        guard = fabs(D) < o.g_guard;
+        if (guard) fl |= F_GUARD;
+    }
+    const bool iso = !o.noniso || dt < o.e_tau;
+    if (o.noniso && dt < o.e_tau) fl |= F_ETAU;
+
+    double Fb_lo = 0.0;
+    R beta = R(0);
+    if (day) {
+        if constexpr (MIXED) {
+            // optical depth summed in FP64; exponentials in FP32
+            st.tau += dt;
+            Fb_lo = mu * Fstar_b * double(exp_em1(float(-st.tau * inv_mu)).e);
+            beta = exp_em1(float(-dt * inv_mu)).e;
+        } else {
+            beta = exp_em1(-dt * inv_mu).e;
+            Fb_lo = st.Fb * beta;
+        }
+    }
+    Layer<R> Ly;
+    layer_terms<R>(R(dt), R(w), R(g), R(E), R(1.0 - w), R(E - w), R(1.0 - w * g), day, R(mu),
+                   R(inv_mu), R(D), guard, R(st.Fb), beta, Blo, Bup, iso, R(inv_eps2), Ly);
+    const double t = Ly.t, r = Ly.r, omr = Ly.omr, A = Ly.A;
+    const double Sup = Ly.Sup, Sdn = Ly.Sdn;
+    const double inv = rcp(omr + r * st.eps);   // 1 / (1 - r c_{j+1})
+    BackRec rec;
+    rec.G = t * inv;
+    rec.H = (r * st.d + Sup) * inv;
+    rec.c = st.c;
+    rec.d = st.d;
+    rec.Fb = st.Fb;
+    const double cn = r + t * t * st.c * inv;
+    const double en = (A * (omr + t) + st.eps * (r * omr + t * t)) * inv;
+    const double dn = Sdn + t * (st.d + st.c * Sup) * inv;
+    st.c = cn;
+    st.eps = en;
+    st.d = dn;
+    st.Fb = Fb_lo;
+    return rec;
+}
+
+// BOA condition F_up_0 - F_dn_0 = F_BOA + F_beam_0 closes the elimination.
+__host__ __device__ __forceinline__ void lane_boa(const LaneState &st, double F_boa, double &Fu,
+                                                  double &Fd, double &Fb0)
+{
+    Fu = (F_boa + st.Fb + st.d) / st.eps;
+    Fd = st.c * Fu + st.d;
+    Fb0 = st.Fb;
+}
+
+// One back-substitution step from interface j to j+1.
+__host__ __device__ __forceinline__ void lane_up(double G, double H, double c, double d,
+                                                 double &Fu, double &Fd)
+{
+    Fu = G * Fu + H;
+    Fd = c * Fu + d;
+}
+
+}  // namespace rtk

@@ -35,7 +35,7 @@ def subset(work: dict, cols) -> dict:
 
 
 def errors(out: dict, ref: dict, p_iface: np.ndarray, floor: float = 1e-3,
-           cols=None, gravity: float = GRAV) -> dict:
+           cols=None, gravity: float = GRAV, floor_bin: float | None = None) -> dict:
     """Scaled errors of the bin-summed outputs (and per-bin ones if present)."""
     def host(x):
         return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
@@ -55,8 +55,9 @@ def errors(out: dict, ref: dict, p_iface: np.ndarray, floor: float = 1e-3,
     if "F_up_bin" in o and "F_up_bin" in ref:
         Sb = (ref["F_up_bin"] + ref["F_dn_bin"] + ref["F_beam_bin"]).max(axis=0)
         Sb = np.maximum(Sb, 1e-300)
+        fb = floor if floor_bin is None else floor_bin
         for k in ("F_up_bin", "F_dn_bin"):
-            e[k] = (np.abs(o[k] - ref[k]) / np.maximum(np.abs(ref[k]), floor * Sb)).max()
+            e[k] = (np.abs(o[k] - ref[k]) / np.maximum(np.abs(ref[k]), fb * Sb)).max()
     if "F_up_toa_bin" in o and "F_up_toa_bin" in ref:
         Sb = (ref["F_up"] + ref["F_dn"] + ref["F_beam"]).max(axis=0)[:, None]
         e["F_up_toa_bin"] = (np.abs(o["F_up_toa_bin"] - ref["F_up_toa_bin"]) /
@@ -64,8 +65,8 @@ def errors(out: dict, ref: dict, p_iface: np.ndarray, floor: float = 1e-3,
     return e
 
 
-def assert_close(out, ref, p_iface, tol, floor=1e-3, cols=None, keys=None):
-    e = errors(out, ref, p_iface, floor=floor, cols=cols)
+def assert_close(out, ref, p_iface, tol, floor=1e-3, cols=None, keys=None, floor_bin=None):
+    e = errors(out, ref, p_iface, floor=floor, cols=cols, floor_bin=floor_bin)
     bad = {k: v for k, v in e.items() if (keys is None or k in keys) and not (v <= tol)}
     assert not bad, f"errors above {tol}: {bad} (all: {e})"
     return e

@@ -17,11 +17,14 @@ from tests.parity import assert_close, errors, subset
 pytestmark = pytest.mark.gpu
 
 FP64_TOL, MIXED_TOL = 1e-10, 1e-5
-# floor of the scale for interface fluxes (see tests/parity.py): FP64 resolves
-# 1e-13 S absolute; FP32 coefficients leave ~1e-8 S absolute noise, so the
-# mixed path is held to 1e-5 relative down to 1e-2 S (F_net and heating are
-# held to 1e-5 S in both paths).
+# floor of the scale for interface fluxes (see tests/parity.py).  FP64 leaves
+# ~1e-14 S absolute, so it is held to 1e-10 relative down to 1e-3 S.  The
+# mixed path is held to its stated target, 1e-5 S on net flux and heating,
+# to 1e-5 relative down to 1e-2 S on bin-summed fluxes, and to 1e-5 S_cb on
+# per-bin fluxes: FP32 coefficient rounding (6e-8 per term, accumulated over
+# the layers) leaves ~1e-7 S_cb absolute in small deep per-bin fluxes.
 FLOOR = {0: 1e-3, 1: 1e-2}
+FLOOR_BIN = {0: 1e-3, 1: 1.0}
 
 
 @pytest.fixture(scope="module")
@@ -79,7 +82,7 @@ def test_small_fp64_and_mixed(rt, torch, name, shape, mode):
     ref = O.solve(w, opts, per_bin=True, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
         out = gpu_solve(rt, torch, w, prec, per_bin=True, opts=opts)
-        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec])
+        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
@@ -91,7 +94,7 @@ def test_cfg0_full(rt, torch, cfg):
     ref = O.solve(w, per_bin=True, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
         out = gpu_solve(rt, torch, w, prec, per_bin=True)
-        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec])
+        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
@@ -107,7 +110,7 @@ def test_cfg1_sampled(rt, torch):
     ref = O.solve(ws, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
         out = gpu_solve(rt, torch, w, prec)
-        e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec], cols=cols)
+        e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec], cols=cols)
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
 
@@ -155,7 +158,7 @@ def test_edge_cases(rt, torch):
     assert ref["flags"][5] & O.F_ECLAMP and ref["flags"][1] & O.F_ETAU
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
         out = gpu_solve(rt, torch, w, prec, per_bin=True)
-        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec])
+        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
