@@ -32,6 +32,7 @@
 #include "rt_physics.hpp"
 
 #include <math.h>
+#include <algorithm>
 #include <type_traits>
 
 namespace rtk {
@@ -40,9 +41,11 @@ namespace {
 // LDS chunk of interfaces reduced at once over bins
 __host__ __device__ constexpr int lds_budget() { return 60 * 1024; }
 
+constexpr int PC = 8;   // levels whose Planck edges are computed per barrier
+
 __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 {
-    int fixed = K * (NB + 1) * 8 + K * 9 * 8 + K * 4 + 64;
+    int fixed = K * 9 * 8 + K * 4 + 64;
     int ch = (lds_budget() - fixed) / (3 * threads * 8);
     if (ch > 8) ch = 8;
     if (ch < 1) ch = 1;
@@ -65,48 +68,51 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
     const bool active = (kloc < K) && (c < C);
     const long long gl = (long long)blockIdx.x * bd + tid;
     const int CH = chunk_for(bd, K, NB);
-    const int nedge = K * (NB + 1);
 
-    R *s_edge = reinterpret_cast<R *>(smem);                  // [K][NB+1]
-    double *s_red = smem + nedge;                              // [3][CH][bd]
-    double *s_fnet = s_red + 3 * CH * bd;                      // [K][CH+1]
+    // LDS: the forward sweep's Planck edge values and the back-substitution's
+    // bin-sum buffers are live at different times and share the same bytes.
+    R *s_pl = reinterpret_cast<R *>(smem);                     // [PC][K][NB+1]
+    double *s_red = smem;                                      // [3][CH][bd]
+    const int nslot = PC * K * (NB + 1);
+    const int front = max(3 * CH * bd, nslot);
+    double *s_fnet = smem + front;                             // [K][CH+1]
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(s_fnet + K * (CH + 1));  // [K]
 
     for (int kk = tid; kk < K; kk += bd) s_flag[kk] = 0u;
     uint32_t fl = 0u;
 
-    // Planck radiance of this lane's bin at one level; all threads take part.
-    auto planck_level = [&](const double *Tsrc, long long off) -> R {
+    // Edge integrals of PC levels (rows q = 0..n-1 of level pointer src[q]) into LDS,
+    // edge-major so that a wavefront's lanes mostly sit in one series regime.
+    auto edge_chunk = [&](const double *Tsrc, long long off0, long long stride, int n) {
         __syncthreads();
-        // edge-major: a wavefront takes one edge of many columns, so its lanes
-        // mostly sit in the same series regime
-        for (int e = tid; e < nedge; e += bd) {
-            int ee = e / K, kk = e - ee * K;
-            int cc = blockIdx.x * K + kk;
+        const int tot = n * K * (NB + 1);
+        for (int e = tid; e < tot; e += bd) {
+            const int q = e / (K * (NB + 1)), rem = e - q * K * (NB + 1);
+            const int ee = rem / K, kk = rem - ee * K;
+            const int cc = blockIdx.x * K + kk;
             R v = R(0);
             if (cc < C) {
-                double T = Tsrc[off + cc];
+                const double T = Tsrc[off0 - q * stride + cc];
                 R x;
-                if constexpr (MIXED) x = a.c2_over_lam_f[ee] / float(T);
+                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(T));
                 else x = a.c2_over_lam[ee] / T;
                 v = planck_edge<R>(x);
             }
-            s_edge[kk * (NB + 1) + ee] = v;
+            s_pl[(q * K + kk) * (NB + 1) + ee] = v;
         }
         __syncthreads();
-        R B = R(0);
-        if (active) {
-            R T = R(Tsrc[off + c]);
-            R T2 = T * T;
-            R I = planck_combine<R>(s_edge[kloc * (NB + 1) + b], s_edge[kloc * (NB + 1) + b + 1]);
-            if constexpr (MIXED) {
-                const R iT = rcp(T);
-                const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
-                if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
-            }
-            B = R(kPref) * T2 * T2 * I;
+    };
+    // This lane's bin radiance from row q of the chunk, at temperature T.
+    auto lane_B = [&](int q, double Td) -> R {
+        const R T = R(Td), T2 = T * T;
+        const R *row = s_pl + (q * K + kloc) * (NB + 1);
+        R I = planck_combine<R>(row[b], row[b + 1]);
+        if constexpr (MIXED) {
+            const R iT = rcp(T);
+            const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
+            if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
         }
-        return B;
+        return R(kPref) * T2 * T2 * I;
     };
 
     double mu = 0.0;
@@ -117,13 +123,11 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
         if (!isfinite(mu)) fl |= F_INVALID;
         double ti = a.Tint[c];
         if (!(ti >= 0.0) || !isfinite(ti)) fl |= F_INVALID;
-    }
-    const double Fboa = double(kPI) * double(planck_level(a.Tint, 0));
-    R Bup = planck_level(a.T, (long long)N * C);
-    if (active) {
         double T = a.T[(long long)N * C + c];
         if (!(T > 0.0) || !isfinite(T)) fl |= F_INVALID;
     }
+    edge_chunk(a.Tint, 0, 0, 1);
+    const double Fboa = active ? double(kPI) * double(lane_B(0, a.Tint[c])) : 0.0;
 
     LaneState st;
     double Fstar_b = 0.0;
@@ -135,23 +139,52 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
     const double inv_eps2 = 1.0 / a.o.eps2;
     const long long LB = (long long)C * NB;
     const long long L = a.L;
+    const long long lane_off = (long long)c * NB + b;
 
-    for (int j = N - 1; j >= 0; --j) {
-        R Blo = planck_level(a.T, (long long)j * C);
-        if (active) {
-            const long long idx = (long long)j * LB + (long long)c * NB + b;
-            const BackRec rec = lane_layer<MIXED>(st, a.dtau[idx], a.w0[idx], a.g0[idx],
-                                                  a.T[(long long)j * C + c], day, mu, inv_mu,
-                                                  Fstar_b, Blo, Bup, a.o, inv_eps2, fl);
-            double *sp = a.scratch + (long long)j * 5 * L + gl;
-            sp[0] = rec.G;
-            sp[L] = rec.H;
-            sp[2 * L] = rec.c;
-            sp[3 * L] = rec.d;
-            sp[4 * L] = rec.Fb;
-        }
-        Bup = Blo;
+    // inputs of the next layer, loaded one layer ahead of their use
+    double nx_dt = 0.0, nx_w = 0.0, nx_g = 0.0, nx_T = 1.0;
+    if (active) {
+        const long long idx = (long long)(N - 1) * LB + lane_off;
+        nx_dt = a.dtau[idx];
+        nx_w = a.w0[idx];
+        nx_g = a.g0[idx];
+        nx_T = a.T[(long long)(N - 1) * C + c];
     }
+    R Bup = R(0);
+    // levels N, N-1, ..., 0 in chunks of PC; level i closes layer i (between i and i+1)
+    for (int s = N; s >= 0; s -= PC) {
+        const int n = min(PC, s + 1);
+        edge_chunk(a.T, (long long)s * C, C, n);
+        for (int q = 0; q < n; ++q) {
+            const int i = s - q;
+            R B = R(0);
+            if (active) B = lane_B(q, a.T[(long long)i * C + c]);
+            if (i == N) {
+                Bup = B;
+                continue;
+            }
+            if (active) {
+                const double dt = nx_dt, w = nx_w, g = nx_g, Tl = nx_T;
+                if (i > 0) {
+                    const long long idx = (long long)(i - 1) * LB + lane_off;
+                    nx_dt = a.dtau[idx];
+                    nx_w = a.w0[idx];
+                    nx_g = a.g0[idx];
+                    nx_T = a.T[(long long)(i - 1) * C + c];
+                }
+                const BackRec rec = lane_layer<MIXED>(st, dt, w, g, Tl, day, mu, inv_mu, Fstar_b,
+                                                      B, Bup, a.o, inv_eps2, fl);
+                double *sp = a.scratch + (long long)i * 5 * L + gl;
+                sp[0] = rec.G;
+                sp[L] = rec.H;
+                sp[2 * L] = rec.c;
+                sp[3 * L] = rec.d;
+                sp[4 * L] = rec.Fb;
+            }
+            Bup = B;
+        }
+    }
+    __syncthreads();   // the LDS edge rows are reused by the bin sums below
 
     // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0, with F_dn_0 = c_0 F_up_0 + d_0
     double Fu = 0.0, Fd = 0.0, Fbi = 0.0;
@@ -160,16 +193,26 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
         if (fl) atomicOr(&s_flag[kloc], fl);
     }
 
-    // back-substitution upward, bin sums in chunks of CH interfaces
+    // back-substitution upward, bin sums in chunks of CH interfaces; the
+    // record of the next layer is loaded one step ahead of its use
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, r4 = 0.0;
+    if (active) {
+        const double *sp = a.scratch + gl;
+        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L]; r4 = sp[4 * L];
+    }
     for (int i0 = 0; i0 <= N; i0 += CH) {
         const int nch = min(CH, N + 1 - i0);
         for (int ii = 0; ii < nch; ++ii) {
             const int i = i0 + ii;
             if (active) {
                 if (i > 0) {
-                    const double *sp = a.scratch + (long long)(i - 1) * 5 * L + gl;
-                    lane_up(sp[0], sp[L], sp[2 * L], sp[3 * L], Fu, Fd);
-                    Fbi = sp[4 * L];
+                    const double G = r0, H = r1, cj = r2, dj = r3;
+                    Fbi = r4;
+                    if (i < N) {
+                        const double *sp = a.scratch + (long long)i * 5 * L + gl;
+                        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L]; r4 = sp[4 * L];
+                    }
+                    lane_up(G, H, cj, dj, Fu, Fd);
                 }
                 const long long k = ((long long)i * C + c) * NB + b;
                 if (a.F_up_bin) a.F_up_bin[k] = Fu;
@@ -242,8 +285,8 @@ Geometry solve_geometry(int C, int NB)
     g.blocks = (C + g.K - 1) / g.K;
     g.lanes = (long long)g.blocks * g.threads;
     const int ch = chunk_for(g.threads, g.K, NB);
-    g.lds = (size_t)g.K * (NB + 1) * 8 + (size_t)3 * ch * g.threads * 8
-          + (size_t)g.K * (ch + 1) * 8 + (size_t)g.K * 4;
+    const size_t front = std::max((size_t)3 * ch * g.threads, (size_t)PC * g.K * (NB + 1));
+    g.lds = front * 8 + (size_t)g.K * (ch + 1) * 8 + (size_t)g.K * 4;
     return g;
 }
 

@@ -67,12 +67,14 @@ template <> struct PCfg<double> {
     static constexpr int NQ = 28;       // Bernoulli terms: (3/2pi)^56 < 1e-18
     static constexpr int NP = 13;       // exponential terms: e^-39 < 1e-16
     static constexpr double TAIL = 1e-17;
+    static constexpr double XCUT = 745.0;
 };
 template <> struct PCfg<float> {
     static constexpr float XS = 2.5f;
     static constexpr int NQ = 10;
     static constexpr int NP = 8;
     static constexpr float TAIL = 1e-8f;
+    static constexpr float XCUT = 104.0f;
 };
 
 template <class R, int K, int NQ>
@@ -105,23 +107,54 @@ __host__ __device__ __forceinline__ R sinhc_horner(R u2)
     }
 }
 
+// Series coefficient tables (compile-time values, read with uniform loads):
+// c_k = B_2k/((2k+3)(2k)!) for the small-x series, 1/n for the large-x series.
+struct SeriesTables {
+    double bern[28];
+    double inv_n[14];
+};
+
+constexpr SeriesTables make_series_tables()
+{
+    SeriesTables t{};
+    for (int k = 0; k < 28; ++k) t.bern[k] = bern_coef(k + 1);
+    for (int n = 0; n < 14; ++n) t.inv_n[n] = 1.0 / (n + 1);
+    return t;
+}
+
+__device__ constexpr SeriesTables kSeries = make_series_tables();
+constexpr SeriesTables kSeriesHost = make_series_tables();
+
+__host__ __device__ __forceinline__ const SeriesTables &series_tables()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return kSeries;
+#else
+    return kSeriesHost;
+#endif
+}
+
 // +Q(x) for x <= XS, -P(x) otherwise: the sign bit records which tail it is.
 template <class R>
 __host__ __device__ __forceinline__ R planck_edge(R x)
 {
     using Cfg = PCfg<R>;
+    const SeriesTables &tb = series_tables();
     if (x <= Cfg::XS) {
-        R x2 = x * x;
-        R poly = bern_horner<R, 1, Cfg::NQ>(x2);
+        const R x2 = x * x;
+        R poly = R(tb.bern[Cfg::NQ - 1]);
+#pragma unroll 4
+        for (int k = Cfg::NQ - 2; k >= 0; --k) poly = fma(poly, x2, R(tb.bern[k]));
         return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + poly * x2);
     }
+    if (!(x < Cfg::XCUT)) return R(-0.0);   // e^{-x} underflows (includes T = 0)
     // term n+1 over term 1 is about e^{-nx}: stop once that is below the last bit
-    R y = exp_em1(-x).e, yn = y, sum = R(0);
-#pragma unroll
-    for (int n = 1; n <= Cfg::NP; ++n) {
-        const R in = R(1) / R(n);
-        R poly = ((x * in + R(3) * in * in) * x + R(6) * in * in * in) * x
-               + R(6) * in * in * in * in;
+    const R y = exp_em1(-x).e;
+    R yn = y, sum = R(0);
+    for (int n = 0; n < Cfg::NP; ++n) {
+        const R t = R(tb.inv_n[n]);
+        // (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4) = t (x^3 + t (3x^2 + t (6x + 6t)))
+        const R poly = t * fma(t, fma(t, R(6) * (x + t), R(3) * x * x), x * x * x);
         sum = fma(yn, poly, sum);
         yn *= y;
         if (yn < Cfg::TAIL * y) break;   // next term relative to the first

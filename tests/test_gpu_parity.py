@@ -181,7 +181,8 @@ def test_strict_mode_flags_edomain(rt, torch):
 def test_conservative_scattering_w0_one(rt, torch):
     """w0 = 1 exactly (regular mode), no thermal emission: the oracle's printed
     form is 0/0 there, so the GPU is checked against energy conservation
-    (zero net flux at every interface) and against the oracle at w0 = 1 - 1e-12."""
+    (zero net flux at every interface) and against the oracle at w0 = 1 - 1e-15
+    (fluxes move by O((1 - w0) tau^2) between the two)."""
     w = small(C=4, N=8, NB=3, seed=41, cloud="none")
     w["w0"] = np.ones_like(w["w0"])
     w["g0"] = np.full_like(w["g0"], 0.4)
@@ -193,7 +194,7 @@ def test_conservative_scattering_w0_one(rt, torch):
     gross = (out["F_up"] + out["F_dn"] + out["F_beam"]).max(axis=0)
     assert np.all(np.abs(out["F_net"]) <= 1e-12 * gross)
     w2 = dict(w)
-    w2["w0"] = np.full_like(w["w0"], 1.0 - 1e-12)
+    w2["w0"] = np.full_like(w["w0"], 1.0 - 1e-15)
     ref = O.solve(w2, opts, extended=True)
     assert_close(out, ref, w["p_iface"], 1e-9, keys=("F_up", "F_dn", "F_beam"))
 
