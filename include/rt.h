@@ -153,6 +153,13 @@ rt_status rt_poll(rt_handle *h, uint64_t ticket);
 /* Blocking variant of rt_poll. */
 rt_status rt_wait(rt_handle *h, uint64_t ticket);
 
+/*
+ * Device bytes of library-owned work buffer one solve of this shape needs
+ * (what the serving path reserves from its budget per admitted request);
+ * -1 on bad arguments.
+ */
+int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers);
+
 /* Latest error message of the handle (never NULL; "" if none). */
 const char *rt_last_error(const rt_handle *h);
 

@@ -154,6 +154,12 @@ extern "C" const char *rt_status_string(rt_status s)
     }
 }
 
+extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers)
+{
+    if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
+    return (int64_t)rtk::solve_scratch_bytes(n_cols, n_layers, h->NB);
+}
+
 extern "C" const char *rt_last_error(const rt_handle *h)
 {
     return h ? h->err.c_str() : "null handle";

@@ -21,7 +21,7 @@ FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1,
 
 #: every symbol include/rt.h declares
 SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes", "rt_submit",
-           "rt_poll", "rt_wait", "rt_last_error", "rt_status_string")
+           "rt_poll", "rt_wait", "rt_work_bytes", "rt_last_error", "rt_status_string")
 
 
 class RtConfig(ct.Structure):
@@ -73,6 +73,8 @@ def lib() -> ct.CDLL:
         L.rt_poll.restype = ct.c_int32
         L.rt_wait.argtypes = [ct.c_void_p, ct.c_uint64]
         L.rt_wait.restype = ct.c_int32
+        L.rt_work_bytes.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32]
+        L.rt_work_bytes.restype = ct.c_int64
         L.rt_last_error.argtypes = [ct.c_void_p]
         L.rt_last_error.restype = ct.c_char_p
         L.rt_status_string.argtypes = [ct.c_int32]
@@ -98,6 +100,10 @@ def rt_create(cfg: RtConfig) -> int:
 
 def rt_destroy(h: int) -> int:
     return lib().rt_destroy(h)
+
+
+def rt_work_bytes(h: int, n_cols: int, n_layers: int) -> int:
+    return lib().rt_work_bytes(h, n_cols, n_layers)
 
 
 def rt_last_error(h: int) -> str:
@@ -219,6 +225,9 @@ class Solver:
 
     def wait(self, ticket: int) -> int:
         return rt_wait(self.h, ticket)
+
+    def work_bytes(self, n_cols: int, n_layers: int) -> int:
+        return rt_work_bytes(self.h, n_cols, n_layers)
 
 
 def to_device(work: dict, device: int = 0) -> dict:

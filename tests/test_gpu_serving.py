@@ -1,0 +1,129 @@
+"""Serving path (rt_submit / rt_poll / rt_wait) on the GPU.
+
+Each request's result must be the same whether it runs alone through
+rt_solve_fluxes or in a mix of uneven requests that overlap on the device
+(bitwise: same kernel, same launch geometry, fixed-order bin sums).
+Admission under a small device-memory budget must queue, never fail.
+"""
+import numpy as np
+import pytest
+
+from paper_2203_02293_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def rt(torch):
+    from paper_2203_02293_amd import rt as r
+    r.lib()
+    return r
+
+
+def request_mix(n, nb, seed):
+    """Uneven requests sharing one spectral set-up (nb bins)."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        C = int(r.integers(1, 700))
+        N = int(r.integers(20, 121))
+        spec = synth.Spec(name="serve", g_level=5, n_layers=N, n_bins=nb, cloud="fraction",
+                          cloud_fraction=float(r.uniform(0, 0.5)), seed=seed * 100 + k)
+        out.append(synth.make(spec, n_cols=C))
+    return out
+
+
+def host(out):
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["flags"] = res["flags"].view(np.uint32)
+    return res
+
+
+@pytest.mark.parametrize("nb", [30, 100])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mix_equals_alone(rt, torch, nb, precision):
+    reqs = request_mix(6, nb, seed=nb + precision)
+    print(f"\n[serving] nb={nb} precision={precision} shapes="
+          f"{[(w['n_cols'], w['n_layers']) for w in reqs]}", flush=True)
+    s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"])
+    inputs = [rt.to_device(w) for w in reqs]
+    alone = []
+    for inp in inputs:
+        o = s.solve(inp, precision=precision)
+        torch.cuda.synchronize()
+        alone.append(host(o))
+    outs = [s.outputs(int(i["mu_star"].shape[0]), int(i["dtau"].shape[0])) for i in inputs]
+    torch.cuda.synchronize()
+    tickets = [s.submit(i, o, precision) for i, o in zip(inputs, outs)]
+    for t in reversed(tickets):
+        assert s.wait(t) == rt.RT_OK
+    for a, o in zip(alone, outs):
+        b = host(o)
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    s.close()
+
+
+def test_small_budget_queues(rt, torch):
+    """A budget that fits one request at a time: all requests still finish,
+    in any order, each with the stand-alone result."""
+    reqs = request_mix(5, 30, seed=7)
+    probe = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"])
+    need = max(probe.work_bytes(w["n_cols"], w["n_layers"]) for w in reqs)
+    probe.close()
+    s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"], hbm_budget_bytes=need + 4096)
+    inputs = [rt.to_device(w) for w in reqs]
+    alone = []
+    for inp in inputs:
+        o = s.solve(inp)
+        torch.cuda.synchronize()
+        alone.append(host(o))
+    outs = [s.outputs(int(i["mu_star"].shape[0]), int(i["dtau"].shape[0])) for i in inputs]
+    torch.cuda.synchronize()
+    tickets = [s.submit(i, o) for i, o in zip(inputs, outs)]
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            st = s.poll(t)
+            if st == rt.RT_OK:
+                pending.discard(t)
+    for a, o in zip(alone, outs):
+        np.testing.assert_array_equal(a["F_net"], host(o)["F_net"])
+    s.close()
+
+
+def test_ticket_errors_and_queue_limit(rt, torch):
+    reqs = request_mix(3, 30, seed=9)
+    s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"], max_inflight=2)
+    inputs = [rt.to_device(w) for w in reqs]
+    outs = [s.outputs(int(i["mu_star"].shape[0]), int(i["dtau"].shape[0])) for i in inputs]
+    torch.cuda.synchronize()
+    with pytest.raises(rt.RtError) as e:
+        s.poll(12345)
+    assert e.value.status == rt.RT_ENOTFOUND
+    t0 = s.submit(inputs[0], outs[0])
+    t1 = s.submit(inputs[1], outs[1])
+    try:
+        t2 = s.submit(inputs[2], outs[2])
+        got_busy = False
+    except rt.RtError as err:
+        assert err.status == rt.RT_EBUSY
+        got_busy = True
+    for t in (t0, t1):
+        assert s.wait(t) == rt.RT_OK
+    if not got_busy:
+        assert s.wait(t2) == rt.RT_OK
+    with pytest.raises(rt.RtError):
+        s.poll(t0)                      # retired after its first completed poll
+    # destroy with a request still in flight waits for it
+    t3 = s.submit(inputs[0], outs[0])
+    s.close()
+    torch.cuda.synchronize()
