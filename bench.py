@@ -22,6 +22,8 @@ import pathlib
 import sys
 import time
 
+import numpy as np
+
 ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
@@ -104,6 +106,69 @@ def cpu_baseline(work, seconds: float = 10.0) -> dict:
                       f"on {threads} OpenMP threads"}
 
 
+def serving(args, torch, rt, synth) -> dict:
+    """Serving mix: uneven requests (columns U{1..4096}, layers U{20..120}, bins in
+    {30, 100, 300}, cloud fraction U[0, 0.5]) arriving as a Poisson process,
+    half FP64 and half mixed, through rt_submit/rt_poll.  Inputs stay resident
+    on the device; one handle per spectral set-up.  Latency = completion time
+    (seen by polling) minus arrival time."""
+    shapes = synth.serving_requests(args.serve_pool, seed=1003, max_cols=4096)
+    pool, solvers = [], {}
+    for k, sh in enumerate(shapes):
+        w = synth.make_request(sh)
+        nb = w["n_bins"]
+        if nb not in solvers:
+            solvers[nb] = rt.Solver(w["lambda_edges"], w["F_star"], max_inflight=256,
+                                    hbm_budget_bytes=args.serve_budget_gib << 30)
+        pool.append(dict(nb=nb, inp=rt.to_device(w), C=w["n_cols"], N=w["n_layers"],
+                         prec=rt.RT_FP64 if k % 2 == 0 else rt.RT_MIXED))
+    torch.cuda.synchronize()
+    # warm each request once (also gives its stand-alone latency)
+    for q in pool:
+        s = solvers[q["nb"]]
+        q["out"] = [s.outputs(q["C"], q["N"]) for _ in range(args.serve_copies)]
+        s.solve(q["inp"], precision=q["prec"], out=q["out"][0])
+    torch.cuda.synchronize()
+    results = []
+    for rate in args.serve_rates:
+        arrivals = synth.poisson_arrivals(args.serve_requests, rate, seed=int(rate))
+        order = np.random.Generator(np.random.PCG64(int(rate) + 1)).integers(
+            0, len(pool), args.serve_requests)
+        busy = [[False] * args.serve_copies for _ in pool]
+        inflight, lat, cb = {}, [], 0
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(arrivals) or inflight:
+            now = time.perf_counter() - t0
+            while i < len(arrivals) and arrivals[i] <= now:
+                q = pool[order[i]]
+                slot = next((m for m in range(args.serve_copies) if not busy[order[i]][m]), None)
+                if slot is None:      # all output copies of this request busy: wait
+                    break
+                busy[order[i]][slot] = True
+                t = solvers[q["nb"]].submit(q["inp"], q["out"][slot], q["prec"])
+                inflight[(q["nb"], t)] = (arrivals[i], order[i], slot)
+                i += 1
+            for key in list(inflight):
+                nb, t = key
+                if solvers[nb].poll(t) == rt.RT_OK:
+                    arr, qi, slot = inflight.pop(key)
+                    lat.append(time.perf_counter() - t0 - arr)
+                    busy[qi][slot] = False
+                    cb += pool[qi]["C"] * pool[qi]["nb"]
+        el = time.perf_counter() - t0
+        results.append({"rate_hz": rate, "requests": len(lat),
+                        "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3,
+                        "solves_per_s": cb / el, "seconds": el})
+        print(f"[bench] serving rate {rate}/s: p50 {results[-1]['p50_ms']:.2f} ms "
+              f"p99 {results[-1]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    for s in solvers.values():
+        s.close()
+    return {"pool": len(pool), "mix": "columns U{1..4096}, layers U{20..120}, bins {30,100,300}, "
+                                      "cloud fraction U[0,0.5], half FP64 / half mixed",
+            "rates": results}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +177,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serving", action="store_true", help="also run the serving mix")
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-copies", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[50.0, 200.0])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 5 device-to-device copies of this many bytes (calibrates "
                          "the HBM byte counters against a kernel of known traffic)")
@@ -177,6 +248,9 @@ def main():
                                       "traffic": traffic_from_profiles("k_solve<true>"),
                                       "kernel": "k_solve<true>"}}
     s.close()
+    if args.serving:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        line["serving"] = serving(args, torch, rt, synth)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)

@@ -115,7 +115,8 @@ rt_status rt_destroy(rt_handle *h);
 typedef struct {
     int32_t n_cols, n_layers;
     int32_t precision;            /* RT_FP64 or RT_MIXED */
-    int32_t reserved_;            /* must be 0 */
+    int32_t cols_per_block;       /* tile: columns per workgroup K, K*NB <= 512;
+                                     0 = the library's default for this shape   */
     const double *p_iface, *T_iface;
     const double *dtau, *w0, *g0;
     const double *mu_star, *T_int;

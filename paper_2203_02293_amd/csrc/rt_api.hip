@@ -22,7 +22,7 @@
 namespace {
 
 constexpr double kH = 6.62607015e-34, kC = 299792458.0, kKB = 1.380649e-23;
-constexpr int kMaxBins = 512;
+constexpr int kMaxBins = rtk::kMaxThreads;
 constexpr int kMaxLayers = 4096;
 constexpr int kStreams = 4;
 constexpr size_t kAlign = 256;
@@ -157,7 +157,7 @@ extern "C" const char *rt_status_string(rt_status s)
 extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers)
 {
     if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
-    return (int64_t)rtk::solve_scratch_bytes(n_cols, n_layers, h->NB);
+    return (int64_t)rtk::solve_scratch_bytes(n_cols, n_layers, h->NB, 0);
 }
 
 extern "C" const char *rt_last_error(const rt_handle *h)
@@ -247,7 +247,8 @@ static rt_status validate(rt_handle *h, const rt_request *r)
         return fail(h, RT_EINVAL, "n_layers must be in [1, %d] (got %d)", kMaxLayers, r->n_layers);
     if (r->precision != RT_FP64 && r->precision != RT_MIXED)
         return fail(h, RT_EINVAL, "precision must be RT_FP64 or RT_MIXED");
-    if (r->reserved_ != 0) return fail(h, RT_EINVAL, "reserved_ must be 0");
+    if (r->cols_per_block < 0 || (long long)r->cols_per_block * h->NB > rtk::kMaxThreads)
+        return fail(h, RT_EINVAL, "cols_per_block * n_bins must be <= %d", rtk::kMaxThreads);
     const void *req_in[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int};
     const char *names_in[] = {"p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"};
     for (int k = 0; k < 7; ++k)
@@ -296,6 +297,7 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
     a.F_dn_bin = r->F_dn_bin;
     a.flags = r->flags;
     a.scratch = scratch;
+    a.K = r->cols_per_block;
     a.o.improved = h->cfg.improved;
     a.o.noniso = h->cfg.noniso;
     a.o.e_clamp = h->cfg.e_clamp;
@@ -313,7 +315,8 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
     rt_status st = validate(h, r);
     if (st != RT_OK) return st;
     (void)hipSetDevice(h->cfg.device);
-    const size_t need = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB);
+    const size_t need =
+        rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, r->cols_per_block);
     if (need > h->scratch_bytes) {
         // growth waits for the device: earlier solves may still use the old buffer
         (void)hipDeviceSynchronize();
@@ -402,7 +405,7 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
-    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB);
+    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, r->cols_per_block);
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);
     h->queued.push_back(j);

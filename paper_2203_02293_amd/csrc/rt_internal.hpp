@@ -40,8 +40,11 @@ struct Geometry {
     size_t lds;     // dynamic LDS bytes
 };
 
-Geometry solve_geometry(int C, int NB);
-size_t solve_scratch_bytes(int C, int N, int NB);
+constexpr int kMaxThreads = 512;   // workgroup size bound of the solve kernel
+
+int default_cols_per_block(int C, int NB);
+Geometry solve_geometry(int C, int NB, int K);
+size_t solve_scratch_bytes(int C, int N, int NB, int K);
 hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s);
 
 }  // namespace rtk

@@ -57,7 +57,7 @@ __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 // TOA, back-substitution from the BOA, bin sums, net flux and heating.
 // ---------------------------------------------------------------------------
 template <bool MIXED>
-__global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
+__global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double smem[];
@@ -274,11 +274,18 @@ __global__ void __launch_bounds__(512) k_solve(const SolveArgs a)
 
 }  // namespace
 
-Geometry solve_geometry(int C, int NB)
+int default_cols_per_block(int C, int NB)
+{
+    int K = 256 / NB;
+    if (K < 1) K = 1;
+    if (K > C) K = C;
+    return K;
+}
+
+Geometry solve_geometry(int C, int NB, int K)
 {
     Geometry g;
-    g.K = 256 / NB;
-    if (g.K < 1) g.K = 1;
+    g.K = K > 0 ? K : default_cols_per_block(C, NB);
     if (g.K > C) g.K = C;
     int lanes = g.K * NB;
     g.threads = ((lanes + 63) / 64) * 64;
@@ -290,15 +297,15 @@ Geometry solve_geometry(int C, int NB)
     return g;
 }
 
-size_t solve_scratch_bytes(int C, int N, int NB)
+size_t solve_scratch_bytes(int C, int N, int NB, int K)
 {
-    Geometry g = solve_geometry(C, NB);
+    Geometry g = solve_geometry(C, NB, K);
     return (size_t)N * 5 * (size_t)g.lanes * sizeof(double);
 }
 
 hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s)
 {
-    Geometry g = solve_geometry(a.C, a.NB);
+    Geometry g = solve_geometry(a.C, a.NB, a.K);
     SolveArgs b = a;
     b.K = g.K;
     b.L = g.lanes;
