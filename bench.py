@@ -29,7 +29,12 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
-WORKLOAD = "cfg1"
+WORKLOADS = {
+    "cfg1": "GCM size: 2562 icosahedral columns x 40 layers x 30 bins log-spaced 0.3-30 um, "
+            "night-side cloud deck",
+    "cfg4": "high resolution: 10242 icosahedral columns x 80 layers x 300 bins log-spaced "
+            "0.3-30 um, cloud decks to w0 0.9999 / g0 0.98, dtau log-uniform [1e-8, 1e3]",
+}
 METRIC = "two-stream column·bin solves/s (FP64 vs mixed, ≤1e-5 rel err); p50/p99 latency"
 
 
@@ -177,6 +182,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
     ap.add_argument("--serving", action="store_true", help="also run the serving mix")
     ap.add_argument("--serve-pool", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -206,6 +212,7 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "read": n * 8, "written": n * 8}))
         return
 
+    WORKLOAD = args.workload
     work = synth.make(WORKLOAD)
     C, N, NB = work["n_cols"], work["n_layers"], work["n_bins"]
     s = rt.Solver(work["lambda_edges"], work["F_star"])
@@ -219,15 +226,14 @@ def main():
     value = C * NB / (ms * 1e-3)
     abytes = algorithmic_bytes(C, N, NB)
     achieved = abytes / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("k_solve<false>")
+    traffic = traffic_from_profiles("k_solve<false>") if WORKLOAD == "cfg1" else None
     line = {
         "metric": METRIC, "value": value, "unit": "column·bin solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "GCM size: 2562 icosahedral columns x 40 layers x 30 bins "
-                               "log-spaced 0.3-30 um, FP64, night-side cloud deck",
+        "config": {"workload": WORKLOADS[WORKLOAD] + ", FP64",
                    "n_cols": C, "n_layers": N, "n_bins": NB, "precision": "fp64"},
         "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -245,7 +251,8 @@ def main():
                          "latency_ms": {"p50": pct(per_m, 50), "p99": pct(per_m, 99)},
                          "roofline": {"bound": "hbm", "achieved": ach_m, "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": ach_m / HBM_PEAK_GBS,
-                                      "traffic": traffic_from_profiles("k_solve<true>"),
+                                      "traffic": (traffic_from_profiles("k_solve<true>")
+                                                  if WORKLOAD == "cfg1" else None),
                                       "kernel": "k_solve<true>"}}
     s.close()
     if args.serving:

@@ -217,3 +217,21 @@ def test_repeat_is_bitwise_identical(rt, torch):
     b = gpu_solve(rt, torch, w, rt.RT_FP64, per_bin=True)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_cfg4_sampled(rt, torch):
+    """High resolution, 10242 x 80 x 300 with cloud decks up to w0 = 0.9999,
+    g0 = 0.98 and dtau log-uniform [1e-8, 1e3]: solved whole on the GPU in
+    both precisions, 24 columns checked against the oracle."""
+    w = synth.make("cfg4")
+    print(f"\n[parity] cfg4 full {w['n_cols']}x{w['n_layers']}x{w['n_bins']}", flush=True)
+    cols = np.unique(np.concatenate([np.linspace(0, w["n_cols"] - 1, 16).astype(int),
+                                     np.argsort(np.abs(w["mu_star"]))[:8]]))
+    ws = subset(w, cols)
+    ref = O.solve(ws, extended=True)
+    for prec, tol in ((rt.RT_MIXED, MIXED_TOL), (rt.RT_FP64, FP64_TOL)):
+        out = gpu_solve(rt, torch, w, prec)
+        e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec],
+                         floor_bin=FLOOR_BIN[prec], cols=cols)
+        print(f"  precision={prec} errors={e}", flush=True)
+        np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
