@@ -139,10 +139,15 @@ rt_status rt_solve_fluxes(rt_handle *h, const rt_request *req, void *hip_stream)
 
 /*
  * Serving path: enqueue a request and return at once with *ticket.  The
- * library admits queued requests onto the device when slots and its memory
- * budget allow, runs admitted requests concurrently, and retires them in any
- * order.  The request's buffers must stay valid, and must not be touched,
- * until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:
+ * library admits queued requests onto the device in arrival order when its
+ * memory budget allows; requests of the same precision and tile width that are
+ * admitted together run as one batched launch (each workgroup finds its
+ * request and column tile in a descriptor table), up to 64 per launch and 16
+ * launches in flight on 4 library-owned streams.  Results equal those of
+ * rt_solve_fluxes bit for bit.  Requests retire in any order.  The inputs must
+ * be complete on the device before the call (the library's streams do not wait
+ * on the caller's), and the request's buffers must stay valid, and must not be
+ * touched, until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:
  * RT_EINVAL (bad request), RT_EBUSY (max_inflight reached), RT_ENOMEM (the
  * request alone exceeds the memory budget).
  */

@@ -76,10 +76,23 @@ struct Arena {
 struct Job {
     uint64_t ticket;
     rt_request req;
-    size_t bytes = 0, off = 0;
-    int stream = -1;
+    int K = 0;                 // tile width used for this request
+    size_t bytes = 0, off = 0; // reservation in the serving arena
+};
+
+constexpr int kMaxBatch = 64;  // requests per batched launch
+constexpr int kSlots = 16;     // batches in flight
+
+// One batched launch in flight: its requests, descriptor buffers and event.
+struct Batch {
+    bool busy = false;
+    std::vector<Job> jobs;
+    rtk::SolveArgs *h_args = nullptr;   // pinned host staging
+    int *h_first = nullptr;
+    rtk::SolveArgs *d_args = nullptr;   // device copy read by the kernel
+    int *d_first = nullptr;
     hipEvent_t done = nullptr;
-    rt_status status = RT_PENDING;
+    int stream = 0;
 };
 
 }  // namespace
@@ -100,7 +113,8 @@ struct rt_handle {
     Arena arena;
     uint64_t next_ticket = 1;
     std::deque<Job> queued;
-    std::map<uint64_t, Job> running;
+    Batch slots[kSlots];
+    std::map<uint64_t, int> running;          // ticket -> batch slot
     std::map<uint64_t, rt_status> finished;   // retired on first poll
 };
 
@@ -226,8 +240,13 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     for (auto &s : h->streams)
         if (s) (void)hipStreamSynchronize(s);
     (void)hipDeviceSynchronize();
-    for (auto &kv : h->running)
-        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    for (auto &b : h->slots) {
+        if (b.done) (void)hipEventDestroy(b.done);
+        if (b.h_args) (void)hipHostFree(b.h_args);
+        if (b.h_first) (void)hipHostFree(b.h_first);
+        (void)hipFree(b.d_args);
+        (void)hipFree(b.d_first);
+    }
     for (auto &s : h->streams)
         if (s) (void)hipStreamDestroy(s);
     (void)hipFree(h->d_c2lam);
@@ -340,6 +359,16 @@ static rt_status ensure_serving(rt_handle *h)
     for (auto &s : h->streams)
         if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
             return fail(h, RT_EDEVICE, "stream creation failed");
+    for (int i = 0; i < kSlots; ++i) {
+        Batch &b = h->slots[i];
+        if (hipHostMalloc((void **)&b.h_args, sizeof(rtk::SolveArgs) * kMaxBatch) != hipSuccess ||
+            hipHostMalloc((void **)&b.h_first, sizeof(int) * kMaxBatch) != hipSuccess ||
+            hipMalloc(&b.d_args, sizeof(rtk::SolveArgs) * kMaxBatch) != hipSuccess ||
+            hipMalloc(&b.d_first, sizeof(int) * kMaxBatch) != hipSuccess ||
+            hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
+            return fail(h, RT_ENOMEM, "serving descriptor buffers");
+        b.stream = i % kStreams;
+    }
     size_t bytes = (size_t)h->cfg.hbm_budget_bytes;
     if (hipMalloc(&h->arena_mem, bytes) != hipSuccess) {
         h->arena_mem = nullptr;
@@ -349,44 +378,72 @@ static rt_status ensure_serving(rt_handle *h)
     return RT_OK;
 }
 
-// Admit queued requests in arrival order while memory and slots allow.
+// Retire finished batches, then admit queued requests: in arrival order, by
+// device-memory footprint, grouped by (precision, tile) into batched launches.
 static void pump(rt_handle *h)
 {
-    // retire finished work first so its memory can be reused
-    for (auto it = h->running.begin(); it != h->running.end();) {
-        hipError_t q = hipEventQuery(it->second.done);
-        if (q == hipErrorNotReady) {
-            ++it;
-            continue;
+    for (int i = 0; i < kSlots; ++i) {
+        Batch &b = h->slots[i];
+        if (!b.busy) continue;
+        hipError_t q = hipEventQuery(b.done);
+        if (q == hipErrorNotReady) continue;
+        rt_status st = (q == hipSuccess) ? RT_OK : RT_EDEVICE;
+        for (const Job &j : b.jobs) {
+            h->arena.release(j.off, j.bytes);
+            h->running.erase(j.ticket);
+            h->finished[j.ticket] = st;
         }
-        rt_status s = (q == hipSuccess) ? RT_OK : RT_EDEVICE;
-        h->arena.release(it->second.off, it->second.bytes);
-        (void)hipEventDestroy(it->second.done);
-        h->finished[it->first] = s;
-        it = h->running.erase(it);
+        b.jobs.clear();
+        b.busy = false;
     }
     while (!h->queued.empty()) {
-        Job &j = h->queued.front();
-        size_t off;
-        if (!h->arena.alloc(j.bytes, &off)) break;   // wait for memory: keep arrival order
-        j.off = off;
-        j.stream = h->next_stream;
-        h->next_stream = (h->next_stream + 1) % kStreams;
-        hipStream_t s = h->streams[j.stream];
-        rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
-        hipError_t e = rtk::launch_solve(a, j.req.precision, s);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&j.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(j.done, s);
+        int slot = -1;
+        for (int i = 0; i < kSlots; ++i)
+            if (!h->slots[i].busy) { slot = i; break; }
+        if (slot < 0) return;                       // every batch slot in flight
+        Batch &b = h->slots[slot];
+        const int prec = h->queued.front().req.precision, K = h->queued.front().K;
+        int blocks = 0, threads = 0;
+        size_t lds = 0;
+        for (auto it = h->queued.begin(); it != h->queued.end() && (int)b.jobs.size() < kMaxBatch;) {
+            if (it->req.precision != prec || it->K != K) { ++it; continue; }
+            size_t off;
+            if (!h->arena.alloc(it->bytes, &off)) break;   // keep arrival order under pressure
+            Job j = *it;
+            j.off = off;
+            rtk::Geometry g = rtk::solve_geometry(j.req.n_cols, h->NB, K);
+            rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
+            a.K = g.K;
+            a.L = g.lanes;
+            b.h_args[b.jobs.size()] = a;
+            b.h_first[b.jobs.size()] = blocks;
+            blocks += g.blocks;
+            threads = g.threads;
+            lds = std::max(lds, g.lds);
+            b.jobs.push_back(j);
+            it = h->queued.erase(it);
+        }
+        if (b.jobs.empty()) return;                 // head request waits for memory
+        const int n = (int)b.jobs.size();
+        hipStream_t s = h->streams[b.stream];
+        hipError_t e = hipMemcpyAsync(b.d_args, b.h_args, sizeof(rtk::SolveArgs) * n,
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.d_first, b.h_first, sizeof(int) * n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, threads, lds, prec, s);
+        if (e == hipSuccess) e = hipEventRecord(b.done, s);
         if (e != hipSuccess) {
             hip_fail(h, e, "serving launch");
-            h->arena.release(off, j.bytes);
-            if (j.done) (void)hipEventDestroy(j.done);
-            h->finished[j.ticket] = RT_EDEVICE;
-            h->queued.pop_front();
-            continue;
+            for (const Job &j : b.jobs) {
+                h->arena.release(j.off, j.bytes);
+                h->finished[j.ticket] = RT_EDEVICE;
+            }
+            b.jobs.clear();
+            return;
         }
-        h->running.emplace(j.ticket, j);
-        h->queued.pop_front();
+        b.busy = true;
+        for (const Job &j : b.jobs) h->running[j.ticket] = slot;
     }
 }
 
@@ -405,7 +462,8 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
-    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, r->cols_per_block);
+    j.K = rtk::solve_geometry(r->n_cols, h->NB, r->cols_per_block).K;
+    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, j.K);
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);
     h->queued.push_back(j);
@@ -439,10 +497,14 @@ extern "C" rt_status rt_wait(rt_handle *h, uint64_t ticket)
         if (s != RT_PENDING) return s;
         auto it = h->running.find(ticket);
         if (it != h->running.end()) {
-            (void)hipEventSynchronize(it->second.done);
-        } else if (!h->running.empty()) {
-            // queued behind memory: wait for the oldest running request
-            (void)hipEventSynchronize(h->running.begin()->second.done);
+            (void)hipEventSynchronize(h->slots[it->second].done);
+        } else {
+            // queued behind memory or slots: wait for any batch in flight
+            for (auto &b : h->slots)
+                if (b.busy) {
+                    (void)hipEventSynchronize(b.done);
+                    break;
+                }
         }
     }
 }

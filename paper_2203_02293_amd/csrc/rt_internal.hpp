@@ -46,5 +46,9 @@ int default_cols_per_block(int C, int NB);
 Geometry solve_geometry(int C, int NB, int K);
 size_t solve_scratch_bytes(int C, int N, int NB, int K);
 hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s);
+// Several requests with the same tile width and bins in one launch: device arrays
+// d_reqs[n] (with K and L filled in) and d_first[n] (first workgroup of each).
+hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
+                              int threads, size_t lds, int precision, hipStream_t s);
 
 }  // namespace rtk

@@ -57,16 +57,16 @@ __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 // TOA, back-substitution from the BOA, bin sums, net flux and heating.
 // ---------------------------------------------------------------------------
 template <bool MIXED>
-__global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
+__device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double smem[];
     const int NB = a.NB, K = a.K, C = a.C, N = a.N;
     const int tid = threadIdx.x, bd = blockDim.x;
     const int kloc = tid / NB, b = tid - kloc * NB;
-    const int c = blockIdx.x * K + kloc;
+    const int c = tile * K + kloc;
     const bool active = (kloc < K) && (c < C);
-    const long long gl = (long long)blockIdx.x * bd + tid;
+    const long long gl = (long long)tile * bd + tid;
     const int CH = chunk_for(bd, K, NB);
 
     // LDS: the forward sweep's Planck edge values and the back-substitution's
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
         for (int e = tid; e < tot; e += bd) {
             const int q = e / (K * (NB + 1)), rem = e - q * K * (NB + 1);
             const int ee = rem / K, kk = rem - ee * K;
-            const int cc = blockIdx.x * K + kk;
+            const int cc = tile * K + kk;
             R v = R(0);
             if (cc < C) {
                 const double T = Tsrc[off0 - q * stride + cc];
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
         // bin sums: one task per (column, interface) of the chunk
         for (int task = tid; task < K * CH; task += bd) {
             const int kk = task / CH, ii = task - kk * CH;
-            const int cc = blockIdx.x * K + kk;
+            const int cc = tile * K + kk;
             if (ii >= nch || cc >= C) continue;
             double su = 0.0, sd = 0.0, sb = 0.0;
             const double *ru = s_red + (0 * CH + ii) * bd + kk * NB;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
         // heating of the layer below each interface of the chunk
         for (int task = tid; task < K * CH; task += bd) {
             const int kk = task / CH, ii = task - kk * CH;
-            const int cc = blockIdx.x * K + kk;
+            const int cc = tile * K + kk;
             const int i = i0 + ii;
             if (ii >= nch || cc >= C || i < 1) continue;
             const double dp = a.p[(long long)(i - 1) * C + cc] - a.p[(long long)i * C + cc];
@@ -267,9 +267,32 @@ __global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
     }
     __syncthreads();
     for (int kk = tid; kk < K; kk += bd) {
-        const int cc = blockIdx.x * K + kk;
+        const int cc = tile * K + kk;
         if (cc < C && a.flags) a.flags[cc] = s_flag[kk];
     }
+}
+
+// One request: workgroup = tile.
+template <bool MIXED>
+__global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
+{
+    solve_tile<MIXED>(a, blockIdx.x);
+}
+
+// Several requests in one launch (serving): workgroup g belongs to the request
+// r with first[r] <= g < first[r+1]; all requests share the tile width.
+template <bool MIXED>
+__global__ void __launch_bounds__(kMaxThreads)
+k_solve_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
+{
+    const int g = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {   // last r with first[r] <= g
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    solve_tile<MIXED>(reqs[lo], g - first[lo]);
 }
 
 }  // namespace
@@ -301,6 +324,18 @@ size_t solve_scratch_bytes(int C, int N, int NB, int K)
 {
     Geometry g = solve_geometry(C, NB, K);
     return (size_t)N * 5 * (size_t)g.lanes * sizeof(double);
+}
+
+hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
+                              int threads, size_t lds, int precision, hipStream_t s)
+{
+    if (precision == 1)
+        hipLaunchKernelGGL(k_solve_batch<true>, dim3(total_blocks), dim3(threads), lds, s, d_reqs,
+                           d_first, n);
+    else
+        hipLaunchKernelGGL(k_solve_batch<false>, dim3(total_blocks), dim3(threads), lds, s, d_reqs,
+                           d_first, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s)
