@@ -66,17 +66,22 @@ def traffic_from_profiles(kernel: str) -> float | None:
     return None if k is None else float(k["bytes_per_launch"])
 
 
-def time_path(s, inp, out, precision, steps, warmup, torch):
+KERNEL_IDS = {"auto": None, "lane": 1, "layer": 2}
+KERNEL_NAMES = {1: "k_solve_lane", 2: "k_solve_layer"}
+
+
+def time_path(s, inp, out, precision, steps, warmup, torch, kernel=None):
     """Warm up, then time exactly `steps` back-to-back solves on the current stream."""
     stream = torch.cuda.current_stream()
+    kw = {} if kernel is None else {"kernel": kernel, "cols_per_block": 0}
     for _ in range(warmup):
-        s.solve(inp, precision=precision, out=out)
+        s.solve(inp, precision=precision, out=out, **kw)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(steps):
-        s.solve(inp, precision=precision, out=out)
+        s.solve(inp, precision=precision, out=out, **kw)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -183,6 +188,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--kernel", default="auto", choices=sorted(KERNEL_IDS),
+                    help="solve kernel of the headline line (auto: tuned choice)")
+    ap.add_argument("--compare-kernels", action="store_true",
+                    help="also time both kernels at their default tiles")
     ap.add_argument("--serving", action="store_true", help="also run the serving mix")
     ap.add_argument("--serve-pool", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -221,12 +230,17 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] {WORKLOAD} {C}x{N}x{NB} resident; timing FP64", file=sys.stderr, flush=True)
 
-    wall, tot, per = time_path(s, inp, out, rt.RT_FP64, args.steps, args.warmup, torch)
+    kernel = KERNEL_IDS[args.kernel]
+    # the kernel that runs: explicit, else the tuned choice, else the library's (layer)
+    used = kernel if kernel is not None else (rt.tuned_launch(NB, rt.RT_FP64, C, N)[0] or 2)
+    used_m = kernel if kernel is not None else (rt.tuned_launch(NB, rt.RT_MIXED, C, N)[0] or 2)
+    kname, kname_m = KERNEL_NAMES[used] + "<false>", KERNEL_NAMES[used_m] + "<true>"
+    wall, tot, per = time_path(s, inp, out, rt.RT_FP64, args.steps, args.warmup, torch, kernel)
     ms = tot / args.steps
     value = C * NB / (ms * 1e-3)
     abytes = algorithmic_bytes(C, N, NB)
     achieved = abytes / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("k_solve<false>") if WORKLOAD == "cfg1" else None
+    traffic = traffic_from_profiles(kname) if WORKLOAD == "cfg1" else None
     line = {
         "metric": METRIC, "value": value, "unit": "column·bin solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -239,11 +253,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": abytes,
-                     "kernel": "k_solve<false>", "kernel_ms": ms},
+                     "kernel": kname, "kernel_ms": ms},
     }
     if not args.no_mixed:
         print("[bench] timing mixed", file=sys.stderr, flush=True)
-        wall_m, tot_m, per_m = time_path(s, inp, out, rt.RT_MIXED, args.steps, args.warmup, torch)
+        wall_m, tot_m, per_m = time_path(s, inp, out, rt.RT_MIXED, args.steps, args.warmup,
+                                         torch, kernel)
         ms_m = tot_m / args.steps
         ach_m = abytes / (ms_m * 1e-3) / 1e9
         line["mixed"] = {"value": C * NB / (ms_m * 1e-3), "ms_per_step": ms_m,
@@ -251,9 +266,17 @@ def main():
                          "latency_ms": {"p50": pct(per_m, 50), "p99": pct(per_m, 99)},
                          "roofline": {"bound": "hbm", "achieved": ach_m, "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": ach_m / HBM_PEAK_GBS,
-                                      "traffic": (traffic_from_profiles("k_solve<true>")
+                                      "traffic": (traffic_from_profiles(kname_m)
                                                   if WORKLOAD == "cfg1" else None),
-                                      "kernel": "k_solve<true>"}}
+                                      "kernel": kname_m}}
+    if args.compare_kernels:
+        cmp = {}
+        for kid, kn in KERNEL_NAMES.items():
+            for prec, tag in ((rt.RT_FP64, "fp64"), (rt.RT_MIXED, "mixed")):
+                print(f"[bench] timing {kn} {tag}", file=sys.stderr, flush=True)
+                _, t, _ = time_path(s, inp, out, prec, args.steps, args.warmup, torch, kid)
+                cmp[f"{kn}:{tag}"] = t / args.steps
+        line["kernels_ms"] = cmp
     s.close()
     if args.serving:
         print("[bench] serving mix", file=sys.stderr, flush=True)

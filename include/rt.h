@@ -43,6 +43,15 @@ typedef int32_t rt_status;
 #define RT_MIXED 1   /* FP32 coefficients, exponentials and Planck integrals; FP64
                         predicates, optical-depth sums and Thomas elimination     */
 
+/* Solve kernels (same results to the precision's tolerance, different launch
+ * shapes).  LANE: one thread per (column, bin) runs the whole sweep of its
+ * lane.  LAYER: the Planck, beam and coefficient work of a tile is spread over
+ * (layer, column, bin) items shared by the workgroup; only the FP64
+ * elimination runs per lane.  AUTO picks LAYER. */
+#define RT_KERNEL_AUTO  0
+#define RT_KERNEL_LANE  1
+#define RT_KERNEL_LAYER 2
+
 /* per-column condition bits written to rt_request.flags */
 #define RT_FLAG_GUARD    1u  /* G+- resonance guard (Section 2.2.1) replaced D by 2 mu_star */
 #define RT_FLAG_ECLAMP   2u  /* E fit below 1 raised to 1 (e_clamp mode)                */
@@ -115,8 +124,13 @@ rt_status rt_destroy(rt_handle *h);
 typedef struct {
     int32_t n_cols, n_layers;
     int32_t precision;            /* RT_FP64 or RT_MIXED */
-    int32_t cols_per_block;       /* tile: columns per workgroup K, K*NB <= 512;
-                                     0 = the library's default for this shape   */
+    int32_t cols_per_block;       /* tile: columns per workgroup K (0 = the
+                                     library's default for this shape); the tile
+                                     must fit the kernel: K*NB <= 512 (lane
+                                     kernel), K*NB <= 1024 and its LDS within the
+                                     device's (layer kernel), else RT_EINVAL      */
+    int32_t kernel;               /* RT_KERNEL_AUTO, RT_KERNEL_LANE or RT_KERNEL_LAYER */
+    int32_t reserved;             /* must be 0 */
     const double *p_iface, *T_iface;
     const double *dtau, *w0, *g0;
     const double *mu_star, *T_int;

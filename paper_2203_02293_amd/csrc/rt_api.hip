@@ -22,7 +22,7 @@
 namespace {
 
 constexpr double kH = 6.62607015e-34, kC = 299792458.0, kKB = 1.380649e-23;
-constexpr int kMaxBins = rtk::kMaxThreads;
+constexpr int kMaxBins = 512;
 constexpr int kMaxLayers = 4096;
 constexpr int kStreams = 4;
 constexpr size_t kAlign = 256;
@@ -76,7 +76,7 @@ struct Arena {
 struct Job {
     uint64_t ticket;
     rt_request req;
-    int K = 0;                 // tile width used for this request
+    rtk::Geometry g;           // launch shape of this request
     size_t bytes = 0, off = 0; // reservation in the serving arena
 };
 
@@ -100,6 +100,7 @@ struct Batch {
 struct rt_handle {
     rt_config cfg{};
     int NB = 0;
+    rtk::DeviceLimits dev{};
     double *d_c2lam = nullptr;
     float *d_c2lam_f = nullptr;
     double *d_fstar = nullptr;
@@ -171,7 +172,9 @@ extern "C" const char *rt_status_string(rt_status s)
 extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers)
 {
     if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
-    return (int64_t)rtk::solve_scratch_bytes(n_cols, n_layers, h->NB, 0);
+    const rtk::Geometry g =
+        rtk::solve_geometry(n_cols, n_layers, h->NB, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
+    return g.threads > 0 ? (int64_t)g.scratch : -1;
 }
 
 extern "C" const char *rt_last_error(const rt_handle *h)
@@ -208,6 +211,22 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
     if (h->cfg.hbm_budget_bytes == 0) h->cfg.hbm_budget_bytes = 8ll << 30;
     if (h->cfg.max_inflight == 0) h->cfg.max_inflight = 64;
     h->NB = NB;
+    {
+        int n_cu = 0, lds = 0;
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, cfg->device) !=
+                hipSuccess) {
+            delete h;
+            return RT_EDEVICE;
+        }
+        h->dev.n_cu = n_cu;
+        h->dev.lds = (size_t)lds;
+        if (rtk::prepare_kernels(h->dev) != hipSuccess) {
+            delete h;
+            return RT_EDEVICE;
+        }
+    }
 
     std::vector<double> c2(NB + 1);
     std::vector<float> c2f(NB + 1);
@@ -258,6 +277,13 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     return RT_OK;
 }
 
+static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
+{
+    const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
+    return rtk::solve_geometry(r->n_cols, r->n_layers, h->NB, r->cols_per_block, kernel,
+                               r->precision, h->dev);
+}
+
 static rt_status validate(rt_handle *h, const rt_request *r)
 {
     if (!r) return fail(h, RT_EINVAL, "request is NULL");
@@ -266,8 +292,13 @@ static rt_status validate(rt_handle *h, const rt_request *r)
         return fail(h, RT_EINVAL, "n_layers must be in [1, %d] (got %d)", kMaxLayers, r->n_layers);
     if (r->precision != RT_FP64 && r->precision != RT_MIXED)
         return fail(h, RT_EINVAL, "precision must be RT_FP64 or RT_MIXED");
-    if (r->cols_per_block < 0 || (long long)r->cols_per_block * h->NB > rtk::kMaxThreads)
-        return fail(h, RT_EINVAL, "cols_per_block * n_bins must be <= %d", rtk::kMaxThreads);
+    if (r->kernel < RT_KERNEL_AUTO || r->kernel > RT_KERNEL_LAYER)
+        return fail(h, RT_EINVAL, "kernel must be RT_KERNEL_AUTO, _LANE or _LAYER");
+    if (r->reserved != 0) return fail(h, RT_EINVAL, "reserved must be 0");
+    if (r->cols_per_block < 0) return fail(h, RT_EINVAL, "cols_per_block must be >= 0");
+    if (request_geometry(h, r).threads == 0)
+        return fail(h, RT_EINVAL, "tile of %d columns x %d bins does not fit the %s kernel",
+                    r->cols_per_block, h->NB, r->kernel == RT_KERNEL_LANE ? "lane" : "layer");
     const void *req_in[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int};
     const char *names_in[] = {"p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"};
     for (int k = 0; k < 7; ++k)
@@ -316,7 +347,6 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
     a.F_dn_bin = r->F_dn_bin;
     a.flags = r->flags;
     a.scratch = scratch;
-    a.K = r->cols_per_block;
     a.o.improved = h->cfg.improved;
     a.o.noniso = h->cfg.noniso;
     a.o.e_clamp = h->cfg.e_clamp;
@@ -334,8 +364,8 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
     rt_status st = validate(h, r);
     if (st != RT_OK) return st;
     (void)hipSetDevice(h->cfg.device);
-    const size_t need =
-        rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, r->cols_per_block);
+    const rtk::Geometry g = request_geometry(h, r);
+    const size_t need = g.scratch;
     if (need > h->scratch_bytes) {
         // growth waits for the device: earlier solves may still use the old buffer
         (void)hipDeviceSynchronize();
@@ -347,7 +377,7 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
         h->scratch_bytes = need;
     }
     rtk::SolveArgs a = make_args(h, r, h->d_scratch);
-    hipError_t e = rtk::launch_solve(a, r->precision, (hipStream_t)stream);
+    hipError_t e = rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(h, e, "solve launch");
     return RT_OK;
 }
@@ -402,24 +432,29 @@ static void pump(rt_handle *h)
             if (!h->slots[i].busy) { slot = i; break; }
         if (slot < 0) return;                       // every batch slot in flight
         Batch &b = h->slots[slot];
-        const int prec = h->queued.front().req.precision, K = h->queued.front().K;
-        int blocks = 0, threads = 0;
-        size_t lds = 0;
+        const int prec = h->queued.front().req.precision;
+        const rtk::Geometry g0 = h->queued.front().g;
+        int blocks = 0;
         for (auto it = h->queued.begin(); it != h->queued.end() && (int)b.jobs.size() < kMaxBatch;) {
-            if (it->req.precision != prec || it->K != K) { ++it; continue; }
+            // one launch shape per batch: same kernel, precision, tile, threads and LDS
+            if (it->req.precision != prec || it->g.kernel != g0.kernel || it->g.K != g0.K ||
+                it->g.threads != g0.threads || it->g.lds != g0.lds || it->g.PC != g0.PC ||
+                it->g.CH != g0.CH) {
+                ++it;
+                continue;
+            }
             size_t off;
             if (!h->arena.alloc(it->bytes, &off)) break;   // keep arrival order under pressure
             Job j = *it;
             j.off = off;
-            rtk::Geometry g = rtk::solve_geometry(j.req.n_cols, h->NB, K);
             rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
-            a.K = g.K;
-            a.L = g.lanes;
+            a.K = j.g.K;
+            a.PC = j.g.PC;
+            a.CH = j.g.CH;
+            a.L = j.g.lanes;
             b.h_args[b.jobs.size()] = a;
             b.h_first[b.jobs.size()] = blocks;
-            blocks += g.blocks;
-            threads = g.threads;
-            lds = std::max(lds, g.lds);
+            blocks += j.g.blocks;
             b.jobs.push_back(j);
             it = h->queued.erase(it);
         }
@@ -431,7 +466,7 @@ static void pump(rt_handle *h)
         if (e == hipSuccess)
             e = hipMemcpyAsync(b.d_first, b.h_first, sizeof(int) * n, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
-            e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, threads, lds, prec, s);
+            e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, g0, prec, s);
         if (e == hipSuccess) e = hipEventRecord(b.done, s);
         if (e != hipSuccess) {
             hip_fail(h, e, "serving launch");
@@ -462,8 +497,8 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
-    j.K = rtk::solve_geometry(r->n_cols, h->NB, r->cols_per_block).K;
-    j.bytes = rtk::solve_scratch_bytes(r->n_cols, r->n_layers, h->NB, j.K);
+    j.g = request_geometry(h, r);
+    j.bytes = j.g.scratch;
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);
     h->queued.push_back(j);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace rtk {
@@ -12,10 +13,19 @@ struct Opts {
     double eps2, e_tau, g_guard, gravity, cp;
 };
 
+// The two solve kernels.
+enum Kernel : int {
+    KERNEL_AUTO = 0,
+    KERNEL_LANE = 1,    // one thread per (column, bin) does everything for its lane
+    KERNEL_LAYER = 2,   // Planck, beam and coefficients as (layer, column, bin) items
+                        // shared by the workgroup; only the elimination is per lane
+};
+
 // Everything one solve kernel needs (passed by value).
 struct SolveArgs {
     int C, N, NB;              // columns, layers, bins
     int K;                     // columns per workgroup
+    int PC, CH;                // layer kernel: levels per chunk, interfaces per bin-sum pass
     // resident tables of the handle
     const double *c2_over_lam; // [NB+1] second radiation constant / edge
     const float *c2_over_lam_f;
@@ -25,30 +35,46 @@ struct SolveArgs {
     // outputs
     double *F_up, *F_dn, *F_beam, *F_net, *heat, *dTdt, *F_up_toa_bin, *F_up_bin, *F_dn_bin;
     uint32_t *flags;
-    // work buffer: [N][5][L] doubles, L = lanes in the grid
+    // work buffer of back-substitution records, [N][R][L] doubles with L lanes in
+    // the grid (R = 5 for the lane kernel, 4 for the layer kernel)
     double *scratch;
     long long L;
     Opts o;
 };
 
-// Launch geometry of the solve kernel for a problem shape.
+// What the launch shape depends on besides the problem: the device.
+struct DeviceLimits {
+    int n_cu;          // compute units
+    size_t lds;        // dynamic LDS bytes one workgroup may use
+};
+
+// Launch geometry of a solve for a problem shape.
 struct Geometry {
+    int kernel;     // KERNEL_LANE or KERNEL_LAYER
     int K;          // columns per workgroup
+    int PC, CH;     // layer kernel: levels per chunk, interfaces per bin-sum pass
     int threads;    // workgroup size (multiple of 64)
     int blocks;     // workgroups
     long long lanes;
     size_t lds;     // dynamic LDS bytes
+    size_t scratch; // work-buffer bytes for N layers (set by solve_geometry)
 };
 
-constexpr int kMaxThreads = 512;   // workgroup size bound of the solve kernel
+constexpr int kMaxThreads = 1024;      // workgroup size bound of the solve kernels
+constexpr int kMaxLaneThreads = 512;   // of the lane kernel
+constexpr int kMaxTileLanes = 1024;    // (column, bin) lanes of one layer-kernel tile
 
-int default_cols_per_block(int C, int NB);
-Geometry solve_geometry(int C, int NB, int K);
-size_t solve_scratch_bytes(int C, int N, int NB, int K);
-hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s);
-// Several requests with the same tile width and bins in one launch: device arrays
-// d_reqs[n] (with K and L filled in) and d_first[n] (first workgroup of each).
+// kernel: KERNEL_* (AUTO picks); K: columns per workgroup (0 = default).
+// Returns threads = 0 when the shape cannot be launched (tile too large).
+Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
+                        const DeviceLimits &dev);
+hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s);
+// Several requests with the same kernel, tile, bins and precision in one launch:
+// device arrays d_reqs[n] (K, PC, CH, L filled in) and d_first[n] (first
+// workgroup of each).
 hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
-                              int threads, size_t lds, int precision, hipStream_t s);
+                              const Geometry &g, int precision, hipStream_t s);
+// Allow the kernels the device's full LDS per workgroup (once per device).
+hipError_t prepare_kernels(const DeviceLimits &dev);
 
 }  // namespace rtk

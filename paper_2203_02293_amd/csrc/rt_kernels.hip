@@ -41,7 +41,7 @@ namespace {
 // LDS chunk of interfaces reduced at once over bins
 __host__ __device__ constexpr int lds_budget() { return 60 * 1024; }
 
-constexpr int PC = 8;   // levels whose Planck edges are computed per barrier
+constexpr int PC = 8;   // lane kernel: levels whose Planck edges are computed per barrier
 
 __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 {
@@ -57,7 +57,7 @@ __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 // TOA, back-substitution from the BOA, bin sums, net flux and heating.
 // ---------------------------------------------------------------------------
 template <bool MIXED>
-__device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
+__device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int tile)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double smem[];
@@ -129,13 +129,15 @@ __device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
     edge_chunk(a.Tint, 0, 0, 1);
     const double Fboa = active ? double(kPI) * double(lane_B(0, a.Tint[c])) : 0.0;
 
-    LaneState st;
+    ElimState st = elim_top(0.0);
     double Fstar_b = 0.0;
     if (active) {
         Fstar_b = a.F_star[b];
-        st = lane_top(day, mu, Fstar_b, a.Ftoa ? a.Ftoa[(long long)c * NB + b] : 0.0);
+        st = elim_top(a.Ftoa ? a.Ftoa[(long long)c * NB + b] : 0.0);
     }
     const double inv_mu = day ? 1.0 / mu : 0.0;
+    const double muF = day ? mu * Fstar_b : 0.0;
+    double Fb_up = muF, tau = 0.0;   // beam at the current interface, tau_N = 0
     const double inv_eps2 = 1.0 / a.o.eps2;
     const long long LB = (long long)C * NB;
     const long long L = a.L;
@@ -172,14 +174,23 @@ __device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
                     nx_g = a.g0[idx];
                     nx_T = a.T[(long long)(i - 1) * C + c];
                 }
-                const BackRec rec = lane_layer<MIXED>(st, dt, w, g, Tl, day, mu, inv_mu, Fstar_b,
-                                                      B, Bup, a.o, inv_eps2, fl);
+                if (!(Tl > 0.0) || !isfinite(Tl)) fl |= F_INVALID;
+                double Fb_lo = 0.0;
+                if (day) {
+                    tau += dt;   // summed from the TOA, as the optical depth is defined
+                    Fb_lo = beam_at<MIXED>(muF, tau, inv_mu);
+                }
+                const Layer<R> Ly = layer_item<MIXED, R>(dt, w, g, day, mu, inv_mu, Fb_up, Fb_lo, B,
+                                                         Bup, a.o, inv_eps2, fl);
+                const BackRec rec = elim_step(st, double(Ly.t), double(Ly.r), double(Ly.omr),
+                                              double(Ly.A), double(Ly.Sup), double(Ly.Sdn));
                 double *sp = a.scratch + (long long)i * 5 * L + gl;
                 sp[0] = rec.G;
                 sp[L] = rec.H;
                 sp[2 * L] = rec.c;
                 sp[3 * L] = rec.d;
-                sp[4 * L] = rec.Fb;
+                sp[4 * L] = Fb_up;
+                Fb_up = Fb_lo;
             }
             Bup = B;
         }
@@ -189,7 +200,8 @@ __device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
     // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0, with F_dn_0 = c_0 F_up_0 + d_0
     double Fu = 0.0, Fd = 0.0, Fbi = 0.0;
     if (active) {
-        lane_boa(st, Fboa, Fu, Fd, Fbi);
+        elim_boa(st, Fboa, Fb_up, Fu, Fd);
+        Fbi = Fb_up;
         if (fl) atomicOr(&s_flag[kloc], fl);
     }
 
@@ -212,7 +224,7 @@ __device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
                         const double *sp = a.scratch + (long long)i * 5 * L + gl;
                         r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L]; r4 = sp[4 * L];
                     }
-                    lane_up(G, H, cj, dj, Fu, Fd);
+                    back_step(G, H, cj, dj, Fu, Fd);
                 }
                 const long long k = ((long long)i * C + c) * NB + b;
                 if (a.F_up_bin) a.F_up_bin[k] = Fu;
@@ -272,46 +284,444 @@ __device__ __forceinline__ void solve_tile(const SolveArgs &a, const int tile)
     }
 }
 
-// One request: workgroup = tile.
-template <bool MIXED>
-__global__ void __launch_bounds__(kMaxThreads) k_solve(const SolveArgs a)
+// ---------------------------------------------------------------------------
+// Layer kernel.  A workgroup holds K whole columns (T = K NB lanes) and walks
+// the levels from the TOA in chunks of PC.  Per chunk:
+//   (b) level items (level, lane): Planck bin radiance from the edge integrals
+//       and the direct beam from the optical depth summed down from the TOA;
+//   (c) layer items (layer, lane): coefficients and normalised sources, into
+//       LDS; the next chunk's dtau/w0/g0 are loaded meanwhile;
+//   (d) the T sweep threads run the FP64 elimination through the chunk and
+//       write the back-substitution records; the other threads compute the
+//       next chunk's Planck edge integrals and the beam bin sums.
+// Items of (b) and (c) are spread over all threads of the workgroup, so the
+// transcendental work of a chunk runs at full occupancy even when the grid
+// holds few (column, bin) lanes.  The back-substitution and the bin sums
+// follow as in the lane kernel.
+// ---------------------------------------------------------------------------
+struct LpLayout {
+    size_t flag, mu;                               // persistent
+    size_t F, in, tau, B, rec, rfl, edge, front;   // forward sweep
+    size_t red, fnet, back;                        // back-substitution (aliases the forward)
+    size_t total;
+};
+
+__host__ __device__ inline size_t lp_align(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline LpLayout lp_layout(int K, int NB, int PC, int CH, bool mixed)
 {
-    solve_tile<MIXED>(a, blockIdx.x);
+    const size_t T = (size_t)K * NB, rs = mixed ? 4 : 8;
+    LpLayout L;
+    size_t o = 0;
+    L.flag = o; o += lp_align(4 * (size_t)K);
+    L.mu = o;   o += lp_align(8 * (size_t)K);
+    const size_t base = o;
+    L.F = o;    o += lp_align(8 * (PC + 1) * T);          // beam, rows = levels, row 0 = chunk top
+    L.in = o;   o += lp_align(8 * 3 * PC * T);            // dtau, w0, g0 of the chunk's layers
+    L.tau = o;  o += lp_align(8 * 2 * T);                 // optical depth at the chunk top (2 buffers)
+    L.B = o;    o += lp_align(rs * (PC + 1) * T);         // Planck bin radiance, rows as F
+    L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
+    L.rfl = o;  o += lp_align(4 * PC * T);                // flags per layer
+    L.edge = o; o += lp_align(rs * PC * K * (NB + 1));    // Planck edge integrals
+    L.front = o;
+    size_t ob = base;
+    L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH interfaces
+    L.fnet = ob; ob += lp_align(8 * (size_t)K * (CH + 1));
+    L.back = ob;
+    L.total = L.front > L.back ? L.front : L.back;
+    return L;
 }
 
-// Several requests in one launch (serving): workgroup g belongs to the request
-// r with first[r] <= g < first[r+1]; all requests share the tile width.
 template <bool MIXED>
-__global__ void __launch_bounds__(kMaxThreads)
-k_solve_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
+__device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int tile)
 {
-    const int g = blockIdx.x;
+    using R = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double smem[];
+    char *lds = reinterpret_cast<char *>(smem);
+    const int NB = a.NB, K = a.K, C = a.C, N = a.N, PC = a.PC, CH = a.CH;
+    const int T = K * NB;
+    const int tid = threadIdx.x, W = blockDim.x;
+    const LpLayout Lo = lp_layout(K, NB, PC, CH, MIXED);
+    uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
+    double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [K]
+    double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
+    double *s_in = reinterpret_cast<double *>(lds + Lo.in);           // [3][PC][T]
+    double *s_tau = reinterpret_cast<double *>(lds + Lo.tau);         // [2][T]
+    R *s_B = reinterpret_cast<R *>(lds + Lo.B);                       // [PC+1][T]
+    R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
+    uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
+    R *s_edge = reinterpret_cast<R *>(lds + Lo.edge);                 // [PC][K][NB+1]
+    double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
+    double *s_fnet = reinterpret_cast<double *>(lds + Lo.fnet);       // [K][CH+1]
+
+    const int c0 = tile * K;                    // first column of the tile
+    const long long LB = (long long)C * NB;     // one layer of a [C][NB] plane
+    const long long toff = (long long)c0 * NB;  // lane 0 of the tile in such a plane
+    const long long L = a.L;
+    const double inv_eps2 = 1.0 / a.o.eps2;
+
+    // the sweep lane of this thread
+    const bool sweep = tid < T;
+    const int kl = sweep ? tid / NB : 0, bl = tid - kl * NB;
+    const bool active = sweep && (c0 + kl < C);
+    const long long gl = (long long)tile * T + tid;
+    uint32_t fl = 0u;
+
+    for (int kk = tid; kk < K; kk += W) {
+        const int cc = c0 + kk;
+        double mu = 0.0;
+        uint32_t f0 = 0u;
+        if (cc < C) {
+            mu = a.mu[cc];
+            if (!isfinite(mu)) f0 |= F_INVALID;
+            const double ti = a.Tint[cc];
+            if (!(ti >= 0.0) || !isfinite(ti)) f0 |= F_INVALID;
+        }
+        s_mu[kk] = mu;
+        s_flag[kk] = f0;
+    }
+
+    // Planck edge integrals of n levels lev0, lev0-1, ... (or of T_int) into
+    // edge rows 0..n-1, edge-major so a wavefront's lanes share one edge.
+    auto edges = [&](int lev0, int n, bool interior) {
+        const int per = K * (NB + 1);
+        for (int e = tid; e < n * per; e += W) {
+            const int q = e / per, rem = e - q * per;
+            const int ee = rem / K, kk = rem - ee * K;
+            const int cc = c0 + kk;
+            R v = R(0);
+            if (cc < C) {
+                const double Tv = interior ? a.Tint[cc] : a.T[(long long)(lev0 - q) * C + cc];
+                R x;
+                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
+                else x = a.c2_over_lam[ee] / Tv;
+                v = planck_edge<R>(x);
+            }
+            s_edge[(q * K + kk) * (NB + 1) + ee] = v;
+        }
+    };
+    // Bin radiance of (column kk, bin b) from edge row q at temperature Td.
+    auto bin_B = [&](int q, int kk, int b, double Td) -> R {
+        const R Tr = R(Td), T2 = Tr * Tr;
+        const R *row = s_edge + (q * K + kk) * (NB + 1);
+        R I = planck_combine<R>(row[b], row[b + 1]);
+        if constexpr (MIXED) {
+            const R iT = rcp(Tr);
+            const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
+            if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
+        }
+        return R(kPref) * T2 * T2 * I;
+    };
+    // Beam bin sums of n levels held in beam rows r0.. (level lev0 - q in row r0 + q).
+    auto beam_sums = [&](int r0, int lev0, int n) {
+        for (int task = tid; task < n * K; task += W) {
+            const int q = task / K, kk = task - q * K, cc = c0 + kk;
+            if (cc >= C) continue;
+            const double *row = s_F + (size_t)(r0 + q) * T + kk * NB;
+            double sb = 0.0;
+            for (int b = 0; b < NB; ++b) sb += row[b];
+            a.F_beam[(long long)(lev0 - q) * C + cc] = sb;
+        }
+    };
+
+    // dtau, w0, g0 of layers s-1 .. s-n into LDS rows 0..n-1
+    auto stage = [&](int s, int n) {
+        for (int e = tid; e < n * T; e += W) {
+            const int q = e / T, l = e - q * T;
+            double dt = 0.0, w = 0.0, g = 0.0;
+            if (c0 + l / NB < C) {
+                const long long idx = (long long)(s - 1 - q) * LB + toff + l;
+                dt = a.dtau[idx];
+                w = a.w0[idx];
+                g = a.g0[idx];
+            }
+            s_in[(0 * PC + q) * T + l] = dt;
+            s_in[(1 * PC + q) * T + l] = w;
+            s_in[(2 * PC + q) * T + l] = g;
+        }
+    };
+
+    // F_BOA = pi B_b(T_int) of the sweep lanes
+    edges(0, 1, true);
+    __syncthreads();
+    const double Fboa = active ? double(kPI) * double(bin_B(0, kl, bl, a.Tint[c0 + kl])) : 0.0;
+    __syncthreads();
+    // level N: Planck and the unattenuated beam, row 0
+    edges(N, 1, false);
+    __syncthreads();
+    for (int l = tid; l < T; l += W) {
+        const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
+        R B = R(0);
+        double Fb = 0.0;
+        if (cc < C) {
+            const double Tv = a.T[(long long)N * C + cc];
+            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+            B = bin_B(0, kk, b, Tv);
+            const double mu = s_mu[kk];
+            if (mu > 0.0) Fb = mu * a.F_star[b];
+        }
+        s_B[l] = B;
+        s_F[l] = Fb;
+        s_tau[l] = 0.0;
+    }
+    __syncthreads();
+    beam_sums(0, N, 1);
+    // inputs and edge integrals of the first chunk
+    stage(N, min(PC, N));
+    edges(N - 1, min(PC, N), false);
+    __syncthreads();
+
+    ElimState st = elim_top(0.0);
+    if (active && a.Ftoa) st = elim_top(a.Ftoa[toff + tid]);
+    int cur = 0;
+    for (int s = N; s > 0;) {
+        const int n = min(PC, s);          // layers s-1 .. s-n, levels s-1 .. s-n in rows 1..n
+        const int s2 = s - n, n2 = min(PC, s2);
+
+        // (b) level items
+        for (int e = tid; e < n * T; e += W) {
+            const int q = e / T, l = e - q * T;
+            const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
+            R B = R(0);
+            double Fb = 0.0;
+            if (cc < C) {
+                const double Tv = a.T[(long long)(s - 1 - q) * C + cc];
+                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+                B = bin_B(q, kk, b, Tv);
+                const double mu = s_mu[kk];
+                if (mu > 0.0) {
+                    double tau = s_tau[cur * T + l];
+                    for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
+                    Fb = beam_at<MIXED>(mu * a.F_star[b], tau, 1.0 / mu);
+                    if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
+                }
+            }
+            s_B[(q + 1) * T + l] = B;
+            s_F[(q + 1) * T + l] = Fb;
+        }
+        __syncthreads();
+
+        // (c) layer items.  Mixed: the next chunk's inputs are loaded first, into
+        // registers, and land in LDS in (d); FP64 items leave no registers for that.
+        double pf[2][3];
+        if constexpr (MIXED) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int e = tid + k * W;
+                pf[k][0] = pf[k][1] = pf[k][2] = 0.0;
+                if (e < n2 * T) {
+                    const int q = e / T, l = e - q * T;
+                    if (c0 + l / NB < C) {
+                        const long long idx = (long long)(s2 - 1 - q) * LB + toff + l;
+                        pf[k][0] = a.dtau[idx];
+                        pf[k][1] = a.w0[idx];
+                        pf[k][2] = a.g0[idx];
+                    }
+                }
+            }
+        }
+        for (int e = tid; e < n * T; e += W) {
+            const int q = e / T, l = e - q * T;
+            const int kk = l / NB;
+            uint32_t f = 0u;
+            Layer<R> Ly{};
+            if (c0 + kk < C) {
+                const double mu = s_mu[kk];
+                const bool day = mu > 0.0;
+                const double inv_mu = day ? 1.0 / mu : 0.0;
+                Ly = layer_item<MIXED, R>(s_in[(0 * PC + q) * T + l], s_in[(1 * PC + q) * T + l],
+                                          s_in[(2 * PC + q) * T + l], day, mu, inv_mu,
+                                          s_F[q * T + l], s_F[(q + 1) * T + l],
+                                          s_B[(q + 1) * T + l], s_B[q * T + l], a.o, inv_eps2, f);
+            }
+            R *rp = s_rec + (size_t)q * 6 * T + l;
+            rp[0] = Ly.t;
+            rp[T] = Ly.r;
+            rp[2 * T] = Ly.omr;
+            rp[3 * T] = Ly.A;
+            rp[4 * T] = Ly.Sup;
+            rp[5 * T] = Ly.Sdn;
+            s_rfl[q * T + l] = f;
+        }
+        __syncthreads();
+
+        // (d) elimination through the chunk (sweep threads); next chunk staged meanwhile
+        if (active) {
+            for (int q = 0; q < n; ++q) {
+                const R *rp = s_rec + (size_t)q * 6 * T + tid;
+                fl |= s_rfl[q * T + tid];
+                const BackRec rec = elim_step(st, double(rp[0]), double(rp[T]), double(rp[2 * T]),
+                                              double(rp[3 * T]), double(rp[4 * T]),
+                                              double(rp[5 * T]));
+                double *sp = a.scratch + (long long)(s - 1 - q) * 4 * L + gl;
+                sp[0] = rec.G;
+                sp[L] = rec.H;
+                sp[2 * L] = rec.c;
+                sp[3 * L] = rec.d;
+            }
+        }
+        beam_sums(1, s - 1, n);
+        for (int l = tid; l < T; l += W) {   // level s-n becomes the next chunk's top
+            s_B[l] = s_B[(size_t)n * T + l];
+            s_F[l] = s_F[(size_t)n * T + l];
+        }
+        if constexpr (MIXED) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int e = tid + k * W;
+                if (e < n2 * T) {
+                    const int q = e / T, l = e - q * T;
+                    s_in[(0 * PC + q) * T + l] = pf[k][0];
+                    s_in[(1 * PC + q) * T + l] = pf[k][1];
+                    s_in[(2 * PC + q) * T + l] = pf[k][2];
+                }
+            }
+        } else {
+            stage(s2, n2);
+        }
+        if (n2 > 0) edges(s2 - 1, n2, false);
+        cur ^= 1;
+        s = s2;
+        __syncthreads();
+    }
+
+    // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0 (row 0 holds level 0 now)
+    double Fu = 0.0, Fd = 0.0;
+    if (active) {
+        elim_boa(st, Fboa, s_F[tid], Fu, Fd);
+        if (fl) atomicOr(&s_flag[kl], fl);
+    }
+    __syncthreads();   // the bin-sum buffers alias the forward buffers
+
+    // back-substitution upward, bin sums in passes of CH interfaces; the next
+    // record is loaded one step ahead of its use
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    if (active) {
+        const double *sp = a.scratch + gl;
+        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L];
+    }
+    for (int i0 = 0; i0 <= N; i0 += CH) {
+        const int nch = min(CH, N + 1 - i0);
+        for (int ii = 0; ii < nch; ++ii) {
+            const int i = i0 + ii;
+            if (active) {
+                if (i > 0) {
+                    const double G = r0, H = r1, cj = r2, dj = r3;
+                    if (i < N) {
+                        const double *sp = a.scratch + (long long)i * 4 * L + gl;
+                        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L];
+                    }
+                    back_step(G, H, cj, dj, Fu, Fd);
+                }
+                const long long k = (long long)i * LB + toff + tid;
+                if (a.F_up_bin) a.F_up_bin[k] = Fu;
+                if (a.F_dn_bin) a.F_dn_bin[k] = Fd;
+                if (i == N && a.F_up_toa_bin) a.F_up_toa_bin[toff + tid] = Fu;
+            }
+            if (sweep) {
+                s_red[(0 * CH + ii) * T + tid] = Fu;
+                s_red[(1 * CH + ii) * T + tid] = Fd;
+            }
+        }
+        __syncthreads();
+        for (int task = tid; task < K * CH; task += W) {
+            const int kk = task / CH, ii = task - kk * CH;
+            const int cc = c0 + kk;
+            if (ii >= nch || cc >= C) continue;
+            double su = 0.0, sd = 0.0;
+            const double *ru = s_red + (0 * CH + ii) * T + kk * NB;
+            const double *rd = s_red + (1 * CH + ii) * T + kk * NB;
+            for (int bb = 0; bb < NB; ++bb) {
+                su += ru[bb];
+                sd += rd[bb];
+            }
+            const long long o = (long long)(i0 + ii) * C + cc;
+            const double fn = su - sd - a.F_beam[o];   // written by this workgroup above
+            a.F_up[o] = su;
+            a.F_dn[o] = sd;
+            a.F_net[o] = fn;
+            s_fnet[kk * (CH + 1) + ii + 1] = fn;
+            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
+        }
+        __syncthreads();
+        // heating of the layer below each interface of the pass
+        for (int task = tid; task < K * CH; task += W) {
+            const int kk = task / CH, ii = task - kk * CH;
+            const int cc = c0 + kk;
+            const int i = i0 + ii;
+            if (ii >= nch || cc >= C || i < 1) continue;
+            const double dp = a.p[(long long)(i - 1) * C + cc] - a.p[(long long)i * C + cc];
+            if (!(dp > 0.0)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+            const double qh =
+                a.o.gravity * (s_fnet[kk * (CH + 1) + ii] - s_fnet[kk * (CH + 1) + ii + 1]) / dp;
+            a.heat[(long long)(i - 1) * C + cc] = qh;
+            if (a.dTdt) a.dTdt[(long long)(i - 1) * C + cc] = qh / a.o.cp;
+        }
+        __syncthreads();
+        for (int kk = tid; kk < K; kk += W) s_fnet[kk * (CH + 1)] = s_fnet[kk * (CH + 1) + nch];
+        __syncthreads();
+    }
+    for (int kk = tid; kk < K; kk += W) {
+        const int cc = c0 + kk;
+        if (cc < C && a.flags) a.flags[cc] = s_flag[kk];
+    }
+}
+
+// Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
+// three wavefronts per SIMD can hold; the FP32 items fit four.
+__host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ? 1024 : 768; }
+
+// Workgroup of request r with first[r] <= g < first[r+1] (batched launches).
+__device__ __forceinline__ int batch_slot(const int *first, int n, int g)
+{
     int lo = 0, hi = n - 1;
-    while (lo < hi) {   // last r with first[r] <= g
+    while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (first[mid] <= g) lo = mid;
         else hi = mid - 1;
     }
-    solve_tile<MIXED>(reqs[lo], g - first[lo]);
+    return lo;
 }
 
-}  // namespace
-
-int default_cols_per_block(int C, int NB)
+template <bool MIXED>
+__global__ void __launch_bounds__(kMaxLaneThreads) k_solve_lane(const SolveArgs a)
 {
-    int K = 256 / NB;
-    if (K < 1) K = 1;
-    if (K > C) K = C;
-    return K;
+    solve_tile_lane<MIXED>(a, blockIdx.x);
 }
 
-Geometry solve_geometry(int C, int NB, int K)
+template <bool MIXED>
+__global__ void __launch_bounds__(kMaxLaneThreads)
+k_solve_lane_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
 {
-    Geometry g;
-    g.K = K > 0 ? K : default_cols_per_block(C, NB);
+    const int r = batch_slot(first, n, blockIdx.x);
+    solve_tile_lane<MIXED>(reqs[r], blockIdx.x - first[r]);
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(layer_max_threads(MIXED)) k_solve_layer(const SolveArgs a)
+{
+    solve_tile_layer<MIXED>(a, blockIdx.x);
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(layer_max_threads(MIXED))
+k_solve_layer_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
+{
+    const int r = batch_slot(first, n, blockIdx.x);
+    solve_tile_layer<MIXED>(reqs[r], blockIdx.x - first[r]);
+}
+
+int round64(int x) { return (x + 63) / 64 * 64; }
+
+Geometry lane_geometry(int C, int NB, int K)
+{
+    Geometry g{};
+    g.kernel = KERNEL_LANE;
+    g.K = K > 0 ? K : std::max(1, 256 / NB);
     if (g.K > C) g.K = C;
-    int lanes = g.K * NB;
-    g.threads = ((lanes + 63) / 64) * 64;
+    const int lanes = g.K * NB;
+    if (lanes > kMaxLaneThreads) return Geometry{};
+    g.threads = round64(lanes);
     g.blocks = (C + g.K - 1) / g.K;
     g.lanes = (long long)g.blocks * g.threads;
     const int ch = chunk_for(g.threads, g.K, NB);
@@ -320,34 +730,121 @@ Geometry solve_geometry(int C, int NB, int K)
     return g;
 }
 
-size_t solve_scratch_bytes(int C, int N, int NB, int K)
+// Levels per chunk: the largest work per barrier that fits LDS, with the
+// items of a chunk filling whole rounds of the workgroup (at most two).
+Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev)
 {
-    Geometry g = solve_geometry(C, NB, K);
-    return (size_t)N * 5 * (size_t)g.lanes * sizeof(double);
+    Geometry g{};
+    g.kernel = KERNEL_LAYER;
+    if (K <= 0) {
+        const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
+        K = (C + n_cu - 1) / n_cu;             // about one workgroup per compute unit
+        K = std::max(1, std::min(K, layer_max_threads(mixed) / NB));
+    }
+    if (K > C) K = C;
+    const int T = K * NB;
+    if (T > kMaxTileLanes) return Geometry{};
+    const int wmax = layer_max_threads(mixed);
+    if (T > wmax) return Geometry{};
+    double best = -1.0;
+    for (int pc = 1; pc <= 8; ++pc) {
+        if (pc * T > 2 * wmax) break;
+        const LpLayout lo = lp_layout(K, NB, pc, 1, mixed);
+        if (lo.total > dev.lds) break;
+        int W = std::min(wmax, round64(pc * T));
+        W = std::max(W, round64(T));
+        const int rounds = (pc * T + W - 1) / W;
+        const double eff = double(pc * T) / (double(rounds) * W);
+        const double score = eff * (1.0 - 0.15 / pc);
+        if (score > best) {
+            best = score;
+            g.PC = pc;
+            g.threads = W;
+        }
+    }
+    if (best < 0.0) return Geometry{};
+    // interfaces per bin-sum pass: as many as fit in the forward sweep's bytes
+    const LpLayout lo = lp_layout(K, NB, g.PC, 1, mixed);
+    int ch = 1;
+    while (ch < 16 && lp_layout(K, NB, g.PC, ch + 1, mixed).total <= lo.total) ++ch;
+    g.CH = ch;
+    g.K = K;
+    g.blocks = (C + K - 1) / K;
+    g.lanes = (long long)g.blocks * T;
+    g.lds = lp_layout(K, NB, g.PC, g.CH, mixed).total;
+    return g;
 }
 
-hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
-                              int threads, size_t lds, int precision, hipStream_t s)
+}  // namespace
+
+Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
+                        const DeviceLimits &dev)
 {
-    if (precision == 1)
-        hipLaunchKernelGGL(k_solve_batch<true>, dim3(total_blocks), dim3(threads), lds, s, d_reqs,
-                           d_first, n);
-    else
-        hipLaunchKernelGGL(k_solve_batch<false>, dim3(total_blocks), dim3(threads), lds, s, d_reqs,
-                           d_first, n);
+    Geometry g = (kernel == KERNEL_LANE) ? lane_geometry(C, NB, K)
+                                         : layer_geometry(C, NB, K, precision == 1, dev);
+    if (g.threads > 0)
+        g.scratch = (size_t)N * (g.kernel == KERNEL_LANE ? 5 : 4) * (size_t)g.lanes * sizeof(double);
+    return g;
+}
+
+hipError_t prepare_kernels(const DeviceLimits &dev)
+{
+    const int bytes = (int)dev.lds;
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer_batch<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer_batch<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s)
+{
+    SolveArgs b = a;
+    b.K = g.K;
+    b.PC = g.PC;
+    b.CH = g.CH;
+    b.L = g.lanes;
+    const bool mixed = precision == 1;
+    if (g.kernel == KERNEL_LANE) {
+        if (mixed)
+            hipLaunchKernelGGL(k_solve_lane<true>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+        else
+            hipLaunchKernelGGL(k_solve_lane<false>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL(k_solve_layer<true>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+        else
+            hipLaunchKernelGGL(k_solve_layer<false>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs &a, int precision, hipStream_t s)
+hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
+                              const Geometry &g, int precision, hipStream_t s)
 {
-    Geometry g = solve_geometry(a.C, a.NB, a.K);
-    SolveArgs b = a;
-    b.K = g.K;
-    b.L = g.lanes;
-    if (precision == 1)
-        hipLaunchKernelGGL(k_solve<true>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
-    else
-        hipLaunchKernelGGL(k_solve<false>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+    const bool mixed = precision == 1;
+    if (g.kernel == KERNEL_LANE) {
+        if (mixed)
+            hipLaunchKernelGGL(k_solve_lane_batch<true>, dim3(total_blocks), dim3(g.threads), g.lds,
+                               s, d_reqs, d_first, n);
+        else
+            hipLaunchKernelGGL(k_solve_lane_batch<false>, dim3(total_blocks), dim3(g.threads),
+                               g.lds, s, d_reqs, d_first, n);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL(k_solve_layer_batch<true>, dim3(total_blocks), dim3(g.threads),
+                               g.lds, s, d_reqs, d_first, n);
+        else
+            hipLaunchKernelGGL(k_solve_layer_batch<false>, dim3(total_blocks), dim3(g.threads),
+                               g.lds, s, d_reqs, d_first, n);
+    }
     return hipGetLastError();
 }
 

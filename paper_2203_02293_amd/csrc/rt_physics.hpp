@@ -251,10 +251,11 @@ struct Layer {
 // Coefficients and normalised sources of one layer (see the file header).
 // Differences near 1 (1 - w0, E - w0, 1 - w0 g0) arrive already formed in
 // FP64 by the caller: in FP32 they would lose up to ~2 digits for cloud layers.
+// Fup and Flo are the direct beam at the layer's top and bottom interfaces.
 template <class R>
 __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R omw, R Ew, R om,
                                                      bool day, R mu, R inv_mu, R Dres,
-                                                     bool guard, R f, R beta, R Blo, R Bup,
+                                                     bool guard, R Fup, R Flo, R Blo, R Bup,
                                                      bool iso, R inv_eps2, Layer<R> &L)
 {
     const R one = R(1), half = R(0.5);
@@ -300,11 +301,13 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
             R P = c1 * rcp(Dd);
             R Gp = half * (P * (ik - mu) + Qc);
             R Gm = -half * (P * (ik + mu) + Qc);
-            sb_up = f * (r * Gm - Gp * (one - t * beta));
-            sb_dn = f * (r * beta * Gp - Gm * (beta - t));
+            // f [r G- - G+ (1 - t beta)] and f [r beta G+ - G- (beta - t)], f beta = Flo
+            sb_up = r * Gm * Fup - Gp * (Fup - t * Flo);
+            sb_dn = r * Gp * Flo - Gm * (Flo - t * Fup);
         } else {
             // resonance-regularised: X, Yh = Y (a - lambda) are finite at mu lambda = 1
             R a = inv_mu;
+            R beta = exp_em1(-dtau * inv_mu).e;
             R i1s = rcp(one + s);
             R X = (Qc - c1 * ik * rcp(one + lm)) * i1s;
             R Yh = (Qc * (a - lam) - c1 * a * ik) * i1s;
@@ -313,8 +316,8 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
             R rho = zm * rcp(zp);
             R iom = (zp * zp) * rcp(s * den);       // 1 / (1 - rho^2 T^2)
             R obt = -exp_em1(-(a + lam) * dtau).em1; // 1 - beta T
-            sb_up = f * (rho * Tr * Z - X * obt) * iom;
-            sb_dn = f * (rho * Tr * X * obt - Z) * iom;
+            sb_up = Fup * (rho * Tr * Z - X * obt) * iom;
+            sb_dn = Fup * (rho * Tr * X * obt - Z) * iom;
         }
         Sup += sb_up;
         Sdn += sb_dn;
@@ -323,43 +326,27 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
     L.Sdn = Sdn;
 }
 
-// ---------------------------------------------------------------------------
-// One lane's sweep: state carried from the TOA down, one layer per call.
-// ---------------------------------------------------------------------------
-struct LaneState {
-    double c, eps, d;   // F_dn_i = c F_up_i + d, eps = 1 - c (no subtraction)
-    double Fb, tau;     // direct beam and optical depth at the current interface
-};
-
-// What the back-substitution needs of layer j: F_up_{j+1} = G F_up_j + H,
-// F_dn_{j+1} = c F_up_{j+1} + d, beam at interface j+1.
-struct BackRec {
-    double G, H, c, d, Fb;
-};
-
-__host__ __device__ __forceinline__ LaneState lane_top(bool day, double mu, double Fstar_b,
-                                                       double F_toa)
+// Direct beam at an interface of optical depth tau below the TOA (Section
+// 2.2.1, Beer's law), mu = -mu_star > 0.  The mixed path takes the
+// exponential in FP32 of the FP64 optical depth.
+template <bool MIXED>
+__host__ __device__ __forceinline__ double beam_at(double mu_Fstar, double tau, double inv_mu)
 {
-    LaneState s;
-    s.c = 0.0;          // nothing above the TOA reflects
-    s.eps = 1.0;
-    s.d = F_toa;        // F_dn_N = F_TOA (Fig. 5 caption)
-    s.Fb = day ? mu * Fstar_b : 0.0;
-    s.tau = 0.0;
-    return s;
+    if constexpr (MIXED) return mu_Fstar * double(exp_em1(float(-tau * inv_mu)).e);
+    else return mu_Fstar * exp_em1(-tau * inv_mu).e;
 }
 
-// Layer j between interfaces j and j+1, given B at both ends (Section 2.2.1,
-// Appendix B), then one step of Thomas forward elimination in FP64 (Section 2.2.2).
+// Layer j between interfaces j and j+1 (Section 2.2.1, Appendix B): the
+// paper's branch decisions in FP64, the coefficients in R.  Fb_up and Fb_lo
+// are the beam at the top and bottom interfaces; Blo, Bup the Planck bin
+// radiances there.
 template <bool MIXED, class R>
-__host__ __device__ __forceinline__ BackRec lane_layer(LaneState &st, double dt, double w,
-                                                       double g, double Tl, bool day, double mu,
-                                                       double inv_mu, double Fstar_b, R Blo,
-                                                       R Bup, const Opts &o, double inv_eps2,
-                                                       uint32_t &fl)
+__host__ __device__ __forceinline__ Layer<R> layer_item(double dt, double w, double g, bool day,
+                                                        double mu, double inv_mu, double Fb_up,
+                                                        double Fb_lo, R Blo, R Bup, const Opts &o,
+                                                        double inv_eps2, uint32_t &fl)
 {
-    if (!(dt >= 0.0) || !isfinite(dt) || !(w >= 0.0 && w <= 1.0) || !(g > -1.0 && g < 1.0) ||
-        !(Tl > 0.0) || !isfinite(Tl))
+    if (!(dt >= 0.0) || !isfinite(dt) || !(w >= 0.0 && w <= 1.0) || !(g > -1.0 && g < 1.0))
         fl |= F_INVALID;
     const double E = efit_exact(w, g, o, fl);
     bool guard = false;
@@ -371,54 +358,67 @@ __host__ __device__ __forceinline__ BackRec lane_layer(LaneState &st, double dt,
     }
     const bool iso = !o.noniso || dt < o.e_tau;
     if (o.noniso && dt < o.e_tau) fl |= F_ETAU;
-
-    double Fb_lo = 0.0;
-    R beta = R(0);
-    if (day) {
-        if constexpr (MIXED) {
-            // optical depth summed in FP64; exponentials in FP32
-            st.tau += dt;
-            Fb_lo = mu * Fstar_b * double(exp_em1(float(-st.tau * inv_mu)).e);
-            beta = exp_em1(float(-dt * inv_mu)).e;
-        } else {
-            beta = exp_em1(-dt * inv_mu).e;
-            Fb_lo = st.Fb * beta;
-        }
-    }
     Layer<R> Ly;
     layer_terms<R>(R(dt), R(w), R(g), R(E), R(1.0 - w), R(E - w), R(1.0 - w * g), day, R(mu),
-                   R(inv_mu), R(D), guard, R(st.Fb), beta, Blo, Bup, iso, R(inv_eps2), Ly);
-    const double t = Ly.t, r = Ly.r, omr = Ly.omr, A = Ly.A;
-    const double Sup = Ly.Sup, Sdn = Ly.Sdn;
+                   R(inv_mu), R(D), guard, R(Fb_up), R(Fb_lo), Blo, Bup, iso, R(inv_eps2), Ly);
+    return Ly;
+}
+
+// ---------------------------------------------------------------------------
+// Thomas elimination from the TOA (Section 2.2.2) on the normalised relations
+//   F_up_{j+1} = t F_up_j + r F_dn_{j+1} + S_up,  F_dn_j = t F_dn_{j+1} + r F_up_j + S_dn.
+// State at interface i: F_dn_i = c F_up_i + d, with eps = 1 - c carried
+// without subtraction.  Always FP64.
+// ---------------------------------------------------------------------------
+struct ElimState {
+    double c, eps, d;
+};
+
+// What the back-substitution needs of layer j: F_up_{j+1} = G F_up_j + H,
+// F_dn_{j+1} = c F_up_{j+1} + d.
+struct BackRec {
+    double G, H, c, d;
+};
+
+__host__ __device__ __forceinline__ ElimState elim_top(double F_toa)
+{
+    ElimState s;
+    s.c = 0.0;      // nothing above the TOA reflects
+    s.eps = 1.0;
+    s.d = F_toa;    // F_dn_N = F_TOA
+    return s;
+}
+
+__host__ __device__ __forceinline__ BackRec elim_step(ElimState &st, double t, double r,
+                                                      double omr, double A, double Sup,
+                                                      double Sdn)
+{
     const double inv = rcp(omr + r * st.eps);   // 1 / (1 - r c_{j+1})
     BackRec rec;
     rec.G = t * inv;
     rec.H = (r * st.d + Sup) * inv;
     rec.c = st.c;
     rec.d = st.d;
-    rec.Fb = st.Fb;
     const double cn = r + t * t * st.c * inv;
     const double en = (A * (omr + t) + st.eps * (r * omr + t * t)) * inv;
     const double dn = Sdn + t * (st.d + st.c * Sup) * inv;
     st.c = cn;
     st.eps = en;
     st.d = dn;
-    st.Fb = Fb_lo;
     return rec;
 }
 
 // BOA condition F_up_0 - F_dn_0 = F_BOA + F_beam_0 closes the elimination.
-__host__ __device__ __forceinline__ void lane_boa(const LaneState &st, double F_boa, double &Fu,
-                                                  double &Fd, double &Fb0)
+__host__ __device__ __forceinline__ void elim_boa(const ElimState &st, double F_boa, double Fb0,
+                                                  double &Fu, double &Fd)
 {
-    Fu = (F_boa + st.Fb + st.d) / st.eps;
+    Fu = (F_boa + Fb0 + st.d) / st.eps;
     Fd = st.c * Fu + st.d;
-    Fb0 = st.Fb;
 }
 
 // One back-substitution step from interface j to j+1.
-__host__ __device__ __forceinline__ void lane_up(double G, double H, double c, double d,
-                                                 double &Fu, double &Fd)
+__host__ __device__ __forceinline__ void back_step(double G, double H, double c, double d,
+                                                   double &Fu, double &Fd)
 {
     Fu = G * Fu + H;
     Fd = c * Fu + d;

@@ -17,6 +17,7 @@ LIB_PATH = pathlib.Path(__file__).resolve().parent / "librt_mi355x.so"
 RT_OK, RT_PENDING = 0, 1
 RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EDOMAIN, RT_EBUSY, RT_ENOTFOUND = -1, -2, -3, -4, -5, -6
 RT_FP64, RT_MIXED = 0, 1
+RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER = 0, 1, 2
 FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
 
 #: every symbol include/rt.h declares
@@ -35,7 +36,8 @@ class RtConfig(ct.Structure):
 
 class RtRequest(ct.Structure):
     _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("precision", ct.c_int32),
-                ("cols_per_block", ct.c_int32)] + [
+                ("cols_per_block", ct.c_int32), ("kernel", ct.c_int32),
+                ("reserved", ct.c_int32)] + [
         (n, ct.c_void_p) for n in (
             "p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "F_toa",
             "F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
@@ -186,15 +188,18 @@ class Solver:
         return out
 
     def request(self, inp: dict, out: dict, precision: int = RT_FP64,
-                cols_per_block: int | None = None) -> RtRequest:
+                cols_per_block: int | None = None, kernel: int | None = None) -> RtRequest:
         """Build an rt_request from device tensors (shapes as in include/rt.h).
-        ``cols_per_block`` None: take the tuned tile for this shape (0 if none)."""
+        ``cols_per_block`` and ``kernel`` None: the tuned choice for this shape
+        (library defaults if none); an explicit tile with no kernel: RT_KERNEL_AUTO."""
         C = int(inp["mu_star"].shape[0])
         N = int(inp["dtau"].shape[0])
-        if cols_per_block is None:
-            cols_per_block = tuned_cols_per_block(self.n_bins, precision, C, N)
+        if cols_per_block is None and kernel is None:
+            kernel, cols_per_block = tuned_launch(self.n_bins, precision, C, N)
         r = RtRequest()
-        r.n_cols, r.n_layers, r.precision, r.cols_per_block = C, N, precision, cols_per_block
+        r.n_cols, r.n_layers, r.precision = C, N, precision
+        r.cols_per_block = cols_per_block or 0
+        r.kernel = kernel or RT_KERNEL_AUTO
 
         def ptr(t):
             if t is None:
@@ -210,20 +215,21 @@ class Solver:
         return r
 
     def solve(self, inp: dict, precision: int = RT_FP64, per_bin: bool = False,
-              out: dict | None = None, stream=None, cols_per_block: int | None = None) -> dict:
+              out: dict | None = None, stream=None, cols_per_block: int | None = None,
+              kernel: int | None = None) -> dict:
         """Stream-ordered solve on the current (or given) torch stream."""
         import torch
         C, N = int(inp["mu_star"].shape[0]), int(inp["dtau"].shape[0])
         if out is None:
             out = self.outputs(C, N, per_bin)
-        req = self.request(inp, out, precision, cols_per_block)
+        req = self.request(inp, out, precision, cols_per_block, kernel)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         rt_solve_fluxes(self.h, req, s.cuda_stream)
         return out
 
     def submit(self, inp: dict, out: dict, precision: int = RT_FP64,
-               cols_per_block: int | None = None) -> int:
-        return rt_submit(self.h, self.request(inp, out, precision, cols_per_block))
+               cols_per_block: int | None = None, kernel: int | None = None) -> int:
+        return rt_submit(self.h, self.request(inp, out, precision, cols_per_block, kernel))
 
     def poll(self, ticket: int) -> int:
         return rt_poll(self.h, ticket)
@@ -239,23 +245,24 @@ TUNING_PATH = pathlib.Path(__file__).resolve().parent / "tuning.json"
 _tuning = None
 
 
-def tuned_cols_per_block(n_bins: int, precision: int, n_cols: int, n_layers: int) -> int:
-    """Tile width chosen by the autotuner (``tune.py``) for the nearest measured
-    shape with the same bins and precision; 0 (library default) if none."""
+def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int) -> tuple[int, int]:
+    """(kernel, tile width) chosen by the autotuner (``tune.py``) for the nearest
+    measured shape with the same bins and precision; (0, 0) = library defaults."""
     global _tuning
     if _tuning is None:
         import json
         _tuning = json.loads(TUNING_PATH.read_text())["entries"] if TUNING_PATH.exists() else []
-    best, dist = 0, None
+    best, dist = (0, 0), None
     for e in _tuning:
         if e["n_bins"] != n_bins or e["precision"] != precision:
             continue
         d = abs(np.log(e["n_cols"] / n_cols)) + abs(np.log(e["n_layers"] / n_layers))
         if dist is None or d < dist:
-            best, dist = e["cols_per_block"], d
-    if best * n_bins > 512 or best > n_cols:
-        return 0
-    return best
+            best, dist = (e.get("kernel", 0), e["cols_per_block"]), d
+    kernel, K = best
+    if K > n_cols:
+        K = 0
+    return kernel, K
 
 
 def to_device(work: dict, device: int = 0) -> dict:

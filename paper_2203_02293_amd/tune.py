@@ -1,9 +1,9 @@
-"""Autotuner of the solve kernel's tile (columns per workgroup).
+"""Autotuner of the solve launch: kernel (lane or layer) and tile width.
 
 For each representative shape (columns, layers, bins) and precision it times
-rt_solve_fluxes with every admissible tile width K (K * bins <= 512) and
+rt_solve_fluxes with each kernel and every admissible tile width K and
 records the fastest in ``tuning.json`` next to this file.  The binding
-(``rt.tuned_cols_per_block``) picks the entry nearest to a request's shape.
+(``rt.tuned_launch``) picks the entry nearest to a request's shape.
 
     python -m paper_2203_02293_amd.tune [--quick]
 """
@@ -25,19 +25,30 @@ SHAPES = [  # (columns, layers, bins): GCM size, serving mix corners, high resol
 ]
 
 
-def candidates(nb: int, n_cols: int) -> list[int]:
-    ks = [k for k in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32) if k * nb <= 512 and k <= n_cols]
-    return ks or [1]
+def candidates(nb: int, n_cols: int) -> list[tuple[int, int]]:
+    """(kernel, K) pairs: the layer kernel's default tile and a spread around it,
+    and the lane kernel's tiles (K * bins <= 512)."""
+    out = [(rt.RT_KERNEL_LAYER, 0)]
+    out += [(rt.RT_KERNEL_LAYER, k) for k in (1, 2, 3, 4, 6, 8, 10, 11, 12, 16, 24, 32)
+            if k * nb <= 1024 and k <= n_cols]
+    out += [(rt.RT_KERNEL_LANE, k) for k in (1, 2, 4, 8, 16)
+            if k * nb <= 512 and k <= n_cols]
+    return out
 
 
-def time_one(s, inp, out, precision, k, reps, torch):
-    for _ in range(3):
-        s.solve(inp, precision=precision, out=out, cols_per_block=k)
+def time_one(s, inp, out, precision, cand, reps, torch):
+    kernel, k = cand
+    try:
+        s.solve(inp, precision=precision, out=out, cols_per_block=k, kernel=kernel)
+    except rt.RtError:
+        return None    # tile does not fit this kernel (LDS)
+    for _ in range(2):
+        s.solve(inp, precision=precision, out=out, cols_per_block=k, kernel=kernel)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        s.solve(inp, precision=precision, out=out, cols_per_block=k)
+        s.solve(inp, precision=precision, out=out, cols_per_block=k, kernel=kernel)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -59,15 +70,21 @@ def main(argv=None):
         inp = rt.to_device(w)
         out = s.outputs(C, N)
         for prec in (rt.RT_FP64, rt.RT_MIXED):
-            times = {k: time_one(s, inp, out, prec, k, args.reps, torch) for k in candidates(NB, C)}
+            times = {}
+            for cand in candidates(NB, C):
+                t = time_one(s, inp, out, prec, cand, args.reps, torch)
+                if t is not None:
+                    times[cand] = t
             best = min(times, key=times.get)
             entries.append(dict(n_cols=C, n_layers=N, n_bins=NB, precision=prec,
-                                cols_per_block=best, ms=times[best]))
+                                kernel=best[0], cols_per_block=best[1], ms=times[best]))
+            name = {rt.RT_KERNEL_LANE: "lane", rt.RT_KERNEL_LAYER: "layer"}
             report.append(dict(shape=[C, N, NB], precision=prec,
-                               ms={str(k): round(v, 4) for k, v in times.items()}, best=best))
+                               ms={f"{name[kk]}:{k}": round(v, 4) for (kk, k), v in times.items()},
+                               best=[name[best[0]], best[1]]))
             print(f"[tune] {C}x{N}x{NB} prec={prec}: " +
-                  " ".join(f"K={k}:{v:.3f}ms" for k, v in times.items()) + f" -> {best}",
-                  file=sys.stderr, flush=True)
+                  " ".join(f"{name[kk]}:K={k}:{v:.3f}ms" for (kk, k), v in times.items()) +
+                  f" -> {name[best[0]]}:{best[1]}", file=sys.stderr, flush=True)
         s.close()
         del inp, out
         torch.cuda.empty_cache()

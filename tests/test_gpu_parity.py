@@ -42,14 +42,20 @@ def rt(torch):
     return r
 
 
-def gpu_solve(rt, torch, w, precision, per_bin=False, opts=None, F_toa=None):
+KERNELS = [1, 2]               # RT_KERNEL_LANE, RT_KERNEL_LAYER
+KERNEL_IDS = ["lane", "layer"]
+
+
+def gpu_solve(rt, torch, w, precision, per_bin=False, opts=None, F_toa=None, kernel=None,
+              cols_per_block=None):
     o = opts or O.Options()
     s = rt.Solver(w["lambda_edges"], w["F_star"], improved=o.improved, noniso=o.noniso,
                   e_clamp=o.e_clamp, eps2=o.eps2, e_tau=o.e_tau, g_guard=o.g_guard)
     inp = rt.to_device(w)
     if F_toa is not None:
         inp["F_toa"] = torch.from_numpy(np.ascontiguousarray(F_toa)).cuda()
-    out = s.solve(inp, precision=precision, per_bin=per_bin)
+    out = s.solve(inp, precision=precision, per_bin=per_bin, kernel=kernel,
+                  cols_per_block=cols_per_block)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items()}
     res["flags"] = res["flags"].view(np.uint32)
@@ -73,43 +79,47 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
 @pytest.mark.parametrize("name,shape", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("mode", ["improved_noniso", "regular_noniso", "improved_iso"])
-def test_small_fp64_and_mixed(rt, torch, name, shape, mode):
-    print(f"\n[parity] {name} {shape} {mode}", flush=True)
+def test_small_fp64_and_mixed(rt, torch, name, shape, mode, kernel):
+    print(f"\n[parity] {name} {shape} {mode} kernel={kernel}", flush=True)
     w = small(**shape)
     opts = O.Options(improved=int(mode.startswith("improved")), noniso=int("noniso" in mode))
     ref = O.solve(w, opts, per_bin=True, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
-        out = gpu_solve(rt, torch, w, prec, per_bin=True, opts=opts)
+        out = gpu_solve(rt, torch, w, prec, per_bin=True, opts=opts, kernel=kernel)
         e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
 
-@pytest.mark.parametrize("cfg", ["cfg0"])
-def test_cfg0_full(rt, torch, cfg):
-    w = synth.make(cfg)
-    print(f"\n[parity] {cfg} full {w['n_cols']}x{w['n_layers']}x{w['n_bins']}", flush=True)
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_cfg0_full(rt, torch, kernel):
+    w = synth.make("cfg0")
+    print(f"\n[parity] cfg0 full {w['n_cols']}x{w['n_layers']}x{w['n_bins']} kernel={kernel}",
+          flush=True)
     ref = O.solve(w, per_bin=True, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
-        out = gpu_solve(rt, torch, w, prec, per_bin=True)
+        out = gpu_solve(rt, torch, w, prec, per_bin=True, kernel=kernel)
         e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
 
-def test_cfg1_sampled(rt, torch):
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_cfg1_sampled(rt, torch, kernel):
     """GCM size 2562 x 40 x 30 solved whole on the GPU; 128 columns (day,
     night, cloud, terminator) checked against the oracle one by one."""
     w = synth.make("cfg1")
-    print(f"\n[parity] cfg1 full {w['n_cols']}x{w['n_layers']}x{w['n_bins']}", flush=True)
+    print(f"\n[parity] cfg1 full {w['n_cols']}x{w['n_layers']}x{w['n_bins']} kernel={kernel}",
+          flush=True)
     cols = np.unique(np.concatenate([np.linspace(0, w["n_cols"] - 1, 96).astype(int),
                                      np.argsort(np.abs(w["mu_star"]))[:32]]))
     ws = subset(w, cols)
     ref = O.solve(ws, extended=True)
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
-        out = gpu_solve(rt, torch, w, prec)
+        out = gpu_solve(rt, torch, w, prec, kernel=kernel)
         e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec], cols=cols)
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
@@ -151,13 +161,14 @@ def edge_workload():
     return w
 
 
-def test_edge_cases(rt, torch):
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_edge_cases(rt, torch, kernel):
     w = edge_workload()
     ref = O.solve(w, per_bin=True, extended=True)
     assert ref["flags"][3] & O.F_GUARD and not ref["flags"][4] & O.F_GUARD
     assert ref["flags"][5] & O.F_ECLAMP and ref["flags"][1] & O.F_ETAU
     for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
-        out = gpu_solve(rt, torch, w, prec, per_bin=True)
+        out = gpu_solve(rt, torch, w, prec, per_bin=True, kernel=kernel)
         e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"], ref["flags"])
@@ -199,24 +210,39 @@ def test_conservative_scattering_w0_one(rt, torch):
     assert_close(out, ref, w["p_iface"], 1e-9, keys=("F_up", "F_dn", "F_beam"))
 
 
-def test_invalid_inputs_flagged(rt, torch):
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_invalid_inputs_flagged(rt, torch, kernel):
     w = small(C=5, N=6, NB=4, seed=51)
     w = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in w.items()}
     w["w0"][2, 1, 0] = 1.5
     w["T_iface"][3, 2] = -5.0
     w["p_iface"][4, 3] = w["p_iface"][3, 3] * 2
-    out = gpu_solve(rt, torch, w, rt.RT_FP64)
+    out = gpu_solve(rt, torch, w, rt.RT_FP64, kernel=kernel)
     assert out["flags"][1] & O.F_INVALID and out["flags"][2] & O.F_INVALID
     assert out["flags"][3] & O.F_INVALID
     assert not out["flags"][0] & O.F_INVALID and not out["flags"][4] & O.F_INVALID
 
 
-def test_repeat_is_bitwise_identical(rt, torch):
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_repeat_is_bitwise_identical(rt, torch, kernel):
     w = small(C=40, N=12, NB=30, seed=61)
-    a = gpu_solve(rt, torch, w, rt.RT_FP64, per_bin=True)
-    b = gpu_solve(rt, torch, w, rt.RT_FP64, per_bin=True)
+    a = gpu_solve(rt, torch, w, rt.RT_FP64, per_bin=True, kernel=kernel)
+    b = gpu_solve(rt, torch, w, rt.RT_FP64, per_bin=True, kernel=kernel)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("K", [1, 3, 8, 37])
+def test_layer_kernel_tiles(rt, torch, K):
+    """Layer kernel with tiles that leave a ragged last workgroup, several
+    chunks of levels and a last chunk shorter than the others."""
+    w = small(C=37, N=23, NB=7, seed=71)
+    print(f"\n[parity] tiles K={K}", flush=True)
+    ref = O.solve(w, per_bin=True, extended=True)
+    for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
+        out = gpu_solve(rt, torch, w, prec, per_bin=True, kernel=2, cols_per_block=K)
+        assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
+        np.testing.assert_array_equal(out["flags"], ref["flags"])
 
 
 def test_cfg4_sampled(rt, torch):

@@ -47,22 +47,24 @@ def host(out):
     return res
 
 
+@pytest.mark.parametrize("kernel", [1, 2], ids=["lane", "layer"])
 @pytest.mark.parametrize("nb", [30, 100])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_mix_equals_alone(rt, torch, nb, precision):
+def test_mix_equals_alone(rt, torch, nb, precision, kernel):
     reqs = request_mix(6, nb, seed=nb + precision)
-    print(f"\n[serving] nb={nb} precision={precision} shapes="
+    print(f"\n[serving] nb={nb} precision={precision} kernel={kernel} shapes="
           f"{[(w['n_cols'], w['n_layers']) for w in reqs]}", flush=True)
     s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"])
     inputs = [rt.to_device(w) for w in reqs]
     alone = []
     for inp in inputs:
-        o = s.solve(inp, precision=precision)
+        o = s.solve(inp, precision=precision, kernel=kernel, cols_per_block=0)
         torch.cuda.synchronize()
         alone.append(host(o))
     outs = [s.outputs(int(i["mu_star"].shape[0]), int(i["dtau"].shape[0])) for i in inputs]
     torch.cuda.synchronize()
-    tickets = [s.submit(i, o, precision) for i, o in zip(inputs, outs)]
+    tickets = [s.submit(i, o, precision, kernel=kernel, cols_per_block=0)
+               for i, o in zip(inputs, outs)]
     for t in reversed(tickets):
         assert s.wait(t) == rt.RT_OK
     for a, o in zip(alone, outs):
