@@ -314,7 +314,7 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int PC, int CH, boo
     LpLayout L;
     size_t o = 0;
     L.flag = o; o += lp_align(4 * (size_t)K);
-    L.mu = o;   o += lp_align(8 * (size_t)K);
+    L.mu = o;   o += lp_align(8 * 2 * (size_t)K);              // mu, 1/mu per column
     const size_t base = o;
     L.F = o;    o += lp_align(8 * (PC + 1) * T);          // beam, rows = levels, row 0 = chunk top
     L.in = o;   o += lp_align(8 * 3 * PC * T);            // dtau, w0, g0 of the chunk's layers
@@ -343,7 +343,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const int tid = threadIdx.x, W = blockDim.x;
     const LpLayout Lo = lp_layout(K, NB, PC, CH, MIXED);
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
-    double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [K]
+    double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
     double *s_in = reinterpret_cast<double *>(lds + Lo.in);           // [3][PC][T]
     double *s_tau = reinterpret_cast<double *>(lds + Lo.tau);         // [2][T]
@@ -378,14 +378,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (!(ti >= 0.0) || !isfinite(ti)) f0 |= F_INVALID;
         }
         s_mu[kk] = mu;
+        s_mu[K + kk] = mu > 0.0 ? 1.0 / mu : 0.0;
         s_flag[kk] = f0;
     }
+
+    // Item offset of this thread within a round of W items: the sweep threads
+    // (tid < T) take the last T offsets, so in phase (d), where they are busy
+    // with the elimination, a partial round leaves them out.
+    const int rot = (tid + W - T) % W;
 
     // Planck edge integrals of n levels lev0, lev0-1, ... (or of T_int) into
     // edge rows 0..n-1, edge-major so a wavefront's lanes share one edge.
     auto edges = [&](int lev0, int n, bool interior) {
         const int per = K * (NB + 1);
-        for (int e = tid; e < n * per; e += W) {
+        for (int e = rot; e < n * per; e += W) {
             const int q = e / per, rem = e - q * per;
             const int ee = rem / K, kk = rem - ee * K;
             const int cc = c0 + kk;
@@ -394,7 +400,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 const double Tv = interior ? a.Tint[cc] : a.T[(long long)(lev0 - q) * C + cc];
                 R x;
                 if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
-                else x = a.c2_over_lam[ee] / Tv;
+                else x = a.c2_over_lam[ee] * rcp(Tv);
                 v = planck_edge<R>(x);
             }
             s_edge[(q * K + kk) * (NB + 1) + ee] = v;
@@ -414,7 +420,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     };
     // Beam bin sums of n levels held in beam rows r0.. (level lev0 - q in row r0 + q).
     auto beam_sums = [&](int r0, int lev0, int n) {
-        for (int task = tid; task < n * K; task += W) {
+        for (int task = rot; task < n * K; task += W) {
             const int q = task / K, kk = task - q * K, cc = c0 + kk;
             if (cc >= C) continue;
             const double *row = s_F + (size_t)(r0 + q) * T + kk * NB;
@@ -426,7 +432,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
 
     // dtau, w0, g0 of layers s-1 .. s-n into LDS rows 0..n-1
     auto stage = [&](int s, int n) {
-        for (int e = tid; e < n * T; e += W) {
+        for (int e = rot; e < n * T; e += W) {
             const int q = e / T, l = e - q * T;
             double dt = 0.0, w = 0.0, g = 0.0;
             if (c0 + l / NB < C) {
@@ -492,7 +498,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 if (mu > 0.0) {
                     double tau = s_tau[cur * T + l];
                     for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
-                    Fb = beam_at<MIXED>(mu * a.F_star[b], tau, 1.0 / mu);
+                    Fb = beam_at<MIXED>(mu * a.F_star[b], tau, s_mu[K + kk]);
                     if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
                 }
             }
@@ -528,7 +534,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (c0 + kk < C) {
                 const double mu = s_mu[kk];
                 const bool day = mu > 0.0;
-                const double inv_mu = day ? 1.0 / mu : 0.0;
+                const double inv_mu = s_mu[K + kk];
                 Ly = layer_item<MIXED, R>(s_in[(0 * PC + q) * T + l], s_in[(1 * PC + q) * T + l],
                                           s_in[(2 * PC + q) * T + l], day, mu, inv_mu,
                                           s_F[q * T + l], s_F[(q + 1) * T + l],

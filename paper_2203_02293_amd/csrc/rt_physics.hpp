@@ -259,9 +259,11 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
                                                      bool iso, R inv_eps2, Layer<R> &L)
 {
     const R one = R(1), half = R(0.5);
-    R kap = R(2) * E * om;
-    R ik = rcp(kap);
-    R s = sqrt(Ew * rcp(E * om));
+    const R Eom = E * om;
+    R kap = R(2) * Eom;
+    const R iEom = rcp(Eom);
+    R ik = R(0.5) * iEom;   // 1/kappa
+    R s = sqrt(Ew * iEom);
     R lam = kap * s;
     R u = lam * dtau;
     ExpEm1<R> ex = exp_em1(-u);
