@@ -120,6 +120,21 @@ rt_status rt_destroy(rt_handle *h);
  *   flags             [C]        RT_FLAG_* bits per column, or NULL
  * Values outside their domain do not stop the solve: the column's outputs are
  * then unspecified and its flags carry RT_FLAG_INVALID.
+ *
+ * Sub-layer grid (non-isothermal layers split at their centres, Section 2.2.1
+ * and the grid figure): set T_center (and p_center).  Each layer j is then two
+ * slabs, lower (interface j to centre j) and upper (centre j to interface
+ * j+1), each with its own optical properties and a Planck function linear in
+ * optical depth between its two boundary levels:
+ *   T_center, p_center [N][C]      centre temperature and pressure,
+ *                                  p_iface[j] > p_center[j] > p_iface[j+1]
+ *   dtau, w0, g0       [2N][C][NB] slab 2j = lower half of layer j, 2j+1 = upper
+ *   F_up_center, F_dn_center, F_beam_center, F_net_center [N][C]  bin sums at
+ *                                  the centres (all four required)
+ *   F_up_bin, F_dn_bin [2N+1][C][NB] per-bin fluxes at all levels, interface j
+ *                                  at level 2j and centre j at level 2j+1
+ * Interface outputs and heating keep their shapes (heating per layer from the
+ * interface net fluxes).  Needs the layer kernel (RT_KERNEL_LANE: RT_EINVAL).
  */
 typedef struct {
     int32_t n_cols, n_layers;
@@ -140,6 +155,9 @@ typedef struct {
     double *F_up_toa_bin;
     double *F_up_bin, *F_dn_bin;
     uint32_t *flags;
+    /* sub-layer grid: NULL T_center = one slab per layer */
+    const double *T_center, *p_center;
+    double *F_up_center, *F_dn_center, *F_beam_center, *F_net_center;
 } rt_request;
 
 /*

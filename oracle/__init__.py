@@ -251,5 +251,46 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
     return out
 
 
+def solve_sublayer(work: dict, opts: Options | None = None, per_bin: bool = False,
+                   cols: tuple[int, int] | None = None, n_threads: int = 0,
+                   F_toa: np.ndarray | None = None, extended: bool = False) -> dict:
+    """Sub-layer grid of non-isothermal layers (Section 2.2.1 and the grid
+    figure): layer j is split at its centre into a lower sub-layer (interface j
+    to centre j) and an upper one (centre j to interface j+1).  Each sub-layer
+    is a slab with its own optical properties (``dtau``, ``w0``, ``g0`` of shape
+    [2N][C][NB], slab 2j lower, 2j+1 upper) and a Planck function linear in
+    optical depth between its two boundary levels, which is what the four
+    sub-layer flux relations of Section 2.2.1 state.  So the system is the
+    plain one over 2N slabs whose levels alternate interface, centre,
+    interface, ...; interface fluxes are the even levels, centre fluxes the odd
+    ones, and the heating of layer j comes from its interface net fluxes and
+    pressures (Section 2.2.5).  ``work`` holds ``T_center`` and ``p_center``
+    [N][C] besides the usual arrays; ``n_layers`` counts layers, not slabs.
+    """
+    o = opts or Options()
+    N, C = int(work["n_layers"]), int(work["n_cols"])
+    Tl = np.empty((2 * N + 1, C))
+    pl = np.empty((2 * N + 1, C))
+    Tl[0::2], Tl[1::2] = _f64(work["T_iface"]), _f64(work["T_center"])
+    pl[0::2], pl[1::2] = _f64(work["p_iface"]), _f64(work["p_center"])
+    w2 = dict(work)
+    w2.update(n_layers=2 * N, T_iface=Tl, p_iface=pl)
+    r = solve(w2, o, per_bin, cols, n_threads, F_toa, extended)
+    out = {}
+    for k in ("F_up", "F_dn", "F_beam", "F_net"):
+        out[k] = np.ascontiguousarray(r[k][0::2])
+        out[k + "_center"] = np.ascontiguousarray(r[k][1::2])
+    p = _f64(work["p_iface"])
+    out["heating"] = o.gravity * (out["F_net"][:-1] - out["F_net"][1:]) / (p[:-1] - p[1:])
+    out["dTdt"] = out["heating"] / o.cp
+    out["F_up_toa_bin"] = r["F_up_toa_bin"]
+    out["flags"] = r["flags"]   # the interleaved pressures must decrease: centres in between
+    out["rc"] = r["rc"]
+    if per_bin:
+        for k in ("F_up_bin", "F_dn_bin", "F_beam_bin"):
+            out[k] = r[k]        # all 2N+1 levels
+    return out
+
+
 def max_threads() -> int:
     return lib().orc_max_threads()

@@ -277,10 +277,13 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     return RT_OK;
 }
 
+// Slabs of a request: one per layer, two on the sub-layer grid.
+static int request_slabs(const rt_request *r) { return r->T_center ? 2 * r->n_layers : r->n_layers; }
+
 static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
 {
     const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
-    return rtk::solve_geometry(r->n_cols, r->n_layers, h->NB, r->cols_per_block, kernel,
+    return rtk::solve_geometry(r->n_cols, request_slabs(r), h->NB, r->cols_per_block, kernel,
                                r->precision, h->dev);
 }
 
@@ -307,14 +310,28 @@ static rt_status validate(rt_handle *h, const rt_request *r)
     const char *names_out[] = {"F_up", "F_dn", "F_beam", "F_net", "heating"};
     for (int k = 0; k < 5; ++k)
         if (!req_out[k]) return fail(h, RT_EINVAL, "%s is NULL", names_out[k]);
+    if (r->T_center) {
+        if (r->kernel == RT_KERNEL_LANE)
+            return fail(h, RT_EINVAL, "the sub-layer grid needs the layer kernel");
+        if (!r->p_center) return fail(h, RT_EINVAL, "p_center is NULL (T_center is set)");
+        if (!r->F_up_center || !r->F_dn_center || !r->F_beam_center || !r->F_net_center)
+            return fail(h, RT_EINVAL, "the sub-layer grid needs all four centre outputs");
+        if (2 * r->n_layers > kMaxLayers)
+            return fail(h, RT_EINVAL, "2 x n_layers must be <= %d", kMaxLayers);
+    } else if (r->p_center || r->F_up_center || r->F_dn_center || r->F_beam_center ||
+               r->F_net_center) {
+        return fail(h, RT_EINVAL, "centre arrays given without T_center");
+    }
     const void *all[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int,
                          r->F_toa, r->F_up, r->F_dn, r->F_beam, r->F_net, r->heating, r->dTdt,
-                         r->F_up_toa_bin, r->F_up_bin, r->F_dn_bin, r->flags};
+                         r->F_up_toa_bin, r->F_up_bin, r->F_dn_bin, r->flags, r->T_center,
+                         r->p_center, r->F_up_center, r->F_dn_center, r->F_beam_center,
+                         r->F_net_center};
     for (const void *p : all)
         if (p && (reinterpret_cast<uintptr_t>(p) % (p == r->flags ? 4 : 8)))
             return fail(h, RT_EINVAL, "misaligned pointer %p", p);
     const long long lanes = (long long)r->n_cols * h->NB;
-    if (lanes * (r->n_layers + 1) > (1ll << 40))
+    if (lanes * (request_slabs(r) + 1) > (1ll << 40))
         return fail(h, RT_EINVAL, "problem too large");
     return RT_OK;
 }
@@ -323,7 +340,14 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
 {
     rtk::SolveArgs a{};
     a.C = r->n_cols;
-    a.N = r->n_layers;
+    a.N = request_slabs(r);
+    a.sub = r->T_center ? 1 : 0;
+    a.Tc = r->T_center;
+    a.pc = r->p_center;
+    a.F_up_c = r->F_up_center;
+    a.F_dn_c = r->F_dn_center;
+    a.F_beam_c = r->F_beam_center;
+    a.F_net_c = r->F_net_center;
     a.NB = h->NB;
     a.c2_over_lam = h->d_c2lam;
     a.c2_over_lam_f = h->d_c2lam_f;

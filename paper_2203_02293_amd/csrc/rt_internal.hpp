@@ -23,9 +23,10 @@ enum Kernel : int {
 
 // Everything one solve kernel needs (passed by value).
 struct SolveArgs {
-    int C, N, NB;              // columns, layers, bins
+    int C, N, NB;              // columns, slabs (layers, or 2 x layers on the sub-layer grid), bins
     int K;                     // columns per workgroup
     int PC, CH;                // layer kernel: levels per chunk, interfaces per bin-sum pass
+    int sub, pad_;             // 1: sub-layer grid, N = 2 x layers slabs, levels interleaved
     // resident tables of the handle
     const double *c2_over_lam; // [NB+1] second radiation constant / edge
     const float *c2_over_lam_f;
@@ -35,6 +36,9 @@ struct SolveArgs {
     // outputs
     double *F_up, *F_dn, *F_beam, *F_net, *heat, *dTdt, *F_up_toa_bin, *F_up_bin, *F_dn_bin;
     uint32_t *flags;
+    // sub-layer grid: centre temperature/pressure [N/2][C], centre outputs [N/2][C]
+    const double *Tc, *pc;
+    double *F_up_c, *F_dn_c, *F_beam_c, *F_net_c;
     // work buffer of back-substitution records, [N][R][L] doubles with L lanes in
     // the grid (R = 5 for the lane kernel, 4 for the layer kernel)
     double *scratch;

@@ -302,7 +302,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 struct LpLayout {
     size_t flag, mu;                               // persistent
     size_t F, in, tau, B, rec, rfl, edge, front;   // forward sweep
-    size_t red, fnet, back;                        // back-substitution (aliases the forward)
+    size_t red, back;                              // back-substitution (aliases the forward)
     size_t total;
 };
 
@@ -325,8 +325,7 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int PC, int CH, boo
     L.edge = o; o += lp_align(rs * PC * K * (NB + 1));    // Planck edge integrals
     L.front = o;
     size_t ob = base;
-    L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH interfaces
-    L.fnet = ob; ob += lp_align(8 * (size_t)K * (CH + 1));
+    L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
     L.back = ob;
     L.total = L.front > L.back ? L.front : L.back;
     return L;
@@ -352,7 +351,6 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
     R *s_edge = reinterpret_cast<R *>(lds + Lo.edge);                 // [PC][K][NB+1]
     double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
-    double *s_fnet = reinterpret_cast<double *>(lds + Lo.fnet);       // [K][CH+1]
 
     const int c0 = tile * K;                    // first column of the tile
     const long long LB = (long long)C * NB;     // one layer of a [C][NB] plane
@@ -382,6 +380,18 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         s_flag[kk] = f0;
     }
 
+    // Temperature of level l and the bin-summed output slot of level l: on the
+    // sub-layer grid even levels are interfaces and odd levels layer centres.
+    const bool sub = a.sub != 0;
+    auto T_at = [&](int l, int cc) -> double {
+        if (sub) return ((l & 1) ? a.Tc : a.T)[(long long)(l >> 1) * C + cc];
+        return a.T[(long long)l * C + cc];
+    };
+    auto out_at = [&](double *iface, double *centre, int l, int cc) -> double * {
+        if (sub) return ((l & 1) ? centre : iface) + (long long)(l >> 1) * C + cc;
+        return iface + (long long)l * C + cc;
+    };
+
     // Item offset of this thread within a round of W items: the sweep threads
     // (tid < T) take the last T offsets, so in phase (d), where they are busy
     // with the elimination, a partial round leaves them out.
@@ -397,7 +407,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
-                const double Tv = interior ? a.Tint[cc] : a.T[(long long)(lev0 - q) * C + cc];
+                const double Tv = interior ? a.Tint[cc] : T_at(lev0 - q, cc);
                 R x;
                 if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
                 else x = a.c2_over_lam[ee] * rcp(Tv);
@@ -426,7 +436,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const double *row = s_F + (size_t)(r0 + q) * T + kk * NB;
             double sb = 0.0;
             for (int b = 0; b < NB; ++b) sb += row[b];
-            a.F_beam[(long long)(lev0 - q) * C + cc] = sb;
+            *out_at(a.F_beam, a.F_beam_c, lev0 - q, cc) = sb;
         }
     };
 
@@ -460,7 +470,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         R B = R(0);
         double Fb = 0.0;
         if (cc < C) {
-            const double Tv = a.T[(long long)N * C + cc];
+            const double Tv = T_at(N, cc);
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
             B = bin_B(0, kk, b, Tv);
             const double mu = s_mu[kk];
@@ -491,7 +501,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             R B = R(0);
             double Fb = 0.0;
             if (cc < C) {
-                const double Tv = a.T[(long long)(s - 1 - q) * C + cc];
+                const double Tv = T_at(s - 1 - q, cc);
                 if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
                 B = bin_B(q, kk, b, Tv);
                 const double mu = s_mu[kk];
@@ -641,32 +651,35 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 su += ru[bb];
                 sd += rd[bb];
             }
-            const long long o = (long long)(i0 + ii) * C + cc;
-            const double fn = su - sd - a.F_beam[o];   // written by this workgroup above
-            a.F_up[o] = su;
-            a.F_dn[o] = sd;
-            a.F_net[o] = fn;
-            s_fnet[kk * (CH + 1) + ii + 1] = fn;
+            const int lev = i0 + ii;
+            const double fn = su - sd - *out_at(a.F_beam, a.F_beam_c, lev, cc);   // written above
+            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
+            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
+            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
             if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
         }
         __syncthreads();
-        // heating of the layer below each interface of the pass
-        for (int task = tid; task < K * CH; task += W) {
-            const int kk = task / CH, ii = task - kk * CH;
-            const int cc = c0 + kk;
-            const int i = i0 + ii;
-            if (ii >= nch || cc >= C || i < 1) continue;
-            const double dp = a.p[(long long)(i - 1) * C + cc] - a.p[(long long)i * C + cc];
-            if (!(dp > 0.0)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-            const double qh =
-                a.o.gravity * (s_fnet[kk * (CH + 1) + ii] - s_fnet[kk * (CH + 1) + ii + 1]) / dp;
-            a.heat[(long long)(i - 1) * C + cc] = qh;
-            if (a.dTdt) a.dTdt[(long long)(i - 1) * C + cc] = qh / a.o.cp;
-        }
-        __syncthreads();
-        for (int kk = tid; kk < K; kk += W) s_fnet[kk * (CH + 1)] = s_fnet[kk * (CH + 1) + nch];
-        __syncthreads();
     }
+
+    // heating of each layer from the net flux at its two interfaces (written above)
+    const int NL = sub ? N / 2 : N;
+    for (int task = tid; task < NL * K; task += W) {
+        const int j = task / K, kk = task - j * K, cc = c0 + kk;
+        if (cc >= C) continue;
+        const long long o = (long long)j * C + cc;
+        const double p0 = a.p[o], p1 = a.p[o + C];
+        const double dp = p0 - p1;
+        bool bad = !(dp > 0.0);
+        if (sub) {
+            const double pm = a.pc[o];
+            bad = bad || !(p0 > pm && pm > p1);
+        }
+        if (bad) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+        const double qh = a.o.gravity * (a.F_net[o] - a.F_net[o + C]) / dp;
+        a.heat[o] = qh;
+        if (a.dTdt) a.dTdt[o] = qh / a.o.cp;
+    }
+    __syncthreads();
     for (int kk = tid; kk < K; kk += W) {
         const int cc = c0 + kk;
         if (cc < C && a.flags) a.flags[cc] = s_flag[kk];

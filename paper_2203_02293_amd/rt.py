@@ -41,7 +41,8 @@ class RtRequest(ct.Structure):
         (n, ct.c_void_p) for n in (
             "p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "F_toa",
             "F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
-            "F_up_bin", "F_dn_bin", "flags")]
+            "F_up_bin", "F_dn_bin", "flags", "T_center", "p_center", "F_up_center",
+            "F_dn_center", "F_beam_center", "F_net_center")]
 
 
 class RtError(RuntimeError):
@@ -172,7 +173,10 @@ class Solver:
             pass
 
     # -- requests
-    def outputs(self, n_cols: int, n_layers: int, per_bin: bool = False):
+    def outputs(self, n_cols: int, n_layers: int, per_bin: bool = False,
+                sublayer: bool = False):
+        """Output tensors of one solve; ``sublayer`` adds the centre fluxes and
+        sizes per-bin fluxes for all 2N+1 levels."""
         import torch
         dev = torch.device("cuda", self.device)
         f = dict(dtype=torch.float64, device=dev)
@@ -182,9 +186,13 @@ class Solver:
         out["dTdt"] = torch.empty((N, C), **f)
         out["F_up_toa_bin"] = torch.empty((C, NB), **f)
         out["flags"] = torch.zeros(C, dtype=torch.int32, device=dev)
+        if sublayer:
+            for k in ("F_up_center", "F_dn_center", "F_beam_center", "F_net_center"):
+                out[k] = torch.empty((N, C), **f)
         if per_bin:
-            out["F_up_bin"] = torch.empty((N + 1, C, NB), **f)
-            out["F_dn_bin"] = torch.empty((N + 1, C, NB), **f)
+            levels = 2 * N + 1 if sublayer else N + 1
+            out["F_up_bin"] = torch.empty((levels, C, NB), **f)
+            out["F_dn_bin"] = torch.empty((levels, C, NB), **f)
         return out
 
     def request(self, inp: dict, out: dict, precision: int = RT_FP64,
@@ -193,7 +201,8 @@ class Solver:
         ``cols_per_block`` and ``kernel`` None: the tuned choice for this shape
         (library defaults if none); an explicit tile with no kernel: RT_KERNEL_AUTO."""
         C = int(inp["mu_star"].shape[0])
-        N = int(inp["dtau"].shape[0])
+        sub = inp.get("T_center") is not None
+        N = int(inp["dtau"].shape[0]) // (2 if sub else 1)
         if cols_per_block is None and kernel is None:
             kernel, cols_per_block = tuned_launch(self.n_bins, precision, C, N)
         r = RtRequest()
@@ -209,8 +218,11 @@ class Solver:
         for k in ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"):
             setattr(r, k, ptr(inp[k]))
         r.F_toa = ptr(inp.get("F_toa"))
+        r.T_center = ptr(inp.get("T_center"))
+        r.p_center = ptr(inp.get("p_center"))
         for k in ("F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
-                  "F_up_bin", "F_dn_bin", "flags"):
+                  "F_up_bin", "F_dn_bin", "flags", "F_up_center", "F_dn_center",
+                  "F_beam_center", "F_net_center"):
             setattr(r, k, ptr(out.get(k)))
         return r
 
@@ -219,9 +231,10 @@ class Solver:
               kernel: int | None = None) -> dict:
         """Stream-ordered solve on the current (or given) torch stream."""
         import torch
-        C, N = int(inp["mu_star"].shape[0]), int(inp["dtau"].shape[0])
+        sub = inp.get("T_center") is not None
+        C, N = int(inp["mu_star"].shape[0]), int(inp["dtau"].shape[0]) // (2 if sub else 1)
         if out is None:
-            out = self.outputs(C, N, per_bin)
+            out = self.outputs(C, N, per_bin, sublayer=sub)
         req = self.request(inp, out, precision, cols_per_block, kernel)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         rt_solve_fluxes(self.h, req, s.cuda_stream)
@@ -269,8 +282,9 @@ def to_device(work: dict, device: int = 0) -> dict:
     """Copy the arrays of a ``synth`` workload to device tensors."""
     import torch
     dev = torch.device("cuda", device)
-    keys = ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int")
-    d = {k: torch.from_numpy(np.ascontiguousarray(work[k])).to(dev) for k in keys}
+    keys = ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "T_center", "p_center")
+    d = {k: torch.from_numpy(np.ascontiguousarray(work[k])).to(dev) for k in keys
+         if work.get(k) is not None}
     if work.get("F_toa") is not None:
         d["F_toa"] = torch.from_numpy(np.ascontiguousarray(work["F_toa"])).to(dev)
     return d

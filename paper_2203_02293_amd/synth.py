@@ -221,6 +221,64 @@ def make(spec: Spec | str, n_cols: int | None = None, mu_star: np.ndarray | None
     )
 
 
+def make_sublayer(spec: Spec | str, n_cols: int | None = None, seed: int | None = None) -> dict:
+    """Workload on the sub-layer grid of non-isothermal layers: T and p given at
+    the layer centres (as a dynamical core supplies them, centre pressure the
+    geometric mean of the interfaces), interface T linearly interpolated in
+    log p between neighbouring centres and extrapolated at BOA and TOA.
+    Per-level quantities (an opacity-like optical depth per unit pressure,
+    albedo, asymmetry) are drawn at all 2N+1 levels, and each sub-layer takes
+    the arithmetic mean of its two levels, as the paper prescribes for
+    sub-layer properties.  dtau/w0/g0 have shape [2N][C][NB] (slab 2j = lower
+    half of layer j)."""
+    if isinstance(spec, str):
+        spec = SPECS[spec]
+    base = make(spec, n_cols=n_cols, seed=seed)
+    C, N, NB = base["n_cols"], base["n_layers"], base["n_bins"]
+    rs = _streams((spec.seed if seed is None else seed) + 7919, 4)
+    p_if = base["p_iface"]
+    p_c = np.sqrt(p_if[:-1] * p_if[1:])
+    lp_if, lp_c = np.log(p_if[:, 0]), np.log(p_c[:, 0])
+    mu = base["mu_star"]
+    T_c = (spec.t_base + spec.t_day * np.maximum(mu, 0.0)[None, :] ** 0.25
+           + spec.t_noise * rs[0].standard_normal((N, C)))
+    T_if = np.empty((N + 1, C))
+    for c in range(C):   # linear in log p through the centres, extended at the ends
+        T_if[:, c] = np.interp(lp_if[::-1], lp_c[::-1], T_c[::-1, c])[::-1]
+        if N > 1:
+            sb = (T_c[0, c] - T_c[1, c]) / (lp_c[0] - lp_c[1])
+            st = (T_c[-1, c] - T_c[-2, c]) / (lp_c[-1] - lp_c[-2])
+            T_if[0, c] = T_c[0, c] + sb * (lp_if[0] - lp_c[0])
+            T_if[-1, c] = T_c[-1, c] + st * (lp_if[-1] - lp_c[-1])
+    T_if = np.maximum(T_if, 10.0)
+    # levels 0..2N alternate interface, centre; sub-layer k lies between levels k and k+1
+    p_lev = np.empty(2 * N + 1)
+    p_lev[0::2], p_lev[1::2] = p_if[:, 0], p_c[:, 0]
+    dp_sub = p_lev[:-1] - p_lev[1:]
+    scale = dp_sub / (2.0 * dp_sub.max())
+    k_lev = np.exp(rs[1].uniform(math.log(spec.dtau_lo), math.log(spec.dtau_hi),
+                                 size=(2 * N + 1, C, NB)))
+    w_lev = rs[2].uniform(spec.w0_lo, spec.w0_hi, size=(2 * N + 1, C, NB))
+    g_lev = np.zeros((2 * N + 1, C, NB))
+    if spec.cloud != "none":
+        cloudy_col = mu <= 0.0 if spec.cloud == "night" else \
+            rs[3].uniform(size=C) < spec.cloud_fraction
+        cloud_lev = (p_lev >= spec.cloud_p_lo_bar * BAR) & (p_lev <= spec.cloud_p_hi_bar * BAR)
+        mask = cloud_lev[:, None] & cloudy_col[None, :]
+        cw = rs[3].uniform(spec.cloud_w0_lo, spec.cloud_w0_hi, size=(2 * N + 1, C, NB))
+        cg = rs[3].uniform(spec.cloud_g0_lo, spec.cloud_g0_hi, size=(2 * N + 1, C, NB))
+        w_lev = np.where(mask[:, :, None], cw, w_lev)
+        g_lev = np.where(mask[:, :, None], cg, g_lev)
+    mean = lambda a: 0.5 * (a[:-1] + a[1:])   # sub-layer value: mean of its two levels
+    base.update(
+        T_iface=np.ascontiguousarray(T_if), T_center=np.ascontiguousarray(T_c),
+        p_center=np.ascontiguousarray(p_c),
+        dtau=np.ascontiguousarray(mean(k_lev) * scale[:, None, None]),
+        w0=np.ascontiguousarray(mean(w_lev)), g0=np.ascontiguousarray(mean(g_lev)),
+        sublayer=True)
+    return base
+
+
 # --------------------------------------------------------------------------
 # serving mix (uneven requests, Poisson arrivals)
 # --------------------------------------------------------------------------

@@ -245,6 +245,62 @@ def test_layer_kernel_tiles(rt, torch, K):
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
 
+SUB_CASES = [
+    ("sub_small", dict(C=7, N=6, NB=5, seed=81)),
+    ("sub_bins30", dict(C=23, N=20, NB=30, seed=82)),
+    ("sub_one_layer", dict(C=5, N=1, NB=3, seed=83)),
+]
+
+
+@pytest.mark.parametrize("name,shape", SUB_CASES, ids=[c[0] for c in SUB_CASES])
+def test_sublayer_grid(rt, torch, name, shape):
+    """Sub-layer grid (layers split at their centres): interface and centre
+    fluxes, per-bin fluxes at all 2N+1 levels and heating against the oracle."""
+    spec = synth.Spec(name="s", g_level=3, n_layers=shape["N"], n_bins=shape["NB"],
+                      cloud="night", seed=shape["seed"])
+    w = synth.make_sublayer(spec, n_cols=shape["C"])
+    print(f"\n[parity] {name} {shape}", flush=True)
+    ref = O.solve_sublayer(w, per_bin=True, extended=True)
+    for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
+        out = gpu_solve(rt, torch, w, prec, per_bin=True)
+        assert "F_net_center" in out and out["F_up_bin"].shape[0] == 2 * shape["N"] + 1
+        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
+        print(f"  precision={prec} errors={e}", flush=True)
+        np.testing.assert_array_equal(out["flags"], ref["flags"])
+
+
+def test_sublayer_cfg1_sampled(rt, torch):
+    """GCM size on the sub-layer grid (2562 x 2*40 slabs x 30 bins), 32
+    columns checked against the oracle."""
+    w = synth.make_sublayer("cfg1")
+    cols = np.linspace(0, w["n_cols"] - 1, 32).astype(int)
+    ws = subset(w, cols)
+    ref = O.solve_sublayer(ws, extended=True)
+    for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
+        out = gpu_solve(rt, torch, w, prec)
+        e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec],
+                         floor_bin=FLOOR_BIN[prec], cols=cols)
+        print(f"  precision={prec} errors={e}", flush=True)
+        np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
+
+
+def test_sublayer_request_errors(rt, torch):
+    """The sub-layer grid needs the layer kernel and all four centre outputs."""
+    w = synth.make_sublayer(synth.Spec(name="s", g_level=1, n_layers=3, n_bins=2, seed=84),
+                            n_cols=2)
+    s = rt.Solver(w["lambda_edges"], w["F_star"])
+    inp = rt.to_device(w)
+    out = s.outputs(2, 3, sublayer=True)
+    with pytest.raises(rt.RtError) as e:
+        s.solve(inp, out=out, kernel=rt.RT_KERNEL_LANE, cols_per_block=0)
+    assert e.value.status == rt.RT_EINVAL
+    del out["F_beam_center"]
+    with pytest.raises(rt.RtError) as e:
+        s.solve(inp, out=out)
+    assert e.value.status == rt.RT_EINVAL
+    s.close()
+
+
 def test_cfg4_sampled(rt, torch):
     """High resolution, 10242 x 80 x 300 with cloud decks up to w0 = 0.9999,
     g0 = 0.98 and dtau log-uniform [1e-8, 1e3]: solved whole on the GPU in
