@@ -34,6 +34,10 @@ WORKLOADS = {
             "night-side cloud deck",
     "cfg4": "high resolution: 10242 icosahedral columns x 80 layers x 300 bins log-spaced "
             "0.3-30 um, cloud decks to w0 0.9999 / g0 0.98, dtau log-uniform [1e-8, 1e3]",
+    "cfg1_kdist": "GCM size with k-distribution bins: 2562 icosahedral columns x 40 layers x "
+                  "30 bins x 20 Gaussian points (600 solves per column), night-side cloud deck",
+    "cfg1_sub": "GCM size on the sub-layer grid: 2562 icosahedral columns x 40 layers split "
+                "at their centres (80 slabs) x 30 bins, night-side cloud deck",
 }
 METRIC = "two-stream column·bin solves/s (FP64 vs mixed, ≤1e-5 rel err); p50/p99 latency"
 
@@ -97,22 +101,25 @@ def pct(v, q):
 
 
 def cpu_baseline(work, seconds: float = 10.0) -> dict:
-    """The CPU oracle as it stands, timed on this host on whole cfg1 solves
-    repeated for about `seconds` (all host threads)."""
+    """The CPU oracle as it stands, timed on this host on whole solves of the
+    benchmark workload repeated for about `seconds` (all host threads)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    oracle.solve(work, n_threads=threads, cols=(0, 64))   # load and warm
+    run = oracle.solve_sublayer if work.get("sublayer") else oracle.solve
+    run(work, n_threads=threads, cols=(0, 64))   # load and warm
     reps, t0 = 0, time.perf_counter()
     while True:
-        oracle.solve(work, n_threads=threads)
+        run(work, n_threads=threads)
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    cb = work["n_cols"] * work["n_bins"] * reps
+    nbg = work["n_bins"] * work.get("n_gauss", 1)
+    cb = work["n_cols"] * nbg * reps
+    shape = f"{work['n_cols']}x{work['n_layers']}x{nbg}"
     return {"value": cb / el, "unit": "column·bin solves/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} whole FP64 solves of the 2562x40x30 workload in {el:.1f} s "
+            "sample": f"{reps} whole FP64 solves of the {shape} workload in {el:.1f} s "
                       f"on {threads} OpenMP threads"}
 
 
@@ -222,11 +229,19 @@ def main():
         return
 
     WORKLOAD = args.workload
-    work = synth.make(WORKLOAD)
-    C, N, NB = work["n_cols"], work["n_layers"], work["n_bins"]
-    s = rt.Solver(work["lambda_edges"], work["F_star"])
+    if WORKLOAD == "cfg1_kdist":
+        work = synth.make_kdist("cfg1", n_gauss=20)
+    elif WORKLOAD == "cfg1_sub":
+        work = synth.make_sublayer("cfg1")
+    else:
+        work = synth.make(WORKLOAD)
+    C, N = work["n_cols"], work["n_layers"]
+    NB = work["n_bins"] * work.get("n_gauss", 1)      # solves per column
+    s = rt.Solver(work["lambda_edges"], work["F_star"], gauss_weights=work.get("gauss_w"))
     inp = rt.to_device(work)
-    out = s.outputs(C, N)
+    out = s.outputs(C, N, sublayer=work.get("sublayer", False))
+    if work.get("sublayer"):
+        N = 2 * N                                       # slabs
     torch.cuda.synchronize()
     print(f"[bench] {WORKLOAD} {C}x{N}x{NB} resident; timing FP64", file=sys.stderr, flush=True)
 

@@ -87,6 +87,13 @@ typedef struct {
                                      by in-flight requests (0: 8 GiB)                */
     int32_t max_inflight;         /* serving: max queued + running requests (0: 64)  */
     int32_t device;               /* HIP device ordinal                              */
+    int32_t n_gauss;              /* k-distribution (Section 2.1.3): NG Gaussian
+                                     points per bin (0 or 1: plain bins); each
+                                     (bin, g) pair is solved with its bin's Planck
+                                     function and stellar flux, and bin sums are
+                                     sum_b sum_g w_g F.  NB * NG <= 768.           */
+    int32_t reserved;             /* must be 0 */
+    const double *gauss_weights;  /* HOST [NG] weights w_g > 0 (NULL if NG <= 1)   */
 } rt_config;
 
 /* Fill *cfg with the defaults (NB = 0 and NULL tables: the caller sets them). */
@@ -104,7 +111,9 @@ rt_status rt_destroy(rt_handle *h);
 
 /*
  * One solve.  Shapes: C = n_cols >= 1, N = n_layers in [1, 4096], NB from the
- * handle.  Inputs (device, read only):
+ * handle.  With NG > 1 Gaussian points per bin, every [..][NB] array below
+ * except F_up_toa_bin has NB * NG entries instead, index b * NG + g, and
+ * needs the layer kernel.  Inputs (device, read only):
  *   p_iface, T_iface  [N+1][C]   Pa, K; p strictly decreasing with i, T > 0
  *   dtau, w0, g0      [N][C][NB] layer optical depth (>= 0), single-scattering
  *                                albedo in [0,1], asymmetry in (-1,1)
@@ -115,7 +124,8 @@ rt_status rt_destroy(rt_handle *h);
  *   F_up, F_dn, F_beam, F_net [N+1][C]  bin sums, W m^-2; F_net = F_up - F_dn - F_beam
  *   heating           [N][C]     W kg^-1, g (F_net_j - F_net_{j+1}) / (p_j - p_{j+1})
  *   dTdt              [N][C]     K s^-1 = heating / cp, or NULL
- *   F_up_toa_bin      [C][NB]    upward flux at TOA per bin (spectrum), or NULL
+ *   F_up_toa_bin      [C][NB]    upward flux at TOA per bin (spectrum; the
+ *                                weighted sum over its g-points), or NULL
  *   F_up_bin, F_dn_bin [N+1][C][NB] per-bin fluxes, or NULL
  *   flags             [C]        RT_FLAG_* bits per column, or NULL
  * Values outside their domain do not stop the solve: the column's outputs are

@@ -41,7 +41,8 @@ def build(force: bool = True) -> pathlib.Path:
     Two builds of the same source: FP64 (the oracle) and binary128 (used to
     measure the rounding error of FP64 evaluations; the parity reference)."""
     for out, extra in ((LIB, []), (LIB_X, ["-DORC_QUAD=1"])):
-        if force or not out.exists() or out.stat().st_mtime < SRC.stat().st_mtime:
+        newest = max(SRC.stat().st_mtime, SRC.with_suffix(".h").stat().st_mtime)
+        if force or not out.exists() or out.stat().st_mtime < newest:
             tmp = out.with_suffix(".so.tmp")
             subprocess.run(
                 ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
@@ -70,8 +71,8 @@ _up = ct.POINTER(ct.c_uint32)
 
 class Problem(ct.Structure):
     _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("n_bins", ct.c_int32),
-                ("col_begin", ct.c_int32), ("col_end", ct.c_int32),
-                ("lambda_edges", _dp), ("F_star", _dp), ("p_iface", _dp), ("T_iface", _dp),
+                ("col_begin", ct.c_int32), ("col_end", ct.c_int32), ("n_gauss", ct.c_int32),
+                ("pad_", ct.c_int32), ("gauss_w", _dp), ("lambda_edges", _dp), ("F_star", _dp), ("p_iface", _dp), ("T_iface", _dp),
                 ("dtau", _dp), ("w0", _dp), ("g0", _dp), ("mu_star", _dp), ("T_int", _dp),
                 ("F_toa", _dp), ("F_up", _dp), ("F_dn", _dp), ("F_beam", _dp), ("F_net", _dp),
                 ("heating", _dp), ("dTdt", _dp), ("F_up_toa_bin", _dp), ("F_up_bin", _dp),
@@ -110,7 +111,8 @@ def lib(extended: bool = False) -> ct.CDLL:
     """The FP64 oracle library, or its binary128 build if ``extended``."""
     path = LIB_X if extended else LIB
     if path not in _libs:
-        if not path.exists() or path.stat().st_mtime < SRC.stat().st_mtime:
+        newest = max(SRC.stat().st_mtime, SRC.with_suffix(".h").stat().st_mtime)
+        if not path.exists() or path.stat().st_mtime < newest:
             build(force=True)
         _libs[path] = load(path)
     return _libs[path]
@@ -223,9 +225,15 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
 
     ``cols`` restricts the solve to a column range (other outputs stay zero).
     ``n_threads`` = 0 uses OpenMP's default.  ``extended`` runs the same code
-    in binary128 (parity reference; results rounded to FP64).
+    in binary128 (parity reference; results rounded to FP64).  A k-distribution
+    workload carries ``gauss_w`` [NG] (g-point weights of every bin, summing to
+    1) and per-(bin, g-point) arrays of NB*NG entries; per-bin outputs are then
+    per (bin, g-point) and ``F_up_toa_bin`` is the weighted sum over g.
     """
     C, N, NB = int(work["n_cols"]), int(work["n_layers"]), int(work["n_bins"])
+    gw = work.get("gauss_w")
+    NG = 1 if gw is None else int(np.asarray(gw).size)
+    gw = None if gw is None else _f64(gw)
     c0, c1 = cols if cols is not None else (0, C)
     arr = {k: _f64(work[k]) for k in ("lambda_edges", "F_star", "p_iface", "T_iface",
                                         "dtau", "w0", "g0", "mu_star", "T_int")}
@@ -237,8 +245,8 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
     out["flags"] = np.zeros(C, dtype=np.uint32)
     if per_bin:
         for k in ("F_up_bin", "F_dn_bin", "F_beam_bin"):
-            out[k] = np.zeros((N + 1, C, NB))
-    P = Problem(C, N, NB, c0, c1, _p(arr["lambda_edges"]), _p(arr["F_star"]),
+            out[k] = np.zeros((N + 1, C, NB * NG))
+    P = Problem(C, N, NB, c0, c1, NG, 0, _p(gw), _p(arr["lambda_edges"]), _p(arr["F_star"]),
                 _p(arr["p_iface"]), _p(arr["T_iface"]), _p(arr["dtau"]), _p(arr["w0"]),
                 _p(arr["g0"]), _p(arr["mu_star"]), _p(arr["T_int"]), _p(Ft),
                 _p(out["F_up"]), _p(out["F_dn"]), _p(out["F_beam"]), _p(out["F_net"]),

@@ -430,7 +430,7 @@ int orc_column_bin(int N, const double *B, const double *dtau, const double *w0,
 
 static int orc_valid_column(const orc_problem *P, int c)
 {
-    const int C = P->n_cols, N = P->n_layers, NB = P->n_bins;
+    const int C = P->n_cols, N = P->n_layers, NB = P->n_bins * P->n_gauss;
     if (!isfinite(P->mu_star[c]) || !(P->T_int[c] >= 0.0)) return 0;
     for (int i = 0; i <= N; ++i) {
         double T = P->T_iface[(long)i * C + c], p = P->p_iface[(long)i * C + c];
@@ -451,9 +451,11 @@ static int orc_valid_column(const orc_problem *P, int c)
 /* Whole problem: every (column, bin), bin sums, net flux and heating rate. */
 int orc_solve(const orc_problem *P, const orc_opts *o, int n_threads)
 {
-    const int C = P->n_cols, N = P->n_layers, NB = P->n_bins;
+    const int C = P->n_cols, N = P->n_layers, NB = P->n_bins, NG = P->n_gauss;
+    const int NBG = NB * NG;   /* (bin, g-point) pairs per column */
     const int c0 = P->col_begin, c1 = P->col_end;
-    if (C <= 0 || N <= 0 || NB <= 0 || c0 < 0 || c1 > C || c0 > c1) return -1;
+    if (C <= 0 || N <= 0 || NB <= 0 || NG <= 0 || c0 < 0 || c1 > C || c0 > c1) return -1;
+    if (NG > 1 && !P->gauss_w) return -1;
     if (!gl_ready) orc_gauss_legendre();
     int rc_all = 0;
 #ifdef _OPENMP
@@ -473,21 +475,27 @@ int orc_solve(const orc_problem *P, const orc_opts *o, int n_threads)
             for (int i = 0; i <= N; ++i)
                 B[i] = orc_planck_bin_r(P->T_iface[(long)i * C + c], l1, l2);
             real F_boa = ORC_PI * orc_planck_bin_r(P->T_int[c], l1, l2);
-            real F_toa = P->F_toa ? P->F_toa[(long)c * NB + b] : 0;
-            long off = (long)c * NB + b, stride = (long)C * NB;
-            int rc = orc_column_bin_r(N, B, P->dtau + off, P->w0 + off, P->g0 + off, stride,
-                                      mu, P->F_star[b], F_boa, F_toa, o, fu, fd, fb, &fl);
-            if (rc) rc_all |= 1;
-            for (int i = 0; i <= N; ++i) {
-                su[i] += fu[i];
-                sd[i] += fd[i];
-                sb[i] += fb[i];
-                long k = ((long)i * C + c) * NB + b;
-                if (P->F_up_bin) P->F_up_bin[k] = fu[i];
-                if (P->F_dn_bin) P->F_dn_bin[k] = fd[i];
-                if (P->F_beam_bin) P->F_beam_bin[k] = fb[i];
+            real toa = 0;
+            for (int g = 0; g < NG; ++g) {
+                const real wg = NG > 1 ? (real)P->gauss_w[g] : 1;
+                const int bg = b * NG + g;
+                real F_toa = P->F_toa ? P->F_toa[(long)c * NBG + bg] : 0;
+                long off = (long)c * NBG + bg, stride = (long)C * NBG;
+                int rc = orc_column_bin_r(N, B, P->dtau + off, P->w0 + off, P->g0 + off, stride,
+                                          mu, P->F_star[b], F_boa, F_toa, o, fu, fd, fb, &fl);
+                if (rc) rc_all |= 1;
+                for (int i = 0; i <= N; ++i) {
+                    su[i] += wg * fu[i];
+                    sd[i] += wg * fd[i];
+                    sb[i] += wg * fb[i];
+                    long k = ((long)i * C + c) * NBG + bg;
+                    if (P->F_up_bin) P->F_up_bin[k] = fu[i];
+                    if (P->F_dn_bin) P->F_dn_bin[k] = fd[i];
+                    if (P->F_beam_bin) P->F_beam_bin[k] = fb[i];
+                }
+                toa += wg * fu[N];
             }
-            if (P->F_up_toa_bin) P->F_up_toa_bin[(long)c * NB + b] = fu[N];
+            if (P->F_up_toa_bin) P->F_up_toa_bin[(long)c * NB + b] = toa;
         }
         for (int i = 0; i <= N; ++i) {
             long k = (long)i * C + c;

@@ -50,21 +50,31 @@ typedef struct {
     uint32_t flags;
 } orc_layer;
 
+/*
+ * k-distribution (Section 2.1.3): each bin b holds NG quadrature points
+ * (g-points) with weights w_g summing to 1; a g-point is solved like a bin
+ * of its own (its bin's Planck function and stellar flux) and bin sums are
+ * sum_b sum_g w_g F.  Arrays over "(bin, g)" use index b*NG + g.  NG = 1
+ * (weights NULL) is the plain per-bin problem.
+ */
 typedef struct {
     int32_t n_cols, n_layers, n_bins, col_begin, col_end; /* [col_begin,col_end) */
+    int32_t n_gauss;              /* NG >= 1 g-points per bin          */
+    int32_t pad_;
+    const double *gauss_w;        /* [NG] weights, or NULL when NG = 1 */
     const double *lambda_edges;   /* [NB+1] m                          */
     const double *F_star;         /* [NB]   W m^-2 at normal incidence */
     const double *p_iface;        /* [N+1][C] Pa                       */
     const double *T_iface;        /* [N+1][C] K                        */
-    const double *dtau, *w0, *g0; /* [N][C][NB]                        */
+    const double *dtau, *w0, *g0; /* [N][C][NB*NG]                     */
     const double *mu_star;        /* [C]                               */
     const double *T_int;          /* [C]                               */
-    const double *F_toa;          /* [C][NB] or NULL                   */
+    const double *F_toa;          /* [C][NB*NG] or NULL                */
     /* outputs */
-    double *F_up, *F_dn, *F_beam, *F_net;  /* [N+1][C] */
+    double *F_up, *F_dn, *F_beam, *F_net;  /* [N+1][C] weighted bin sums */
     double *heating, *dTdt;                /* [N][C] (dTdt may be NULL) */
-    double *F_up_toa_bin;                  /* [C][NB] or NULL */
-    double *F_up_bin, *F_dn_bin, *F_beam_bin; /* [N+1][C][NB] or NULL */
+    double *F_up_toa_bin;                  /* [C][NB] weighted over g, or NULL */
+    double *F_up_bin, *F_dn_bin, *F_beam_bin; /* [N+1][C][NB*NG] or NULL */
     uint32_t *flags;                       /* [C] or NULL */
 } orc_problem;
 

@@ -23,6 +23,7 @@ namespace {
 
 constexpr double kH = 6.62607015e-34, kC = 299792458.0, kKB = 1.380649e-23;
 constexpr int kMaxBins = 512;
+constexpr int kMaxBinPoints = 768;   // bins x Gaussian points: lanes of one column
 constexpr int kMaxLayers = 4096;
 constexpr int kStreams = 4;
 constexpr size_t kAlign = 256;
@@ -99,8 +100,11 @@ struct Batch {
 
 struct rt_handle {
     rt_config cfg{};
-    int NB = 0;
+    int NB = 0;          // bins
+    int NG = 1;          // Gaussian points per bin
+    int NBG = 0;         // lanes per column, NB * NG
     rtk::DeviceLimits dev{};
+    double *d_gw = nullptr;
     double *d_c2lam = nullptr;
     float *d_c2lam_f = nullptr;
     double *d_fstar = nullptr;
@@ -173,7 +177,7 @@ extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_l
 {
     if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
     const rtk::Geometry g =
-        rtk::solve_geometry(n_cols, n_layers, h->NB, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
+        rtk::solve_geometry(n_cols, n_layers, h->NBG, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
     return g.threads > 0 ? (int64_t)g.scratch : -1;
 }
 
@@ -196,8 +200,16 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
         if (!(cfg->stellar_flux[b] >= 0.0) || !std::isfinite(cfg->stellar_flux[b])) return RT_EINVAL;
     if (!(cfg->eps2 > 0.0) || !(cfg->e_tau >= 0.0) || !(cfg->g_guard >= 0.0) ||
         !(cfg->gravity > 0.0) || !(cfg->cp > 0.0) || cfg->hbm_budget_bytes < 0 ||
-        cfg->max_inflight < 0)
+        cfg->max_inflight < 0 || cfg->n_gauss < 0 || cfg->reserved != 0)
         return RT_EINVAL;
+    const int NG = cfg->n_gauss > 1 ? cfg->n_gauss : 1;
+    if ((long long)NB * NG > kMaxBinPoints) return RT_EINVAL;
+    if (NG > 1) {
+        if (!cfg->gauss_weights) return RT_EINVAL;
+        for (int g = 0; g < NG; ++g)
+            if (!(cfg->gauss_weights[g] > 0.0) || !std::isfinite(cfg->gauss_weights[g]))
+                return RT_EINVAL;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return RT_EDEVICE;
@@ -208,9 +220,12 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
     h->cfg = *cfg;
     h->cfg.lambda_edges = nullptr;
     h->cfg.stellar_flux = nullptr;
+    h->cfg.gauss_weights = nullptr;
     if (h->cfg.hbm_budget_bytes == 0) h->cfg.hbm_budget_bytes = 8ll << 30;
     if (h->cfg.max_inflight == 0) h->cfg.max_inflight = 64;
     h->NB = NB;
+    h->NG = NG;
+    h->NBG = NB * NG;
     {
         int n_cu = 0, lds = 0;
         if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) !=
@@ -238,13 +253,17 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
     hipError_t err;
     if ((err = hipMalloc(&h->d_c2lam, sizeof(double) * (NB + 1))) != hipSuccess ||
         (err = hipMalloc(&h->d_c2lam_f, sizeof(float) * (NB + 1))) != hipSuccess ||
-        (err = hipMalloc(&h->d_fstar, sizeof(double) * NB)) != hipSuccess) {
+        (err = hipMalloc(&h->d_fstar, sizeof(double) * NB)) != hipSuccess ||
+        (err = hipMalloc(&h->d_gw, sizeof(double) * NG)) != hipSuccess) {
         rt_destroy(h);
         return RT_ENOMEM;
     }
+    std::vector<double> gw(NG, 1.0);
+    if (NG > 1) gw.assign(cfg->gauss_weights, cfg->gauss_weights + NG);
     if (hipMemcpy(h->d_c2lam, c2.data(), sizeof(double) * (NB + 1), hipMemcpyHostToDevice) ||
         hipMemcpy(h->d_c2lam_f, c2f.data(), sizeof(float) * (NB + 1), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->d_fstar, cfg->stellar_flux, sizeof(double) * NB, hipMemcpyHostToDevice)) {
+        hipMemcpy(h->d_fstar, cfg->stellar_flux, sizeof(double) * NB, hipMemcpyHostToDevice) ||
+        hipMemcpy(h->d_gw, gw.data(), sizeof(double) * NG, hipMemcpyHostToDevice)) {
         rt_destroy(h);
         return RT_EDEVICE;
     }
@@ -271,6 +290,7 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     (void)hipFree(h->d_c2lam);
     (void)hipFree(h->d_c2lam_f);
     (void)hipFree(h->d_fstar);
+    (void)hipFree(h->d_gw);
     (void)hipFree(h->d_scratch);
     (void)hipFree(h->arena_mem);
     delete h;
@@ -283,7 +303,7 @@ static int request_slabs(const rt_request *r) { return r->T_center ? 2 * r->n_la
 static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
 {
     const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
-    return rtk::solve_geometry(r->n_cols, request_slabs(r), h->NB, r->cols_per_block, kernel,
+    return rtk::solve_geometry(r->n_cols, request_slabs(r), h->NBG, r->cols_per_block, kernel,
                                r->precision, h->dev);
 }
 
@@ -298,10 +318,12 @@ static rt_status validate(rt_handle *h, const rt_request *r)
     if (r->kernel < RT_KERNEL_AUTO || r->kernel > RT_KERNEL_LAYER)
         return fail(h, RT_EINVAL, "kernel must be RT_KERNEL_AUTO, _LANE or _LAYER");
     if (r->reserved != 0) return fail(h, RT_EINVAL, "reserved must be 0");
+    if (h->NG > 1 && r->kernel == RT_KERNEL_LANE)
+        return fail(h, RT_EINVAL, "Gaussian points per bin need the layer kernel");
     if (r->cols_per_block < 0) return fail(h, RT_EINVAL, "cols_per_block must be >= 0");
     if (request_geometry(h, r).threads == 0)
         return fail(h, RT_EINVAL, "tile of %d columns x %d bins does not fit the %s kernel",
-                    r->cols_per_block, h->NB, r->kernel == RT_KERNEL_LANE ? "lane" : "layer");
+                    r->cols_per_block, h->NBG, r->kernel == RT_KERNEL_LANE ? "lane" : "layer");
     const void *req_in[] = {r->p_iface, r->T_iface, r->dtau, r->w0, r->g0, r->mu_star, r->T_int};
     const char *names_in[] = {"p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"};
     for (int k = 0; k < 7; ++k)
@@ -330,7 +352,7 @@ static rt_status validate(rt_handle *h, const rt_request *r)
     for (const void *p : all)
         if (p && (reinterpret_cast<uintptr_t>(p) % (p == r->flags ? 4 : 8)))
             return fail(h, RT_EINVAL, "misaligned pointer %p", p);
-    const long long lanes = (long long)r->n_cols * h->NB;
+    const long long lanes = (long long)r->n_cols * h->NBG;
     if (lanes * (request_slabs(r) + 1) > (1ll << 40))
         return fail(h, RT_EINVAL, "problem too large");
     return RT_OK;
@@ -348,7 +370,9 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
     a.F_dn_c = r->F_dn_center;
     a.F_beam_c = r->F_beam_center;
     a.F_net_c = r->F_net_center;
-    a.NB = h->NB;
+    a.NB = h->NBG;
+    a.NG = h->NG;
+    a.wg = h->d_gw;
     a.c2_over_lam = h->d_c2lam;
     a.c2_over_lam_f = h->d_c2lam_f;
     a.F_star = h->d_fstar;

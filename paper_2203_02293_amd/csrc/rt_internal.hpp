@@ -26,11 +26,13 @@ struct SolveArgs {
     int C, N, NB;              // columns, slabs (layers, or 2 x layers on the sub-layer grid), bins
     int K;                     // columns per workgroup
     int PC, CH;                // layer kernel: levels per chunk, interfaces per bin-sum pass
-    int sub, pad_;             // 1: sub-layer grid, N = 2 x layers slabs, levels interleaved
+    int sub;                   // 1: sub-layer grid, N = 2 x layers slabs, levels interleaved
+    int NG;                    // Gaussian points per bin: NB = bins x NG lanes per column
     // resident tables of the handle
-    const double *c2_over_lam; // [NB+1] second radiation constant / edge
+    const double *c2_over_lam; // [NB/NG+1] second radiation constant / edge
     const float *c2_over_lam_f;
-    const double *F_star;      // [NB]
+    const double *F_star;      // [NB/NG]
+    const double *wg;          // [NG] quadrature weights (NG > 1)
     // inputs
     const double *p, *T, *dtau, *w0, *g0, *mu, *Tint, *Ftoa;
     // outputs

@@ -308,7 +308,8 @@ struct LpLayout {
 
 __host__ __device__ inline size_t lp_align(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline LpLayout lp_layout(int K, int NB, int PC, int CH, bool mixed)
+// NB: lanes per column (bins x Gaussian points), NBR: bins (Planck edges NBR+1)
+__host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, int CH, bool mixed)
 {
     const size_t T = (size_t)K * NB, rs = mixed ? 4 : 8;
     LpLayout L;
@@ -322,7 +323,7 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int PC, int CH, boo
     L.B = o;    o += lp_align(rs * (PC + 1) * T);         // Planck bin radiance, rows as F
     L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
     L.rfl = o;  o += lp_align(4 * PC * T);                // flags per layer
-    L.edge = o; o += lp_align(rs * PC * K * (NB + 1));    // Planck edge integrals
+    L.edge = o; o += lp_align(rs * PC * K * (NBR + 1));   // Planck edge integrals
     L.front = o;
     size_t ob = base;
     L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
@@ -338,9 +339,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     extern __shared__ double smem[];
     char *lds = reinterpret_cast<char *>(smem);
     const int NB = a.NB, K = a.K, C = a.C, N = a.N, PC = a.PC, CH = a.CH;
+    const int NG = a.NG, NBR = NB / NG;   // lanes per column = bins x Gaussian points
     const int T = K * NB;
     const int tid = threadIdx.x, W = blockDim.x;
-    const LpLayout Lo = lp_layout(K, NB, PC, CH, MIXED);
+    const LpLayout Lo = lp_layout(K, NB, NBR, PC, CH, MIXED);
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
@@ -349,7 +351,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     R *s_B = reinterpret_cast<R *>(lds + Lo.B);                       // [PC+1][T]
     R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
     uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
-    R *s_edge = reinterpret_cast<R *>(lds + Lo.edge);                 // [PC][K][NB+1]
+    R *s_edge = reinterpret_cast<R *>(lds + Lo.edge);                 // [PC][K][NBR+1]
     double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
 
     const int c0 = tile * K;                    // first column of the tile
@@ -400,7 +402,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // Planck edge integrals of n levels lev0, lev0-1, ... (or of T_int) into
     // edge rows 0..n-1, edge-major so a wavefront's lanes share one edge.
     auto edges = [&](int lev0, int n, bool interior) {
-        const int per = K * (NB + 1);
+        const int per = K * (NBR + 1);
         for (int e = rot; e < n * per; e += W) {
             const int q = e / per, rem = e - q * per;
             const int ee = rem / K, kk = rem - ee * K;
@@ -413,13 +415,15 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 else x = a.c2_over_lam[ee] * rcp(Tv);
                 v = planck_edge<R>(x);
             }
-            s_edge[(q * K + kk) * (NB + 1) + ee] = v;
+            s_edge[(q * K + kk) * (NBR + 1) + ee] = v;
         }
     };
+    // Bin of a lane's (bin, Gaussian point) index, and the point's quadrature weight.
+    auto bin_of = [&](int b) -> int { return NG == 1 ? b : b / NG; };
     // Bin radiance of (column kk, bin b) from edge row q at temperature Td.
     auto bin_B = [&](int q, int kk, int b, double Td) -> R {
         const R Tr = R(Td), T2 = Tr * Tr;
-        const R *row = s_edge + (q * K + kk) * (NB + 1);
+        const R *row = s_edge + (q * K + kk) * (NBR + 1);
         R I = planck_combine<R>(row[b], row[b + 1]);
         if constexpr (MIXED) {
             const R iT = rcp(Tr);
@@ -428,14 +432,23 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
         return R(kPref) * T2 * T2 * I;
     };
+    // Sum over a column's lanes, weighted by the Gaussian points' weights.
+    auto lane_sum = [&](const double *row) -> double {
+        double sum = 0.0;
+        if (NG == 1) {
+            for (int b = 0; b < NB; ++b) sum += row[b];
+        } else {
+            for (int rb = 0; rb < NBR; ++rb)
+                for (int g = 0; g < NG; ++g) sum += a.wg[g] * row[rb * NG + g];
+        }
+        return sum;
+    };
     // Beam bin sums of n levels held in beam rows r0.. (level lev0 - q in row r0 + q).
     auto beam_sums = [&](int r0, int lev0, int n) {
         for (int task = rot; task < n * K; task += W) {
             const int q = task / K, kk = task - q * K, cc = c0 + kk;
             if (cc >= C) continue;
-            const double *row = s_F + (size_t)(r0 + q) * T + kk * NB;
-            double sb = 0.0;
-            for (int b = 0; b < NB; ++b) sb += row[b];
+            const double sb = lane_sum(s_F + (size_t)(r0 + q) * T + kk * NB);
             *out_at(a.F_beam, a.F_beam_c, lev0 - q, cc) = sb;
         }
     };
@@ -460,7 +473,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // F_BOA = pi B_b(T_int) of the sweep lanes
     edges(0, 1, true);
     __syncthreads();
-    const double Fboa = active ? double(kPI) * double(bin_B(0, kl, bl, a.Tint[c0 + kl])) : 0.0;
+    const double Fboa =
+        active ? double(kPI) * double(bin_B(0, kl, bin_of(bl), a.Tint[c0 + kl])) : 0.0;
     __syncthreads();
     // level N: Planck and the unattenuated beam, row 0
     edges(N, 1, false);
@@ -472,9 +486,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (cc < C) {
             const double Tv = T_at(N, cc);
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-            B = bin_B(0, kk, b, Tv);
+            const int rb = bin_of(b);
+            B = bin_B(0, kk, rb, Tv);
             const double mu = s_mu[kk];
-            if (mu > 0.0) Fb = mu * a.F_star[b];
+            if (mu > 0.0) Fb = mu * a.F_star[rb];
         }
         s_B[l] = B;
         s_F[l] = Fb;
@@ -503,12 +518,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (cc < C) {
                 const double Tv = T_at(s - 1 - q, cc);
                 if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-                B = bin_B(q, kk, b, Tv);
+                const int rb = bin_of(b);
+                B = bin_B(q, kk, rb, Tv);
                 const double mu = s_mu[kk];
                 if (mu > 0.0) {
                     double tau = s_tau[cur * T + l];
                     for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
-                    Fb = beam_at<MIXED>(mu * a.F_star[b], tau, s_mu[K + kk]);
+                    Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
                     if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
                 }
             }
@@ -632,7 +648,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 const long long k = (long long)i * LB + toff + tid;
                 if (a.F_up_bin) a.F_up_bin[k] = Fu;
                 if (a.F_dn_bin) a.F_dn_bin[k] = Fd;
-                if (i == N && a.F_up_toa_bin) a.F_up_toa_bin[toff + tid] = Fu;
+                if (i == N && a.F_up_toa_bin && NG == 1) a.F_up_toa_bin[toff + tid] = Fu;
             }
             if (sweep) {
                 s_red[(0 * CH + ii) * T + tid] = Fu;
@@ -644,19 +660,25 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int kk = task / CH, ii = task - kk * CH;
             const int cc = c0 + kk;
             if (ii >= nch || cc >= C) continue;
-            double su = 0.0, sd = 0.0;
-            const double *ru = s_red + (0 * CH + ii) * T + kk * NB;
-            const double *rd = s_red + (1 * CH + ii) * T + kk * NB;
-            for (int bb = 0; bb < NB; ++bb) {
-                su += ru[bb];
-                sd += rd[bb];
-            }
+            const double su = lane_sum(s_red + (0 * CH + ii) * T + kk * NB);
+            const double sd = lane_sum(s_red + (1 * CH + ii) * T + kk * NB);
             const int lev = i0 + ii;
             const double fn = su - sd - *out_at(a.F_beam, a.F_beam_c, lev, cc);   // written above
             *out_at(a.F_up, a.F_up_c, lev, cc) = su;
             *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
             *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
             if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
+        }
+        // TOA spectrum per bin: the weighted sum over the bin's Gaussian points
+        if (NG > 1 && a.F_up_toa_bin && i0 + nch == N + 1) {
+            for (int task = tid; task < K * NBR; task += W) {
+                const int kk = task / NBR, rb = task - kk * NBR, cc = c0 + kk;
+                if (cc >= C) continue;
+                const double *ru = s_red + (0 * CH + (N - i0)) * T + kk * NB + rb * NG;
+                double sum = 0.0;
+                for (int g = 0; g < NG; ++g) sum += a.wg[g] * ru[g];
+                a.F_up_toa_bin[(long long)cc * NBR + rb] = sum;
+            }
         }
         __syncthreads();
     }
@@ -768,7 +790,7 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     double best = -1.0;
     for (int pc = 1; pc <= 8; ++pc) {
         if (pc * T > 2 * wmax) break;
-        const LpLayout lo = lp_layout(K, NB, pc, 1, mixed);
+        const LpLayout lo = lp_layout(K, NB, NB, pc, 1, mixed);
         if (lo.total > dev.lds) break;
         int W = std::min(wmax, round64(pc * T));
         W = std::max(W, round64(T));
@@ -783,14 +805,14 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     }
     if (best < 0.0) return Geometry{};
     // interfaces per bin-sum pass: as many as fit in the forward sweep's bytes
-    const LpLayout lo = lp_layout(K, NB, g.PC, 1, mixed);
+    const LpLayout lo = lp_layout(K, NB, NB, g.PC, 1, mixed);
     int ch = 1;
-    while (ch < 16 && lp_layout(K, NB, g.PC, ch + 1, mixed).total <= lo.total) ++ch;
+    while (ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= lo.total) ++ch;
     g.CH = ch;
     g.K = K;
     g.blocks = (C + K - 1) / K;
     g.lanes = (long long)g.blocks * T;
-    g.lds = lp_layout(K, NB, g.PC, g.CH, mixed).total;
+    g.lds = lp_layout(K, NB, NB, g.PC, g.CH, mixed).total;
     return g;
 }
 

@@ -31,7 +31,9 @@ class RtConfig(ct.Structure):
                 ("stellar_flux", ct.POINTER(ct.c_double)), ("eps2", ct.c_double),
                 ("e_tau", ct.c_double), ("g_guard", ct.c_double), ("gravity", ct.c_double),
                 ("cp", ct.c_double), ("hbm_budget_bytes", ct.c_int64),
-                ("max_inflight", ct.c_int32), ("device", ct.c_int32)]
+                ("max_inflight", ct.c_int32), ("device", ct.c_int32),
+                ("n_gauss", ct.c_int32), ("reserved", ct.c_int32),
+                ("gauss_weights", ct.POINTER(ct.c_double))]
 
 
 class RtRequest(ct.Structure):
@@ -146,9 +148,11 @@ class Solver:
 
     def __init__(self, lambda_edges, stellar_flux, improved=1, noniso=1, e_clamp=1,
                  eps2=2.0 / 3.0, e_tau=1e-4, g_guard=1e-5, gravity=47.0, cp=12436.0,
-                 hbm_budget_bytes=0, max_inflight=0, device=0):
+                 hbm_budget_bytes=0, max_inflight=0, device=0, gauss_weights=None):
         self._lam = np.ascontiguousarray(lambda_edges, dtype=np.float64)
         self._fs = np.ascontiguousarray(stellar_flux, dtype=np.float64)
+        self._gw = None if gauss_weights is None else \
+            np.ascontiguousarray(gauss_weights, dtype=np.float64)
         cfg = rt_config_default()
         cfg.n_bins = self._fs.size
         cfg.improved, cfg.noniso, cfg.e_clamp = improved, noniso, e_clamp
@@ -157,7 +161,11 @@ class Solver:
         cfg.eps2, cfg.e_tau, cfg.g_guard = eps2, e_tau, g_guard
         cfg.gravity, cfg.cp = gravity, cp
         cfg.hbm_budget_bytes, cfg.max_inflight, cfg.device = hbm_budget_bytes, max_inflight, device
+        if self._gw is not None:
+            cfg.n_gauss = self._gw.size
+            cfg.gauss_weights = self._gw.ctypes.data_as(ct.POINTER(ct.c_double))
         self.n_bins = cfg.n_bins
+        self.n_gauss = 1 if self._gw is None else self._gw.size
         self.device = device
         self.h = rt_create(cfg)
 
@@ -191,8 +199,8 @@ class Solver:
                 out[k] = torch.empty((N, C), **f)
         if per_bin:
             levels = 2 * N + 1 if sublayer else N + 1
-            out["F_up_bin"] = torch.empty((levels, C, NB), **f)
-            out["F_dn_bin"] = torch.empty((levels, C, NB), **f)
+            out["F_up_bin"] = torch.empty((levels, C, NB * self.n_gauss), **f)
+            out["F_dn_bin"] = torch.empty((levels, C, NB * self.n_gauss), **f)
         return out
 
     def request(self, inp: dict, out: dict, precision: int = RT_FP64,
@@ -204,7 +212,7 @@ class Solver:
         sub = inp.get("T_center") is not None
         N = int(inp["dtau"].shape[0]) // (2 if sub else 1)
         if cols_per_block is None and kernel is None:
-            kernel, cols_per_block = tuned_launch(self.n_bins, precision, C, N)
+            kernel, cols_per_block = tuned_launch(self.n_bins * self.n_gauss, precision, C, N)
         r = RtRequest()
         r.n_cols, r.n_layers, r.precision = C, N, precision
         r.cols_per_block = cols_per_block or 0

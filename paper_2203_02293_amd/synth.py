@@ -279,6 +279,46 @@ def make_sublayer(spec: Spec | str, n_cols: int | None = None, seed: int | None 
     return base
 
 
+def gauss_points(n_gauss: int) -> tuple[np.ndarray, np.ndarray]:
+    """Gauss-Legendre nodes and weights on [0, 1] (weights sum to 1): the
+    quadrature over the cumulative variable g of a k-distribution bin."""
+    x, w = np.polynomial.legendre.leggauss(n_gauss)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def make_kdist(spec: Spec | str, n_cols: int | None = None, n_gauss: int = 20,
+               seed: int | None = None) -> dict:
+    """Workload with k-distribution bins (Section 2.1.3: opacities sorted within
+    each bin and sampled at n_gauss Gaussian points).  Per (layer, column, bin)
+    the base recipe gives an optical depth; it is split into an absorbing part
+    whose sorted opacity rises across the bin, k(g) = k_mid exp(s (g - 1/2))
+    with a spread s ~ U[0, 8] per bin, and a scattering part the same for all
+    g.  w0 at each g-point is scattering over total extinction, as the mixing
+    rule prescribes, and g0 is the base recipe's (cloud decks).  Arrays hold
+    NB * n_gauss entries per column, index bin * n_gauss + g."""
+    if isinstance(spec, str):
+        spec = SPECS[spec]
+    base = make(spec, n_cols=n_cols, seed=seed)
+    N, C, NB = base["n_layers"], base["n_cols"], base["n_bins"]
+    rs = _streams((spec.seed if seed is None else seed) + 104729, 2)
+    gx, gw = gauss_points(n_gauss)
+    spread = rs[0].uniform(0.0, 8.0, size=NB)
+    shape = np.exp(spread[:, None] * (gx[None, :] - 0.5))          # [NB][NG]
+    shape /= (shape * gw[None, :]).sum(axis=1, keepdims=True)        # mean 1 over g
+    scat = base["dtau"] * base["w0"]                                  # [N][C][NB]
+    absb = base["dtau"] - scat
+    dtau = absb[..., None] * shape[None, None] + scat[..., None]      # [N][C][NB][NG]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        w0 = np.where(dtau > 0, scat[..., None] / dtau, 0.0)
+    w0 = np.clip(w0, 0.0, 1.0)
+    g0 = np.repeat(base["g0"][..., None], n_gauss, axis=3)
+    base.update(dtau=np.ascontiguousarray(dtau.reshape(N, C, NB * n_gauss)),
+                w0=np.ascontiguousarray(w0.reshape(N, C, NB * n_gauss)),
+                g0=np.ascontiguousarray(g0.reshape(N, C, NB * n_gauss)),
+                gauss_w=gw, n_gauss=n_gauss)
+    return base
+
+
 # --------------------------------------------------------------------------
 # serving mix (uneven requests, Poisson arrivals)
 # --------------------------------------------------------------------------

@@ -50,7 +50,8 @@ def gpu_solve(rt, torch, w, precision, per_bin=False, opts=None, F_toa=None, ker
               cols_per_block=None):
     o = opts or O.Options()
     s = rt.Solver(w["lambda_edges"], w["F_star"], improved=o.improved, noniso=o.noniso,
-                  e_clamp=o.e_clamp, eps2=o.eps2, e_tau=o.e_tau, g_guard=o.g_guard)
+                  e_clamp=o.e_clamp, eps2=o.eps2, e_tau=o.e_tau, g_guard=o.g_guard,
+                  gauss_weights=w.get("gauss_w"))
     inp = rt.to_device(w)
     if F_toa is not None:
         inp["F_toa"] = torch.from_numpy(np.ascontiguousarray(F_toa)).cuda()
@@ -297,6 +298,56 @@ def test_sublayer_request_errors(rt, torch):
     del out["F_beam_center"]
     with pytest.raises(rt.RtError) as e:
         s.solve(inp, out=out)
+    assert e.value.status == rt.RT_EINVAL
+    s.close()
+
+
+KDIST_CASES = [
+    ("kd_small", dict(C=5, N=6, NB=4, NG=5, seed=91)),
+    ("kd_ragged", dict(C=13, N=9, NB=7, NG=3, seed=92)),
+]
+
+
+@pytest.mark.parametrize("name,shape", KDIST_CASES, ids=[c[0] for c in KDIST_CASES])
+def test_kdist_bins(rt, torch, name, shape):
+    """k-distribution bins (Gaussian points with weights): weighted bin sums,
+    per-(bin, g) fluxes and the weighted TOA spectrum against the oracle."""
+    spec = synth.Spec(name="k", g_level=3, n_layers=shape["N"], n_bins=shape["NB"],
+                      cloud="night", seed=shape["seed"])
+    w = synth.make_kdist(spec, n_cols=shape["C"], n_gauss=shape["NG"])
+    print(f"\n[parity] {name} {shape}", flush=True)
+    ref = O.solve(w, per_bin=True, extended=True)
+    for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
+        out = gpu_solve(rt, torch, w, prec, per_bin=True)
+        assert out["F_up_bin"].shape[2] == shape["NB"] * shape["NG"]
+        e = assert_close(out, ref, w["p_iface"], tol, floor=FLOOR[prec], floor_bin=FLOOR_BIN[prec])
+        print(f"  precision={prec} errors={e}", flush=True)
+        np.testing.assert_array_equal(out["flags"], ref["flags"])
+
+
+def test_kdist_paper_shape_sampled(rt, torch):
+    """The paper's production spectral set-up: 2562 columns x 40 layers x 30
+    bins x 20 Gaussian points (600 solves per column), 16 columns checked."""
+    w = synth.make_kdist("cfg1", n_gauss=20)
+    cols = np.linspace(0, w["n_cols"] - 1, 16).astype(int)
+    ws = subset(w, cols)
+    ws["gauss_w"] = w["gauss_w"]
+    ref = O.solve(ws, extended=True)
+    for prec, tol in ((rt.RT_FP64, FP64_TOL), (rt.RT_MIXED, MIXED_TOL)):
+        out = gpu_solve(rt, torch, w, prec)
+        e = assert_close(out, ref, ws["p_iface"], tol, floor=FLOOR[prec],
+                         floor_bin=FLOOR_BIN[prec], cols=cols)
+        print(f"  precision={prec} errors={e}", flush=True)
+        np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
+
+
+def test_kdist_needs_layer_kernel(rt, torch):
+    spec = synth.Spec(name="k", g_level=1, n_layers=3, n_bins=2, seed=93)
+    w = synth.make_kdist(spec, n_cols=2, n_gauss=4)
+    s = rt.Solver(w["lambda_edges"], w["F_star"], gauss_weights=w["gauss_w"])
+    inp = rt.to_device(w)
+    with pytest.raises(rt.RtError) as e:
+        s.solve(inp, kernel=rt.RT_KERNEL_LANE, cols_per_block=0)
     assert e.value.status == rt.RT_EINVAL
     s.close()
 
