@@ -79,6 +79,13 @@ class Problem(ct.Structure):
                 ("F_dn_bin", _dp), ("F_beam_bin", _dp), ("flags", _up)]
 
 
+class OpTable(ct.Structure):
+    _fields_ = [("n_temp", ct.c_int32), ("n_press", ct.c_int32), ("n_bins", ct.c_int32),
+                ("n_gauss", ct.c_int32), ("temp", _dp), ("log10p", _dp), ("kappa", _dp),
+                ("sigma_gas", _dp), ("cloud_abs", _dp), ("cloud_scat", _dp), ("cloud_g0", _dp),
+                ("f_cloud", ct.c_double), ("m_mean", ct.c_double), ("gravity", ct.c_double)]
+
+
 @dataclasses.dataclass
 class Options:
     """Solver switches (defaults: improved, non-isothermal, Table 3 values)."""
@@ -119,6 +126,18 @@ def lib(extended: bool = False) -> ct.CDLL:
 
 
 def _declare(L: ct.CDLL) -> None:
+    for f in ("orc_rayleigh_h2", "orc_rayleigh_he"):
+        getattr(L, f).restype = ct.c_double
+        getattr(L, f).argtypes = [ct.c_double]
+    L.orc_rayleigh_bin.restype = ct.c_double
+    L.orc_rayleigh_bin.argtypes = [ct.c_double] * 4
+    L.orc_kappa_interp.restype = ct.c_double
+    L.orc_kappa_interp.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_int]
+    L.orc_optics_point.restype = None
+    L.orc_optics_point.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_int,
+                                   ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    L.orc_optics.restype = ct.c_int
+    L.orc_optics.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int] + [ct.c_void_p] * 7
     L.orc_planck_bin.restype = ct.c_double
     L.orc_planck_bin.argtypes = [ct.c_double, ct.c_double, ct.c_double]
     L.orc_efit.restype = ct.c_double
@@ -297,6 +316,70 @@ def solve_sublayer(work: dict, opts: Options | None = None, per_bin: bool = Fals
     if per_bin:
         for k in ("F_up_bin", "F_dn_bin", "F_beam_bin"):
             out[k] = r[k]        # all 2N+1 levels
+    return out
+
+
+# ----------------------------------------------------------------- optical properties
+def rayleigh_h2(lam_m: float) -> float:
+    return lib().orc_rayleigh_h2(float(lam_m))
+
+
+def rayleigh_he(lam_m: float) -> float:
+    return lib().orc_rayleigh_he(float(lam_m))
+
+
+def rayleigh_bin(lam1: float, lam2: float, x_h2: float, x_he: float) -> float:
+    return lib().orc_rayleigh_bin(float(lam1), float(lam2), float(x_h2), float(x_he))
+
+
+class _Tab:
+    """An opacity-table dict (layout of ``synth.opacity_table``) as the C struct;
+    keeps the arrays alive."""
+
+    def __init__(self, tab: dict, lambda_edges, gravity: float):
+        lam = _f64(lambda_edges)
+        NB = lam.size - 1
+        self.arr = {k: _f64(tab[k]) for k in ("temp", "log10p", "kappa")}
+        self.arr["sigma_gas"] = np.array([rayleigh_bin(lam[b], lam[b + 1], tab["x_h2"],
+                                                       tab["x_he"]) for b in range(NB)])
+        for k in ("cloud_abs", "cloud_scat", "cloud_g0"):
+            self.arr[k] = None if tab.get(k) is None else _f64(tab[k])
+        NG = int(tab.get("n_gauss", 1))
+        self.c = OpTable(self.arr["temp"].size, self.arr["log10p"].size, NB, NG,
+                         _p(self.arr["temp"]), _p(self.arr["log10p"]), _p(self.arr["kappa"]),
+                         _p(self.arr["sigma_gas"]), _p(self.arr["cloud_abs"]),
+                         _p(self.arr["cloud_scat"]), _p(self.arr["cloud_g0"]),
+                         float(tab["f_cloud"]), float(tab["m_mean"]), float(gravity))
+
+
+def kappa_interp(tab: dict, lambda_edges, T: float, p: float, bg: int) -> float:
+    t = _Tab(tab, lambda_edges, 1.0)
+    return lib().orc_kappa_interp(ct.byref(t.c), float(T), float(p), int(bg))
+
+
+def optics_point(tab: dict, lambda_edges, T: float, p: float, bg: int) -> tuple:
+    """(extinction per unit mass, w0, g0) at one (T, p) for (bin, g-point) bg."""
+    t = _Tab(tab, lambda_edges, 1.0)
+    ke, w, g = ct.c_double(), ct.c_double(), ct.c_double()
+    lib().orc_optics_point(ct.byref(t.c), float(T), float(p), int(bg), ct.byref(ke),
+                           ct.byref(w), ct.byref(g))
+    return ke.value, w.value, g.value
+
+
+def optics(work: dict, tab: dict, sublayer: bool = False, gravity: float = 47.0) -> dict:
+    """dtau, w0, g0 of every slab from the opacity table (``work`` supplies
+    T/p at interfaces and centres and the bin edges)."""
+    t = _Tab(tab, work["lambda_edges"], gravity)
+    C, N = int(work["n_cols"]), int(work["n_layers"])
+    nbg = t.c.n_bins * t.c.n_gauss
+    S = 2 * N if sublayer else N
+    out = {k: np.zeros((S, C, nbg)) for k in ("dtau", "w0", "g0")}
+    arr = {k: _f64(work[k]) for k in ("T_iface", "p_iface", "T_center", "p_center")}
+    rc = lib().orc_optics(ct.byref(t.c), C, N, int(sublayer), _p(arr["T_iface"]),
+                          _p(arr["p_iface"]), _p(arr["T_center"]), _p(arr["p_center"]),
+                          _p(out["dtau"]), _p(out["w0"]), _p(out["g0"]))
+    if rc:
+        raise ValueError("bad optics arguments")
     return out
 
 

@@ -529,3 +529,158 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================
+ * Optical properties of a layer (the step before the solve)
+ * ====================================================================== */
+
+/*
+ * Rayleigh scattering cross section per molecule, Appendix C:
+ *   sigma = 24 pi^3 / (n_ref^2 lam^4) ((n_r^2 - 1)/(n_r^2 + 2))^2 K_lam,
+ * with K_lam = 1 and the printed refractivity fits (lam' = lam / 1 um).  The
+ * printed constants are CGS (n_ref in cm^-3, lam in cm, sigma in cm^2); the
+ * result is returned in m^2.
+ */
+static double orc_rayleigh_cgs(double lam_cm, double n_ref, double n_r)
+{
+    double r = (n_r * n_r - 1.0) / (n_r * n_r + 2.0);
+    double l4 = lam_cm * lam_cm * lam_cm * lam_cm;
+    const double pi = 3.14159265358979323846;
+    return 24.0 * pi * pi * pi / (n_ref * n_ref * l4) * r * r;
+}
+
+double orc_rayleigh_h2(double lam_m)
+{
+    double lp = lam_m / 1e-6;
+    double n_r = 1.358e-4 * (1.0 + 7.52e-3 / (lp * lp)) + 1.0;
+    return 1e-4 * orc_rayleigh_cgs(lam_m * 100.0, 2.68678e19, n_r);
+}
+
+double orc_rayleigh_he(double lam_m)
+{
+    double lp = lam_m / 1e-6;
+    double n_r = 1e-8 * (2283.0 + 1.8102e13 / (1.5342e10 - 1.0 / (lp * lp))) + 1.0;
+    return 1e-4 * orc_rayleigh_cgs(lam_m * 100.0, 2.546899e19, n_r);
+}
+
+/*
+ * Gas scattering cross section of a bin, x_h2 sigma_H2 + x_he sigma_He
+ * averaged over the bin in wavenumber (the bins are equal in wavenumber and
+ * the paper averages the gas scattering over each bin): composite 20-point
+ * Gauss-Legendre on 16 panels.
+ */
+double orc_rayleigh_bin(double lam1, double lam2, double x_h2, double x_he)
+{
+    if (!gl_ready) orc_gauss_legendre();
+    const double nu1 = 1.0 / lam2, nu2 = 1.0 / lam1;   /* lam1 < lam2 */
+    const int panels = 16;
+    const double h = (nu2 - nu1) / panels;
+    double sum = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        double mid = nu1 + (p + 0.5) * h, s = 0.0;
+        for (int i = 0; i < ORC_GL_N; ++i) {
+            double lam = 1.0 / (mid + 0.5 * h * (double)gl_x[i]);
+            s += (double)gl_w[i] * (x_h2 * orc_rayleigh_h2(lam) + x_he * orc_rayleigh_he(lam));
+        }
+        sum += 0.5 * h * s;
+    }
+    return sum / (nu2 - nu1);
+}
+
+/* last index i with grid[i] <= x, clamped to [0, n-2]; x clamped to the grid */
+static int orc_bracket(const double *grid, int n, double *x)
+{
+    if (*x < grid[0]) *x = grid[0];
+    if (*x > grid[n - 1]) *x = grid[n - 1];
+    int i = 0;
+    while (i < n - 2 && grid[i + 1] <= *x) ++i;
+    return i;
+}
+
+/*
+ * Absorption opacity of (bin, g-point) bg at temperature T and pressure p:
+ * the pre-mixed k-table interpolated bilinearly in T and log10 p, values
+ * outside the table taken at its edge.
+ */
+double orc_kappa_interp(const orc_optab *tb, double T, double p, int bg)
+{
+    const int nbg = tb->n_bins * tb->n_gauss;
+    double x = T, y = log10(p);
+    int i = tb->n_temp > 1 ? orc_bracket(tb->temp, tb->n_temp, &x) : 0;
+    int j = tb->n_press > 1 ? orc_bracket(tb->log10p, tb->n_press, &y) : 0;
+    double t = tb->n_temp > 1 ? (x - tb->temp[i]) / (tb->temp[i + 1] - tb->temp[i]) : 0.0;
+    double u = tb->n_press > 1 ? (y - tb->log10p[j]) / (tb->log10p[j + 1] - tb->log10p[j]) : 0.0;
+    int i1 = tb->n_temp > 1 ? i + 1 : i, j1 = tb->n_press > 1 ? j + 1 : j;
+#define KAP(jj, ii) tb->kappa[((long)(jj) * tb->n_temp + (ii)) * nbg + bg]
+    return (1 - t) * (1 - u) * KAP(j, i) + t * (1 - u) * KAP(j, i1)
+         + (1 - t) * u * KAP(j1, i) + t * u * KAP(j1, i1);
+#undef KAP
+}
+
+/*
+ * Extinction per unit mass, single-scattering albedo and asymmetry of gas
+ * plus condensates at one point (Section 2.2.3): with cross sections per gas
+ * molecule, extinction = sigma_scat,gas + kappa m + f (sigma_abs,cl +
+ * sigma_scat,cl);  w0 = (sigma_scat,gas + f sigma_scat,cl) / extinction;
+ * g0 = f sigma_scat,cl g0,cl / (sigma_scat,gas + f sigma_scat,cl).
+ */
+void orc_optics_point(const orc_optab *tb, double T, double p, int bg, double *kext,
+                      double *w0, double *g0)
+{
+    const int b = bg / tb->n_gauss;
+    const double kap = orc_kappa_interp(tb, T, p, bg);
+    const double sg = tb->sigma_gas[b];
+    const double sa = tb->cloud_abs ? tb->f_cloud * tb->cloud_abs[b] : 0.0;
+    const double ss = tb->cloud_scat ? tb->f_cloud * tb->cloud_scat[b] : 0.0;
+    const double ext = sg + kap * tb->m_mean + sa + ss;   /* per molecule */
+    *kext = ext / tb->m_mean;                              /* per unit mass */
+    *w0 = ext > 0 ? (sg + ss) / ext : 0.0;
+    *g0 = (sg + ss) > 0 && tb->cloud_g0 ? ss * tb->cloud_g0[b] / (sg + ss) : 0.0;
+}
+
+/*
+ * dtau, w0, g0 of every slab, [S][C][NB*NG].  sub = 0: one slab per layer,
+ * properties at the layer centre, dtau = extinction (p_j - p_{j+1}) / g.
+ * sub = 1: the sub-layer grid; properties at interfaces and centres, each
+ * sub-layer taking the arithmetic mean of its two levels (Section 2.2.1),
+ * dtau = mean extinction x the sub-layer's pressure thickness / g.
+ */
+int orc_optics(const orc_optab *tb, int C, int N, int sub, const double *T_iface,
+               const double *p_iface, const double *T_center, const double *p_center,
+               double *dtau, double *w0, double *g0)
+{
+    const int nbg = tb->n_bins * tb->n_gauss;
+    if (C <= 0 || N <= 0 || nbg <= 0 || !T_center || !p_center) return -1;
+    for (int c = 0; c < C; ++c)
+        for (int bg = 0; bg < nbg; ++bg) {
+            if (!sub) {
+                for (int j = 0; j < N; ++j) {
+                    double ke, w, g;
+                    orc_optics_point(tb, T_center[(long)j * C + c], p_center[(long)j * C + c], bg,
+                                     &ke, &w, &g);
+                    long k = ((long)j * C + c) * nbg + bg;
+                    double dp = p_iface[(long)j * C + c] - p_iface[(long)(j + 1) * C + c];
+                    dtau[k] = ke * dp / tb->gravity;
+                    w0[k] = w;
+                    g0[k] = g;
+                }
+            } else {
+                for (int s = 0; s < 2 * N; ++s) {
+                    double T0, p0, T1, p1, ke0, w00, g00, ke1, w01, g01;
+                    /* level s and s+1: even levels are interfaces, odd ones centres */
+                    int l0 = s, l1 = s + 1;
+                    T0 = (l0 & 1) ? T_center[(long)(l0 >> 1) * C + c] : T_iface[(long)(l0 >> 1) * C + c];
+                    p0 = (l0 & 1) ? p_center[(long)(l0 >> 1) * C + c] : p_iface[(long)(l0 >> 1) * C + c];
+                    T1 = (l1 & 1) ? T_center[(long)(l1 >> 1) * C + c] : T_iface[(long)(l1 >> 1) * C + c];
+                    p1 = (l1 & 1) ? p_center[(long)(l1 >> 1) * C + c] : p_iface[(long)(l1 >> 1) * C + c];
+                    orc_optics_point(tb, T0, p0, bg, &ke0, &w00, &g00);
+                    orc_optics_point(tb, T1, p1, bg, &ke1, &w01, &g01);
+                    long k = ((long)s * C + c) * nbg + bg;
+                    dtau[k] = 0.5 * (ke0 + ke1) * (p0 - p1) / tb->gravity;
+                    w0[k] = 0.5 * (w00 + w01);
+                    g0[k] = 0.5 * (g00 + g01);
+                }
+            }
+        }
+    return 0;
+}

@@ -96,6 +96,35 @@ int orc_column_bin(int N, const double *B, const double *dtau, const double *w0,
 int orc_solve(const orc_problem *P, const orc_opts *o, int n_threads);
 int orc_max_threads(void);
 
+/*
+ * Optical properties (the step before the solve, Sections 2.1.3 and 2.2.3,
+ * Appendix C): a pre-mixed k-table of absorption opacity per unit mass over
+ * (T, log10 p), gas Rayleigh scattering and condensates mixed by number.
+ */
+typedef struct {
+    int32_t n_temp, n_press, n_bins, n_gauss;
+    const double *temp;         /* [n_temp] K, ascending                          */
+    const double *log10p;       /* [n_press] log10(p / Pa), ascending             */
+    const double *kappa;        /* [n_press][n_temp][NB*NG] m^2 kg^-1             */
+    const double *sigma_gas;    /* [NB] gas scattering cross section, m^2/molecule */
+    const double *cloud_abs;    /* [NB] condensate absorption cross section, m^2, or NULL */
+    const double *cloud_scat;   /* [NB] condensate scattering cross section, m^2, or NULL */
+    const double *cloud_g0;     /* [NB] condensate asymmetry, or NULL             */
+    double f_cloud;             /* condensate-to-gas number ratio                 */
+    double m_mean;              /* mean molecular mass, kg                        */
+    double gravity;             /* m s^-2                                         */
+} orc_optab;
+
+double orc_rayleigh_h2(double lam_m);
+double orc_rayleigh_he(double lam_m);
+double orc_rayleigh_bin(double lam1, double lam2, double x_h2, double x_he);
+double orc_kappa_interp(const orc_optab *tb, double T, double p, int bg);
+void orc_optics_point(const orc_optab *tb, double T, double p, int bg, double *kext,
+                      double *w0, double *g0);
+int orc_optics(const orc_optab *tb, int C, int N, int sub, const double *T_iface,
+               const double *p_iface, const double *T_center, const double *p_center,
+               double *dtau, double *w0, double *g0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -319,6 +319,53 @@ def make_kdist(spec: Spec | str, n_cols: int | None = None, n_gauss: int = 20,
     return base
 
 
+AMU = 1.66053906660e-27   # kg
+
+
+def opacity_table(n_bins: int, n_gauss: int = 1, seed: int = 2024, n_temp: int = 60,
+                  n_press: int = 28) -> dict:
+    """Synthetic pre-mixed k-table standing in for the opacity calculator's
+    (Section 2.1.3): n_temp temperatures 50-3000 K, n_press pressures 1e-6 to
+    1e3 bar equally spaced in log p, absorption opacity per unit mass for every
+    (bin, Gaussian point), log-normal across bins, rising with g inside a bin,
+    with power-law pressure broadening and an exponential temperature
+    dependence.  Condensate cross sections of 1 um particles (geometric
+    cross section pi r^2 scaled per bin), cloud-to-gas ratio 1e-17 and a mean
+    molecular mass of 2.34 amu as in the paper's set-up; H2/He volume mixing
+    ratios 0.85/0.15 for Rayleigh scattering."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    temp = np.linspace(50.0, 3000.0, n_temp)
+    log10p = np.linspace(math.log10(1e-6 * BAR), math.log10(1e3 * BAR), n_press)
+    nbg = n_bins * n_gauss
+    k_bin = np.exp(r.normal(math.log(1e-2), 2.5, size=n_bins))          # m^2 / kg
+    spread = r.uniform(0.0, 8.0, size=n_bins)
+    gx = gauss_points(n_gauss)[0] if n_gauss > 1 else np.array([0.5])
+    k_bg = (k_bin[:, None] * np.exp(spread[:, None] * (gx[None, :] - 0.5))).reshape(nbg)
+    alpha = r.uniform(0.2, 0.8, size=nbg)                               # pressure broadening
+    beta = r.uniform(-1.0, 2.0, size=nbg)                               # temperature trend
+    P = (10.0 ** log10p) / BAR
+    kappa = (k_bg[None, None, :] * (P[:, None, None] / 1.0) ** alpha[None, None, :]
+             * np.exp(beta[None, None, :] * (temp[None, :, None] - 1000.0) / 1000.0))
+    rad = 1e-6
+    geo = math.pi * rad * rad
+    return dict(temp=temp, log10p=log10p, kappa=np.ascontiguousarray(kappa), n_gauss=n_gauss,
+                cloud_abs=geo * r.uniform(0.1, 1.0, size=n_bins),
+                cloud_scat=geo * r.uniform(1.0, 2.5, size=n_bins),
+                cloud_g0=r.uniform(0.5, 0.9, size=n_bins),
+                f_cloud=1e-17, m_mean=2.34 * AMU, x_h2=0.85, x_he=0.15)
+
+
+def make_atmosphere(spec: Spec | str, n_cols: int | None = None, seed: int | None = None) -> dict:
+    """Temperatures and pressures at interfaces and layer centres (no optical
+    properties): the input of the optical-properties step.  Centre pressure is
+    the geometric mean of the interfaces; interface T is linearly interpolated
+    in log p between centres (the sub-layer recipe of ``make_sublayer``)."""
+    w = make_sublayer(spec, n_cols=n_cols, seed=seed)
+    for k in ("dtau", "w0", "g0"):
+        w.pop(k)
+    return w
+
+
 # --------------------------------------------------------------------------
 # serving mix (uneven requests, Poisson arrivals)
 # --------------------------------------------------------------------------
