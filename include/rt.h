@@ -202,6 +202,54 @@ rt_status rt_poll(rt_handle *h, uint64_t ticket);
 rt_status rt_wait(rt_handle *h, uint64_t ticket);
 
 /*
+ * Optical properties: the step before the solve (Sections 2.1.3 and 2.2.3,
+ * Appendix C).  dtau, w0 and g0 of every slab from
+ *   - a pre-mixed k-table: gas absorption opacity per unit mass kappa for
+ *     every (bin, Gaussian point), interpolated bilinearly in T and log10 p
+ *     (held at the table's edge outside it);
+ *   - gas Rayleigh scattering per molecule, x_H2 sigma_H2 + x_He sigma_He with
+ *     the printed cross sections, averaged over each bin in wavenumber;
+ *   - condensates with per-particle cross sections, f_cloud per gas molecule;
+ * mixed as extinction = sigma_scat,gas + kappa m + f (sigma_abs,cl +
+ * sigma_scat,cl), w0 = (sigma_scat,gas + f sigma_scat,cl) / extinction,
+ * g0 = f sigma_scat,cl g0,cl / (sigma_scat,gas + f sigma_scat,cl) (0 without
+ * scattering), and dtau = extinction / m x (pressure thickness) / gravity.
+ * One slab per layer takes the properties at the layer centre; on the
+ * sub-layer grid each sub-layer takes the arithmetic mean of the properties
+ * at its two levels (Section 2.2.1).
+ */
+typedef struct {
+    int32_t n_temp, n_press;      /* table grid, each in [2, 1024]                  */
+    const double *temp;           /* HOST [n_temp] K, strictly ascending            */
+    const double *log10p;         /* HOST [n_press] log10(p / Pa), strictly ascending */
+    const double *kappa;          /* HOST [n_press][n_temp][NB*NG] m^2 kg^-1, >= 0  */
+    const double *cloud_abs;      /* HOST [NB] m^2 per particle, or NULL (no clouds;
+                                     then cloud_scat and cloud_g0 are NULL too)     */
+    const double *cloud_scat;     /* HOST [NB] m^2 per particle                     */
+    const double *cloud_g0;       /* HOST [NB] asymmetry of the condensates         */
+    double f_cloud;               /* condensate-to-gas number ratio (1e-17), >= 0   */
+    double m_mean;                /* mean molecular mass, kg (2.34 amu), > 0        */
+    double x_h2, x_he;            /* volume mixing ratios for Rayleigh scattering   */
+} rt_opacities;
+
+/* Copy the tables to the device (replacing earlier ones).  RT_EINVAL on bad
+ * values or sizes, RT_ENOMEM / RT_EDEVICE on device failures.  Waits for the
+ * handle's work first. */
+rt_status rt_set_opacities(rt_handle *h, const rt_opacities *op);
+
+typedef struct {
+    int32_t n_cols, n_layers;     /* C >= 1, N in [1, 4096]                         */
+    int32_t sublayer;             /* 0: one slab per layer; 1: sub-layer grid       */
+    int32_t reserved;             /* must be 0                                      */
+    const double *p_iface, *T_iface;    /* DEVICE [N+1][C] Pa, K                    */
+    const double *p_center, *T_center;  /* DEVICE [N][C] Pa, K                      */
+    double *dtau, *w0, *g0;       /* DEVICE out [S][C][NB*NG], S = N or 2N slabs    */
+} rt_optics_request;
+
+/* Stream-ordered; RT_EINVAL without opacities set or on bad arguments. */
+rt_status rt_optical_properties(rt_handle *h, const rt_optics_request *req, void *hip_stream);
+
+/*
  * Device bytes of library-owned work buffer one solve of this shape needs
  * (what the serving path reserves from its budget per admitted request);
  * -1 on bad arguments.

@@ -9,14 +9,14 @@ PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "librt_mi355x.so"
-SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_api.hip"]
+SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_optics.hip", CSRC / "rt_api.hip"]
 HEADERS = [CSRC / "rt_internal.hpp", CSRC / "rt_math.hpp", CSRC / "rt_physics.hpp",
            ROOT / "include" / "rt.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions stay off (see the design notes)
+    # packed FP32 instructions stay off: the kernels use scalar FP32 forms only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

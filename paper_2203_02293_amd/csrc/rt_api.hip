@@ -105,6 +105,12 @@ struct rt_handle {
     int NBG = 0;         // lanes per column, NB * NG
     rtk::DeviceLimits dev{};
     double *d_gw = nullptr;
+    std::vector<double> lam;   // bin edges, m (host copy)
+    // opacity tables (rt_set_opacities)
+    bool have_opac = false;
+    int opac_nT = 0, opac_nP = 0;
+    double opac_m = 0.0;
+    double *d_opac = nullptr;   // temp[nT], log10p[nP], kappa[nP][nT][NBG], then [4][NB] per-bin terms
     double *d_c2lam = nullptr;
     float *d_c2lam_f = nullptr;
     double *d_fstar = nullptr;
@@ -224,6 +230,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
     if (h->cfg.hbm_budget_bytes == 0) h->cfg.hbm_budget_bytes = 8ll << 30;
     if (h->cfg.max_inflight == 0) h->cfg.max_inflight = 64;
     h->NB = NB;
+    h->lam.assign(cfg->lambda_edges, cfg->lambda_edges + NB + 1);
     h->NG = NG;
     h->NBG = NB * NG;
     {
@@ -291,6 +298,7 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     (void)hipFree(h->d_c2lam_f);
     (void)hipFree(h->d_fstar);
     (void)hipFree(h->d_gw);
+    (void)hipFree(h->d_opac);
     (void)hipFree(h->d_scratch);
     (void)hipFree(h->arena_mem);
     delete h;
@@ -404,6 +412,110 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
     a.o.gravity = h->cfg.gravity;
     a.o.cp = h->cfg.cp;
     return a;
+}
+
+extern "C" rt_status rt_set_opacities(rt_handle *h, const rt_opacities *op)
+{
+    if (!h || !op) return RT_EINVAL;
+    const int nT = op->n_temp, nP = op->n_press, NB = h->NB, NBG = h->NBG;
+    if (nT < 2 || nT > 1024 || nP < 2 || nP > 1024 || !op->temp || !op->log10p || !op->kappa)
+        return fail(h, RT_EINVAL, "table grid must be 2..1024 x 2..1024 with all arrays given");
+    for (int i = 0; i < nT; ++i)
+        if (!std::isfinite(op->temp[i]) || (i > 0 && !(op->temp[i] > op->temp[i - 1])))
+            return fail(h, RT_EINVAL, "temperature grid must be finite and strictly ascending");
+    for (int j = 0; j < nP; ++j)
+        if (!std::isfinite(op->log10p[j]) || (j > 0 && !(op->log10p[j] > op->log10p[j - 1])))
+            return fail(h, RT_EINVAL, "log10 pressure grid must be finite and strictly ascending");
+    const size_t nk = (size_t)nP * nT * NBG;
+    for (size_t k = 0; k < nk; ++k)
+        if (!(op->kappa[k] >= 0.0) || !std::isfinite(op->kappa[k]))
+            return fail(h, RT_EINVAL, "kappa must be finite and >= 0");
+    const bool cloud = op->cloud_abs != nullptr;
+    if (cloud != (op->cloud_scat != nullptr) || cloud != (op->cloud_g0 != nullptr))
+        return fail(h, RT_EINVAL, "condensate arrays: all three or none");
+    if (!(op->m_mean > 0.0) || !(op->f_cloud >= 0.0) || !(op->x_h2 >= 0.0) || !(op->x_he >= 0.0) ||
+        !std::isfinite(op->f_cloud) || !std::isfinite(op->x_h2) || !std::isfinite(op->x_he))
+        return fail(h, RT_EINVAL, "m_mean > 0; f_cloud, x_h2, x_he finite and >= 0");
+    std::vector<double> host(nT + nP + nk + 4 * (size_t)NB);
+    std::copy(op->temp, op->temp + nT, host.begin());
+    std::copy(op->log10p, op->log10p + nP, host.begin() + nT);
+    std::copy(op->kappa, op->kappa + nk, host.begin() + nT + nP);
+    double *pb = host.data() + nT + nP + nk;   // per-bin: gas scattering, f abs, f scat, g0
+    for (int b = 0; b < NB; ++b) {
+        const double lo = h->lam[b], hi = h->lam[b + 1];
+        pb[b] = rtk::rayleigh_bin_average(lo, hi, op->x_h2, op->x_he);
+        double sa = 0.0, ss = 0.0, g = 0.0;
+        if (cloud) {
+            sa = op->cloud_abs[b];
+            ss = op->cloud_scat[b];
+            g = op->cloud_g0[b];
+            if (!(sa >= 0.0) || !(ss >= 0.0) || !(g > -1.0 && g < 1.0) || !std::isfinite(sa) ||
+                !std::isfinite(ss))
+                return fail(h, RT_EINVAL, "condensate cross sections >= 0, asymmetry in (-1, 1)");
+        }
+        pb[NB + b] = op->f_cloud * sa;
+        pb[2 * NB + b] = op->f_cloud * ss;
+        pb[3 * NB + b] = g;
+    }
+    (void)hipSetDevice(h->cfg.device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->d_opac);
+    h->d_opac = nullptr;
+    h->have_opac = false;
+    if (hipMalloc(&h->d_opac, host.size() * sizeof(double)) != hipSuccess)
+        return fail(h, RT_ENOMEM, "opacity tables of %zu bytes", host.size() * sizeof(double));
+    if (hipMemcpy(h->d_opac, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return fail(h, RT_EDEVICE, "opacity table upload");
+    h->opac_nT = nT;
+    h->opac_nP = nP;
+    h->opac_m = op->m_mean;
+    h->have_opac = true;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_optical_properties(rt_handle *h, const rt_optics_request *r, void *stream)
+{
+    if (!h) return RT_EINVAL;
+    if (!r) return fail(h, RT_EINVAL, "request is NULL");
+    if (!h->have_opac) return fail(h, RT_EINVAL, "no opacity tables: call rt_set_opacities");
+    if (r->n_cols < 1 || r->n_layers < 1 || r->n_layers > kMaxLayers)
+        return fail(h, RT_EINVAL, "n_cols >= 1 and n_layers in [1, %d]", kMaxLayers);
+    if ((r->sublayer != 0 && r->sublayer != 1) || r->reserved != 0)
+        return fail(h, RT_EINVAL, "sublayer must be 0 or 1, reserved 0");
+    const void *ptrs[] = {r->p_iface, r->T_iface, r->p_center, r->T_center, r->dtau, r->w0, r->g0};
+    for (const void *p : ptrs) {
+        if (!p) return fail(h, RT_EINVAL, "a required array is NULL");
+        if (reinterpret_cast<uintptr_t>(p) % 8) return fail(h, RT_EINVAL, "misaligned pointer %p", p);
+    }
+    (void)hipSetDevice(h->cfg.device);
+    rtk::OpticsArgs a{};
+    a.C = r->n_cols;
+    a.S = r->sublayer ? 2 * r->n_layers : r->n_layers;
+    a.NBG = h->NBG;
+    a.NG = h->NG;
+    a.sub = r->sublayer;
+    a.nT = h->opac_nT;
+    a.nP = h->opac_nP;
+    a.temp = h->d_opac;
+    a.log10p = a.temp + a.nT;
+    a.kappa = a.log10p + a.nP;
+    a.sig_gas = a.kappa + (size_t)a.nP * a.nT * a.NBG;
+    a.sig_cl_abs = a.sig_gas + h->NB;
+    a.sig_cl_scat = a.sig_cl_abs + h->NB;
+    a.g0_cl = a.sig_cl_scat + h->NB;
+    a.m_mean = h->opac_m;
+    a.gravity = h->cfg.gravity;
+    a.p = r->p_iface;
+    a.T = r->T_iface;
+    a.pc = r->p_center;
+    a.Tc = r->T_center;
+    a.dtau = r->dtau;
+    a.w0 = r->w0;
+    a.g0 = r->g0;
+    const hipError_t e = rtk::launch_optics(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "optics launch");
+    return RT_OK;
 }
 
 extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *stream)

@@ -83,4 +83,19 @@ hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n
 // Allow the kernels the device's full LDS per workgroup (once per device).
 hipError_t prepare_kernels(const DeviceLimits &dev);
 
+// Optical properties of the slabs from the opacity tables (one launch).
+struct OpticsArgs {
+    int C, S, NBG, NG;          // columns, slabs, lanes per column, Gaussian points per bin
+    int sub, nT, nP, pad_;      // sub-layer grid; k-table grid sizes
+    const double *temp, *log10p, *kappa;          // [nT], [nP], [nP][nT][NBG]
+    const double *sig_gas, *sig_cl_abs, *sig_cl_scat, *g0_cl;   // [NB]; condensates pre-scaled by f
+    double m_mean, gravity;
+    const double *p, *T, *pc, *Tc;                // [N+1][C], [N][C]
+    double *dtau, *w0, *g0;                       // [S][C][NBG]
+};
+hipError_t launch_optics(const OpticsArgs &a, hipStream_t s);
+// Gas Rayleigh cross section (x_h2 H2 + x_he He, m^2 per molecule) averaged
+// over [lam_lo, lam_hi] in wavenumber.
+double rayleigh_bin_average(double lam_lo, double lam_hi, double x_h2, double x_he);
+
 }  // namespace rtk

@@ -22,7 +22,8 @@ FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1,
 
 #: every symbol include/rt.h declares
 SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes", "rt_submit",
-           "rt_poll", "rt_wait", "rt_work_bytes", "rt_last_error", "rt_status_string")
+           "rt_poll", "rt_wait", "rt_work_bytes", "rt_last_error", "rt_status_string",
+           "rt_set_opacities", "rt_optical_properties")
 
 
 class RtConfig(ct.Structure):
@@ -45,6 +46,21 @@ class RtRequest(ct.Structure):
             "F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
             "F_up_bin", "F_dn_bin", "flags", "T_center", "p_center", "F_up_center",
             "F_dn_center", "F_beam_center", "F_net_center")]
+
+
+class RtOpacities(ct.Structure):
+    _fields_ = [("n_temp", ct.c_int32), ("n_press", ct.c_int32)] + [
+        (n, ct.POINTER(ct.c_double)) for n in ("temp", "log10p", "kappa", "cloud_abs",
+                                               "cloud_scat", "cloud_g0")] + [
+        ("f_cloud", ct.c_double), ("m_mean", ct.c_double), ("x_h2", ct.c_double),
+        ("x_he", ct.c_double)]
+
+
+class RtOpticsRequest(ct.Structure):
+    _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("sublayer", ct.c_int32),
+                ("reserved", ct.c_int32)] + [
+        (n, ct.c_void_p) for n in ("p_iface", "T_iface", "p_center", "T_center", "dtau", "w0",
+                                   "g0")]
 
 
 class RtError(RuntimeError):
@@ -73,6 +89,10 @@ def lib() -> ct.CDLL:
         L.rt_solve_fluxes.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.c_void_p]
         L.rt_solve_fluxes.restype = ct.c_int32
         L.rt_submit.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.POINTER(ct.c_uint64)]
+        L.rt_set_opacities.argtypes = [ct.c_void_p, ct.POINTER(RtOpacities)]
+        L.rt_set_opacities.restype = ct.c_int32
+        L.rt_optical_properties.argtypes = [ct.c_void_p, ct.POINTER(RtOpticsRequest), ct.c_void_p]
+        L.rt_optical_properties.restype = ct.c_int32
         L.rt_submit.restype = ct.c_int32
         L.rt_poll.argtypes = [ct.c_void_p, ct.c_uint64]
         L.rt_poll.restype = ct.c_int32
@@ -123,6 +143,15 @@ def _check(h, st, what):
 
 def rt_solve_fluxes(h: int, req: RtRequest, stream: int | None) -> int:
     return _check(h, lib().rt_solve_fluxes(h, ct.byref(req), stream), "rt_solve_fluxes")
+
+
+def rt_set_opacities(h: int, op: RtOpacities) -> int:
+    return _check(h, lib().rt_set_opacities(h, ct.byref(op)), "rt_set_opacities")
+
+
+def rt_optical_properties(h: int, req: RtOpticsRequest, stream: int | None) -> int:
+    return _check(h, lib().rt_optical_properties(h, ct.byref(req), stream),
+                  "rt_optical_properties")
 
 
 def rt_submit(h: int, req: RtRequest) -> int:
@@ -251,6 +280,44 @@ class Solver:
     def submit(self, inp: dict, out: dict, precision: int = RT_FP64,
                cols_per_block: int | None = None, kernel: int | None = None) -> int:
         return rt_submit(self.h, self.request(inp, out, precision, cols_per_block, kernel))
+
+    def set_opacities(self, tab: dict):
+        """Upload an opacity-table dict (layout of ``synth.opacity_table``)."""
+        keep = {k: np.ascontiguousarray(tab[k], dtype=np.float64)
+                for k in ("temp", "log10p", "kappa", "cloud_abs", "cloud_scat", "cloud_g0")
+                if tab.get(k) is not None}
+        nbg = self.n_bins * self.n_gauss
+        if keep["kappa"].shape != (keep["log10p"].size, keep["temp"].size, nbg):
+            raise ValueError(f"kappa must have shape (n_press, n_temp, {nbg})")
+        for k in ("cloud_abs", "cloud_scat", "cloud_g0"):
+            if k in keep and keep[k].shape != (self.n_bins,):
+                raise ValueError(f"{k} must have shape ({self.n_bins},)")
+        dp = lambda k: keep[k].ctypes.data_as(ct.POINTER(ct.c_double)) if k in keep else None
+        op = RtOpacities(keep["temp"].size, keep["log10p"].size, dp("temp"), dp("log10p"),
+                         dp("kappa"), dp("cloud_abs"), dp("cloud_scat"), dp("cloud_g0"),
+                         float(tab["f_cloud"]), float(tab["m_mean"]), float(tab["x_h2"]),
+                         float(tab["x_he"]))
+        rt_set_opacities(self.h, op)
+
+    def optical_properties(self, atm: dict, sublayer: bool = False, stream=None) -> dict:
+        """dtau, w0, g0 device tensors of every slab from interface/centre T and
+        p device tensors (``atm``: p_iface, T_iface, p_center, T_center)."""
+        import torch
+        C = int(atm["T_iface"].shape[1])
+        N = int(atm["T_center"].shape[0])
+        S = 2 * N if sublayer else N
+        f = dict(dtype=torch.float64, device=torch.device("cuda", self.device))
+        out = {k: torch.empty((S, C, self.n_bins * self.n_gauss), **f)
+               for k in ("dtau", "w0", "g0")}
+        for k in ("p_iface", "T_iface", "p_center", "T_center"):
+            assert atm[k].is_cuda and atm[k].is_contiguous()
+        r = RtOpticsRequest(C, N, int(sublayer), 0, atm["p_iface"].data_ptr(),
+                            atm["T_iface"].data_ptr(), atm["p_center"].data_ptr(),
+                            atm["T_center"].data_ptr(), out["dtau"].data_ptr(),
+                            out["w0"].data_ptr(), out["g0"].data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rt_optical_properties(self.h, r, s.cuda_stream)
+        return out
 
     def poll(self, ticket: int) -> int:
         return rt_poll(self.h, ticket)
