@@ -299,16 +299,21 @@ class Solver:
                          float(tab["x_he"]))
         rt_set_opacities(self.h, op)
 
-    def optical_properties(self, atm: dict, sublayer: bool = False, stream=None) -> dict:
+    def optical_properties(self, atm: dict, sublayer: bool = False, stream=None,
+                           out: dict | None = None) -> dict:
         """dtau, w0, g0 device tensors of every slab from interface/centre T and
-        p device tensors (``atm``: p_iface, T_iface, p_center, T_center)."""
+        p device tensors (``atm``: p_iface, T_iface, p_center, T_center);
+        ``out`` reuses earlier output tensors."""
         import torch
         C = int(atm["T_iface"].shape[1])
         N = int(atm["T_center"].shape[0])
         S = 2 * N if sublayer else N
         f = dict(dtype=torch.float64, device=torch.device("cuda", self.device))
-        out = {k: torch.empty((S, C, self.n_bins * self.n_gauss), **f)
-               for k in ("dtau", "w0", "g0")}
+        if out is None:
+            out = {k: torch.empty((S, C, self.n_bins * self.n_gauss), **f)
+                   for k in ("dtau", "w0", "g0")}
+        for k in ("dtau", "w0", "g0"):
+            assert tuple(out[k].shape) == (S, C, self.n_bins * self.n_gauss)
         for k in ("p_iface", "T_iface", "p_center", "T_center"):
             assert atm[k].is_cuda and atm[k].is_contiguous()
         r = RtOpticsRequest(C, N, int(sublayer), 0, atm["p_iface"].data_ptr(),
