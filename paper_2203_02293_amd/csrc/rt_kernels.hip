@@ -301,7 +301,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 // ---------------------------------------------------------------------------
 struct LpLayout {
     size_t flag, mu;                               // persistent
-    size_t F, in, tau, B, rec, rfl, edge, front;   // forward sweep
+    size_t F, in, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
     size_t red, back;                              // back-substitution (aliases the forward)
     size_t total;
 };
@@ -318,7 +318,8 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.mu = o;   o += lp_align(8 * 2 * (size_t)K);              // mu, 1/mu per column
     const size_t base = o;
     L.F = o;    o += lp_align(8 * (PC + 1) * T);          // beam, rows = levels, row 0 = chunk top
-    L.in = o;   o += lp_align(8 * 3 * PC * T);            // dtau, w0, g0 of the chunk's layers
+    L.in = o;   o += lp_align(8 * 2 * 3 * PC * T);        // dtau, w0, g0 of a chunk's layers, 2 buffers
+    L.Tl = o;   o += lp_align(8 * 2 * (size_t)PC * K);    // T of a chunk's levels, 2 buffers
     L.tau = o;  o += lp_align(8 * 2 * T);                 // optical depth at the chunk top (2 buffers)
     L.B = o;    o += lp_align(rs * (PC + 1) * T);         // Planck bin radiance, rows as F
     L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
@@ -346,7 +347,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
-    double *s_in = reinterpret_cast<double *>(lds + Lo.in);           // [3][PC][T]
+    double *s_in0 = reinterpret_cast<double *>(lds + Lo.in);          // [2][3][PC][T]
+    double *s_T0 = reinterpret_cast<double *>(lds + Lo.Tl);           // [2][PC][K]
     double *s_tau = reinterpret_cast<double *>(lds + Lo.tau);         // [2][T]
     R *s_B = reinterpret_cast<R *>(lds + Lo.B);                       // [PC+1][T]
     R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
@@ -399,9 +401,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // with the elimination, a partial round leaves them out.
     const int rot = (tid + W - T) % W;
 
-    // Planck edge integrals of n levels lev0, lev0-1, ... (or of T_int) into
-    // edge rows 0..n-1, edge-major so a wavefront's lanes share one edge.
-    auto edges = [&](int lev0, int n, bool interior) {
+    // Planck edge integrals of n levels into edge rows 0..n-1, edge-major so a
+    // wavefront's lanes share one edge; temperatures from Ts[q][K] (LDS), or
+    // T_int when Ts is null.
+    auto edges = [&](const double *Ts, int n) {
         const int per = K * (NBR + 1);
         for (int e = rot; e < n * per; e += W) {
             const int q = e / per, rem = e - q * per;
@@ -409,7 +412,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
-                const double Tv = interior ? a.Tint[cc] : T_at(lev0 - q, cc);
+                const double Tv = Ts ? Ts[q * K + kk] : a.Tint[cc];
                 R x;
                 if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
                 else x = a.c2_over_lam[ee] * rcp(Tv);
@@ -453,31 +456,53 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
     };
 
-    // dtau, w0, g0 of layers s-1 .. s-n into LDS rows 0..n-1
-    auto stage = [&](int s, int n) {
-        for (int e = rot; e < n * T; e += W) {
-            const int q = e / T, l = e - q * T;
-            double dt = 0.0, w = 0.0, g = 0.0;
+    // A chunk's inputs (buffer buf): dtau, w0, g0 of layers s-1 .. s-n in rows
+    // 0..n-1 and T of levels s-1 .. s-n.  Loaded into registers first (one item
+    // per thread: the launch has n T <= W) and stored to LDS later, so the
+    // loads overlap other work.
+    struct Prefetch {
+        double dt, w, g, T;
+    };
+    auto load_chunk = [&](int s, int n, Prefetch &pf) {
+        pf.dt = pf.w = pf.g = 0.0;
+        if (tid < n * T) {
+            const int q = tid / T, l = tid - q * T;
             if (c0 + l / NB < C) {
                 const long long idx = (long long)(s - 1 - q) * LB + toff + l;
-                dt = a.dtau[idx];
-                w = a.w0[idx];
-                g = a.g0[idx];
+                pf.dt = a.dtau[idx];
+                pf.w = a.w0[idx];
+                pf.g = a.g0[idx];
             }
-            s_in[(0 * PC + q) * T + l] = dt;
-            s_in[(1 * PC + q) * T + l] = w;
-            s_in[(2 * PC + q) * T + l] = g;
         }
+        pf.T = 1.0;
+        if (tid < n * K) {
+            const int q = tid / K, kk = tid - q * K;
+            if (c0 + kk < C) pf.T = T_at(s - 1 - q, c0 + kk);
+        }
+    };
+    auto store_chunk = [&](int n, int buf, const Prefetch &pf) {
+        double *in = s_in0 + (size_t)buf * 3 * PC * T;
+        if (tid < n * T) {
+            const int q = tid / T, l = tid - q * T;
+            in[(0 * PC + q) * T + l] = pf.dt;
+            in[(1 * PC + q) * T + l] = pf.w;
+            in[(2 * PC + q) * T + l] = pf.g;
+        }
+        if (tid < n * K) s_T0[(size_t)buf * PC * K + tid] = pf.T;
     };
 
     // F_BOA = pi B_b(T_int) of the sweep lanes
-    edges(0, 1, true);
+    edges(nullptr, 1);
     __syncthreads();
     const double Fboa =
         active ? double(kPI) * double(bin_B(0, kl, bin_of(bl), a.Tint[c0 + kl])) : 0.0;
     __syncthreads();
-    // level N: Planck and the unattenuated beam, row 0
-    edges(N, 1, false);
+    // level N: Planck and the unattenuated beam, row 0 (its temperatures
+    // through the level-temperature buffer 1, which the first chunk does not use)
+    double *s_TN = s_T0 + (size_t)PC * K;
+    for (int kk = tid; kk < K; kk += W) s_TN[kk] = c0 + kk < C ? T_at(N, c0 + kk) : 1.0;
+    __syncthreads();
+    edges(s_TN, 1);
     __syncthreads();
     for (int l = tid; l < T; l += W) {
         const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
@@ -497,9 +522,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
     __syncthreads();
     beam_sums(0, N, 1);
-    // inputs and edge integrals of the first chunk
-    stage(N, min(PC, N));
-    edges(N - 1, min(PC, N), false);
+    // inputs and edge integrals of the first chunk (buffer 0)
+    {
+        Prefetch pf;
+        load_chunk(N, min(PC, N), pf);
+        store_chunk(min(PC, N), 0, pf);
+    }
+    __syncthreads();
+    edges(s_T0, min(PC, N));
     __syncthreads();
 
     ElimState st = elim_top(0.0);
@@ -509,14 +539,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         const int n = min(PC, s);          // layers s-1 .. s-n, levels s-1 .. s-n in rows 1..n
         const int s2 = s - n, n2 = min(PC, s2);
 
-        // (b) level items
+        const double *s_in = s_in0 + (size_t)cur * 3 * PC * T;   // this chunk's inputs
+        const double *s_Tc = s_T0 + (size_t)cur * PC * K;        // this chunk's level T
+
+        // (b) level items; the next chunk's inputs are loaded first and land in
+        // LDS (the other buffer) at the end of the phase
+        Prefetch pf;
+        if (n2 > 0) load_chunk(s2, n2, pf);
         for (int e = tid; e < n * T; e += W) {
             const int q = e / T, l = e - q * T;
             const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
             R B = R(0);
             double Fb = 0.0;
             if (cc < C) {
-                const double Tv = T_at(s - 1 - q, cc);
+                const double Tv = s_Tc[q * K + kk];
                 if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
                 const int rb = bin_of(b);
                 B = bin_B(q, kk, rb, Tv);
@@ -531,27 +567,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             s_B[(q + 1) * T + l] = B;
             s_F[(q + 1) * T + l] = Fb;
         }
+        if (n2 > 0) store_chunk(n2, cur ^ 1, pf);
         __syncthreads();
 
-        // (c) layer items.  Mixed: the next chunk's inputs are loaded first, into
-        // registers, and land in LDS in (d); FP64 items leave no registers for that.
-        double pf[2][3];
-        if constexpr (MIXED) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int e = tid + k * W;
-                pf[k][0] = pf[k][1] = pf[k][2] = 0.0;
-                if (e < n2 * T) {
-                    const int q = e / T, l = e - q * T;
-                    if (c0 + l / NB < C) {
-                        const long long idx = (long long)(s2 - 1 - q) * LB + toff + l;
-                        pf[k][0] = a.dtau[idx];
-                        pf[k][1] = a.w0[idx];
-                        pf[k][2] = a.g0[idx];
-                    }
-                }
-            }
-        }
+        // (c) layer items
         for (int e = tid; e < n * T; e += W) {
             const int q = e / T, l = e - q * T;
             const int kk = l / NB;
@@ -577,7 +596,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
         __syncthreads();
 
-        // (d) elimination through the chunk (sweep threads); next chunk staged meanwhile
+        // (d) elimination through the chunk (sweep threads); the next chunk's edge
+        // integrals meanwhile
         if (active) {
             for (int q = 0; q < n; ++q) {
                 const R *rp = s_rec + (size_t)q * 6 * T + tid;
@@ -597,21 +617,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             s_B[l] = s_B[(size_t)n * T + l];
             s_F[l] = s_F[(size_t)n * T + l];
         }
-        if constexpr (MIXED) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int e = tid + k * W;
-                if (e < n2 * T) {
-                    const int q = e / T, l = e - q * T;
-                    s_in[(0 * PC + q) * T + l] = pf[k][0];
-                    s_in[(1 * PC + q) * T + l] = pf[k][1];
-                    s_in[(2 * PC + q) * T + l] = pf[k][2];
-                }
-            }
-        } else {
-            stage(s2, n2);
-        }
-        if (n2 > 0) edges(s2 - 1, n2, false);
+        if (n2 > 0) edges(s_T0 + (size_t)(cur ^ 1) * PC * K, n2);
         cur ^= 1;
         s = s2;
         __syncthreads();
@@ -771,8 +777,9 @@ Geometry lane_geometry(int C, int NB, int K)
     return g;
 }
 
-// Levels per chunk: the largest work per barrier that fits LDS, with the
-// items of a chunk filling whole rounds of the workgroup (at most two).
+// Levels per chunk: the most work per barrier that fits LDS, with the items of
+// a chunk (PC x lanes) in one round of the workgroup: every thread prefetches
+// at most one item of the next chunk.
 Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev)
 {
     Geometry g{};
@@ -789,13 +796,11 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     if (T > wmax) return Geometry{};
     double best = -1.0;
     for (int pc = 1; pc <= 8; ++pc) {
-        if (pc * T > 2 * wmax) break;
+        if (pc * T > wmax) break;
         const LpLayout lo = lp_layout(K, NB, NB, pc, 1, mixed);
         if (lo.total > dev.lds) break;
-        int W = std::min(wmax, round64(pc * T));
-        W = std::max(W, round64(T));
-        const int rounds = (pc * T + W - 1) / W;
-        const double eff = double(pc * T) / (double(rounds) * W);
+        const int W = round64(pc * T);
+        const double eff = double(pc * T) / W;
         const double score = eff * (1.0 - 0.15 / pc);
         if (score > best) {
             best = score;
