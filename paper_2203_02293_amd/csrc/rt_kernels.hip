@@ -300,9 +300,9 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 // follow as in the lane kernel.
 // ---------------------------------------------------------------------------
 struct LpLayout {
-    size_t flag, mu;                               // persistent
+    size_t flag, mu, wl, part;                         // persistent
     size_t F, in, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
-    size_t red, back;                              // back-substitution (aliases the forward)
+    size_t red, back;                                  // back-substitution (aliases the forward)
     size_t total;
 };
 
@@ -316,6 +316,11 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     size_t o = 0;
     L.flag = o; o += lp_align(4 * (size_t)K);
     L.mu = o;   o += lp_align(8 * 2 * (size_t)K);              // mu, 1/mu per column
+    L.wl = o;   o += lp_align(8 * (size_t)NB);                 // weight of each lane of a column
+    size_t np = 1024;                                          // partial sums of the column sums
+    if ((size_t)2 * CH * K > np) np = (size_t)2 * CH * K;
+    if ((size_t)PC * K > np) np = (size_t)PC * K;
+    L.part = o; o += lp_align(8 * np);
     const size_t base = o;
     L.F = o;    o += lp_align(8 * (PC + 1) * T);          // beam, rows = levels, row 0 = chunk top
     L.in = o;   o += lp_align(8 * 2 * 3 * PC * T);        // dtau, w0, g0 of a chunk's layers, 2 buffers
@@ -346,6 +351,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const LpLayout Lo = lp_layout(K, NB, NBR, PC, CH, MIXED);
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
+    double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
+    double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // partial column sums
     double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
     double *s_in0 = reinterpret_cast<double *>(lds + Lo.in);          // [2][3][PC][T]
     double *s_T0 = reinterpret_cast<double *>(lds + Lo.Tl);           // [2][PC][K]
@@ -369,6 +376,29 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const long long gl = (long long)tile * T + tid;
     uint32_t fl = 0u;
 
+    // this thread's item of the level and layer phases (the launch has PC T <= W):
+    // row iq of the chunk, lane il = (column ikk, lane ib of the column, bin irb)
+    const int iq = tid / T, il = tid - iq * T;
+    const int ikk = il / NB, ib = il - ikk * NB;
+    const int irb = NG == 1 ? ib : ib / NG;
+    const bool icol = c0 + ikk < C;
+    // this thread's level-temperature slot (row tq, column tkk)
+    const int tq = tid / K, tkk = tid - tq * K;
+    // Item offset of this thread within a round of W items: the sweep threads
+    // (tid < T) take the last T offsets, so in phase (d), where they are busy
+    // with the elimination, a partial round leaves them out.
+    const int rot = (tid + W - T) % W;
+    // this thread's two edge items (offsets rot and rot + W of a chunk's edges)
+    const int per = K * (NBR + 1);
+    int eq[2], eee[2], ekk[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = rot + k * W, q = e / per, rem = e - q * per;
+        eq[k] = q;
+        eee[k] = rem / K;
+        ekk[k] = rem - eee[k] * K;
+    }
+
     for (int kk = tid; kk < K; kk += W) {
         const int cc = c0 + kk;
         double mu = 0.0;
@@ -383,6 +413,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         s_mu[K + kk] = mu > 0.0 ? 1.0 / mu : 0.0;
         s_flag[kk] = f0;
     }
+    for (int b = tid; b < NB; b += W) s_wl[b] = NG == 1 ? 1.0 : a.wg[b % NG];
 
     // Temperature of level l and the bin-summed output slot of level l: on the
     // sub-layer grid even levels are interfaces and odd levels layer centres.
@@ -396,19 +427,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         return iface + (long long)l * C + cc;
     };
 
-    // Item offset of this thread within a round of W items: the sweep threads
-    // (tid < T) take the last T offsets, so in phase (d), where they are busy
-    // with the elimination, a partial round leaves them out.
-    const int rot = (tid + W - T) % W;
-
     // Planck edge integrals of n levels into edge rows 0..n-1, edge-major so a
     // wavefront's lanes share one edge; temperatures from Ts[q][K] (LDS), or
     // T_int when Ts is null.
     auto edges = [&](const double *Ts, int n) {
-        const int per = K * (NBR + 1);
-        for (int e = rot; e < n * per; e += W) {
-            const int q = e / per, rem = e - q * per;
-            const int ee = rem / K, kk = rem - ee * K;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (eq[k] >= n) continue;
+            const int q = eq[k], ee = eee[k], kk = ekk[k];
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
@@ -421,8 +447,6 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             s_edge[(q * K + kk) * (NBR + 1) + ee] = v;
         }
     };
-    // Bin of a lane's (bin, Gaussian point) index, and the point's quadrature weight.
-    auto bin_of = [&](int b) -> int { return NG == 1 ? b : b / NG; };
     // Bin radiance of (column kk, bin b) from edge row q at temperature Td.
     auto bin_B = [&](int q, int kk, int b, double Td) -> R {
         const R Tr = R(Td), T2 = Tr * Tr;
@@ -435,67 +459,69 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
         return R(kPref) * T2 * T2 * I;
     };
-    // Sum over a column's lanes, weighted by the Gaussian points' weights.
-    auto lane_sum = [&](const double *row) -> double {
-        double sum = 0.0;
-        if (NG == 1) {
-            for (int b = 0; b < NB; ++b) sum += row[b];
-        } else {
-            for (int rb = 0; rb < NBR; ++rb)
-                for (int g = 0; g < NG; ++g) sum += a.wg[g] * row[rb * NG + g];
-        }
-        return sum;
+    // Column sums of nrows rows of lanes (row r of column kk at src + r rstride +
+    // kk NB), weighted by the Gaussian points' weights, in two steps with a
+    // barrier between: (1) P partial sums per (row, column), partial p over the
+    // lanes p, p+P, ... in order; (2) the P partials in order.  Fixed order, so
+    // repeated solves are bitwise identical.
+    auto colsum_P = [&](int nrows) -> int {
+        int P = W / (nrows * K);
+        return P < 1 ? 1 : (P > NB ? NB : P);
     };
-    // Beam bin sums of n levels held in beam rows r0.. (level lev0 - q in row r0 + q).
-    auto beam_sums = [&](int r0, int lev0, int n) {
-        for (int task = rot; task < n * K; task += W) {
-            const int q = task / K, kk = task - q * K, cc = c0 + kk;
-            if (cc >= C) continue;
-            const double sb = lane_sum(s_F + (size_t)(r0 + q) * T + kk * NB);
-            *out_at(a.F_beam, a.F_beam_c, lev0 - q, cc) = sb;
+    auto colsum_partials = [&](const double *src, int rstride, int nrows, int P) {
+        for (int t = tid; t < nrows * K * P; t += W) {
+            const int r = t / (K * P), rem = t - r * (K * P);
+            const int kk = rem / P, p = rem - kk * P;
+            const double *row = src + (size_t)r * rstride + kk * NB;
+            double sum = 0.0;
+            if (NG == 1) {
+                for (int b = p; b < NB; b += P) sum += row[b];
+            } else {
+                for (int b = p; b < NB; b += P) sum += s_wl[b] * row[b];
+            }
+            s_part[t] = sum;
         }
+    };
+    auto colsum_total = [&](int r, int kk, int P) -> double {
+        const double *pp = s_part + ((size_t)r * K + kk) * P;
+        double sum = 0.0;
+        for (int p = 0; p < P; ++p) sum += pp[p];
+        return sum;
     };
 
     // A chunk's inputs (buffer buf): dtau, w0, g0 of layers s-1 .. s-n in rows
     // 0..n-1 and T of levels s-1 .. s-n.  Loaded into registers first (one item
-    // per thread: the launch has n T <= W) and stored to LDS later, so the
-    // loads overlap other work.
+    // per thread) and stored to LDS later, so the loads overlap other work.
     struct Prefetch {
         double dt, w, g, T;
     };
     auto load_chunk = [&](int s, int n, Prefetch &pf) {
         pf.dt = pf.w = pf.g = 0.0;
-        if (tid < n * T) {
-            const int q = tid / T, l = tid - q * T;
-            if (c0 + l / NB < C) {
-                const long long idx = (long long)(s - 1 - q) * LB + toff + l;
-                pf.dt = a.dtau[idx];
-                pf.w = a.w0[idx];
-                pf.g = a.g0[idx];
-            }
+        if (iq < n && icol) {
+            const long long idx = (long long)(s - 1 - iq) * LB + toff + il;
+            pf.dt = a.dtau[idx];
+            pf.w = a.w0[idx];
+            pf.g = a.g0[idx];
         }
         pf.T = 1.0;
-        if (tid < n * K) {
-            const int q = tid / K, kk = tid - q * K;
-            if (c0 + kk < C) pf.T = T_at(s - 1 - q, c0 + kk);
-        }
+        if (tq < n && c0 + tkk < C) pf.T = T_at(s - 1 - tq, c0 + tkk);
     };
     auto store_chunk = [&](int n, int buf, const Prefetch &pf) {
         double *in = s_in0 + (size_t)buf * 3 * PC * T;
-        if (tid < n * T) {
-            const int q = tid / T, l = tid - q * T;
-            in[(0 * PC + q) * T + l] = pf.dt;
-            in[(1 * PC + q) * T + l] = pf.w;
-            in[(2 * PC + q) * T + l] = pf.g;
+        if (iq < n) {
+            in[(0 * PC + iq) * T + il] = pf.dt;
+            in[(1 * PC + iq) * T + il] = pf.w;
+            in[(2 * PC + iq) * T + il] = pf.g;
         }
-        if (tid < n * K) s_T0[(size_t)buf * PC * K + tid] = pf.T;
+        if (tq < n) s_T0[(size_t)buf * PC * K + tid] = pf.T;
     };
 
     // F_BOA = pi B_b(T_int) of the sweep lanes
     edges(nullptr, 1);
     __syncthreads();
     const double Fboa =
-        active ? double(kPI) * double(bin_B(0, kl, bin_of(bl), a.Tint[c0 + kl])) : 0.0;
+        active ? double(kPI) * double(bin_B(0, kl, NG == 1 ? bl : bl / NG, a.Tint[c0 + kl]))
+               : 0.0;
     __syncthreads();
     // level N: Planck and the unattenuated beam, row 0 (its temperatures
     // through the level-temperature buffer 1, which the first chunk does not use)
@@ -504,24 +530,28 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     __syncthreads();
     edges(s_TN, 1);
     __syncthreads();
-    for (int l = tid; l < T; l += W) {
-        const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
+    if (tid < T) {   // iq = 0, il = tid
         R B = R(0);
         double Fb = 0.0;
-        if (cc < C) {
-            const double Tv = T_at(N, cc);
-            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-            const int rb = bin_of(b);
-            B = bin_B(0, kk, rb, Tv);
-            const double mu = s_mu[kk];
-            if (mu > 0.0) Fb = mu * a.F_star[rb];
+        if (icol) {
+            const double Tv = s_TN[ikk];
+            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk], (uint32_t)F_INVALID);
+            B = bin_B(0, ikk, irb, Tv);
+            const double mu = s_mu[ikk];
+            if (mu > 0.0) Fb = mu * a.F_star[irb];
         }
-        s_B[l] = B;
-        s_F[l] = Fb;
-        s_tau[l] = 0.0;
+        s_B[tid] = B;
+        s_F[tid] = Fb;
+        s_tau[tid] = 0.0;
     }
     __syncthreads();
-    beam_sums(0, N, 1);
+    {
+        const int P = colsum_P(1);
+        colsum_partials(s_F, T, 1, P);
+        __syncthreads();
+        for (int kk = tid; kk < K; kk += W)
+            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, N, c0 + kk) = colsum_total(0, kk, P);
+    }
     // inputs and edge integrals of the first chunk (buffer 0)
     {
         Prefetch pf;
@@ -538,29 +568,27 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     for (int s = N; s > 0;) {
         const int n = min(PC, s);          // layers s-1 .. s-n, levels s-1 .. s-n in rows 1..n
         const int s2 = s - n, n2 = min(PC, s2);
-
         const double *s_in = s_in0 + (size_t)cur * 3 * PC * T;   // this chunk's inputs
         const double *s_Tc = s_T0 + (size_t)cur * PC * K;        // this chunk's level T
+        const int Pb = colsum_P(n);
 
         // (b) level items; the next chunk's inputs are loaded first and land in
         // LDS (the other buffer) at the end of the phase
         Prefetch pf;
         if (n2 > 0) load_chunk(s2, n2, pf);
-        for (int e = tid; e < n * T; e += W) {
-            const int q = e / T, l = e - q * T;
-            const int kk = l / NB, b = l - kk * NB, cc = c0 + kk;
+        if (iq < n) {
+            const int q = iq, l = il;
             R B = R(0);
             double Fb = 0.0;
-            if (cc < C) {
-                const double Tv = s_Tc[q * K + kk];
-                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-                const int rb = bin_of(b);
-                B = bin_B(q, kk, rb, Tv);
-                const double mu = s_mu[kk];
+            if (icol) {
+                const double Tv = s_Tc[q * K + ikk];
+                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk], (uint32_t)F_INVALID);
+                B = bin_B(q, ikk, irb, Tv);
+                const double mu = s_mu[ikk];
                 if (mu > 0.0) {
                     double tau = s_tau[cur * T + l];
                     for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
-                    Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
+                    Fb = beam_at<MIXED>(mu * a.F_star[irb], tau, s_mu[K + ikk]);
                     if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
                 }
             }
@@ -570,16 +598,16 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (n2 > 0) store_chunk(n2, cur ^ 1, pf);
         __syncthreads();
 
-        // (c) layer items
-        for (int e = tid; e < n * T; e += W) {
-            const int q = e / T, l = e - q * T;
-            const int kk = l / NB;
+        // (c) layer items; the beam's partial column sums of rows 1..n
+        colsum_partials(s_F + T, T, n, Pb);
+        if (iq < n) {
+            const int q = iq, l = il;
             uint32_t f = 0u;
             Layer<R> Ly{};
-            if (c0 + kk < C) {
-                const double mu = s_mu[kk];
+            if (icol) {
+                const double mu = s_mu[ikk];
                 const bool day = mu > 0.0;
-                const double inv_mu = s_mu[K + kk];
+                const double inv_mu = s_mu[K + ikk];
                 Ly = layer_item<MIXED, R>(s_in[(0 * PC + q) * T + l], s_in[(1 * PC + q) * T + l],
                                           s_in[(2 * PC + q) * T + l], day, mu, inv_mu,
                                           s_F[q * T + l], s_F[(q + 1) * T + l],
@@ -596,8 +624,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
         __syncthreads();
 
-        // (d) elimination through the chunk (sweep threads); the next chunk's edge
-        // integrals meanwhile
+        // (d) elimination through the chunk (sweep threads); the beam sums and the
+        // next chunk's edge integrals meanwhile
         if (active) {
             for (int q = 0; q < n; ++q) {
                 const R *rp = s_rec + (size_t)q * 6 * T + tid;
@@ -612,10 +640,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 sp[3 * L] = rec.d;
             }
         }
-        beam_sums(1, s - 1, n);
-        for (int l = tid; l < T; l += W) {   // level s-n becomes the next chunk's top
-            s_B[l] = s_B[(size_t)n * T + l];
-            s_F[l] = s_F[(size_t)n * T + l];
+        for (int t = rot; t < n * K; t += W) {
+            const int q = t / K, kk = t - q * K;
+            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, s - 1 - q, c0 + kk) = colsum_total(q, kk, Pb);
+        }
+        if (tid < T) {   // level s-n becomes the next chunk's top
+            s_B[tid] = s_B[(size_t)n * T + tid];
+            s_F[tid] = s_F[(size_t)n * T + tid];
         }
         if (n2 > 0) edges(s_T0 + (size_t)(cur ^ 1) * PC * K, n2);
         cur ^= 1;
@@ -631,8 +662,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
     __syncthreads();   // the bin-sum buffers alias the forward buffers
 
-    // back-substitution upward, bin sums in passes of CH interfaces; the next
-    // record is loaded one step ahead of its use
+    // back-substitution upward, bin sums in passes of CH levels; the next record
+    // is loaded one step ahead of its use
     double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
     if (active) {
         const double *sp = a.scratch + gl;
@@ -662,19 +693,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             }
         }
         __syncthreads();
-        for (int task = tid; task < K * CH; task += W) {
-            const int kk = task / CH, ii = task - kk * CH;
-            const int cc = c0 + kk;
-            if (ii >= nch || cc >= C) continue;
-            const double su = lane_sum(s_red + (0 * CH + ii) * T + kk * NB);
-            const double sd = lane_sum(s_red + (1 * CH + ii) * T + kk * NB);
-            const int lev = i0 + ii;
-            const double fn = su - sd - *out_at(a.F_beam, a.F_beam_c, lev, cc);   // written above
-            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
-            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
-            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
-            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
-        }
+        // rows 0..nch-1 hold F_up, rows CH..CH+nch-1 F_dn: both as one block of
+        // 2 CH rows (the unused rows of a short pass are summed and ignored)
+        const int P = colsum_P(2 * CH);
+        colsum_partials(s_red, T, 2 * CH, P);
         // TOA spectrum per bin: the weighted sum over the bin's Gaussian points
         if (NG > 1 && a.F_up_toa_bin && i0 + nch == N + 1) {
             for (int task = tid; task < K * NBR; task += W) {
@@ -685,6 +707,19 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 for (int g = 0; g < NG; ++g) sum += a.wg[g] * ru[g];
                 a.F_up_toa_bin[(long long)cc * NBR + rb] = sum;
             }
+        }
+        __syncthreads();
+        for (int task = tid; task < K * nch; task += W) {
+            const int ii = task / K, kk = task - ii * K, cc = c0 + kk;
+            if (cc >= C) continue;
+            const double su = colsum_total(ii, kk, P);
+            const double sd = colsum_total(CH + ii, kk, P);
+            const int lev = i0 + ii;
+            const double fn = su - sd - *out_at(a.F_beam, a.F_beam_c, lev, cc);   // written above
+            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
+            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
+            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
+            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
         }
         __syncthreads();
     }
