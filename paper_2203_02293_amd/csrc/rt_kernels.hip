@@ -299,6 +299,14 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 // holds few (column, bin) lanes.  The back-substitution and the bin sums
 // follow as in the lane kernel.
 // ---------------------------------------------------------------------------
+// Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
+// three wavefronts per SIMD can hold; the FP32 items fit four.
+__host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ? 1024 : 768; }
+// Items per thread and phase (level or layer items of a chunk).  One: a second
+// item's prefetch registers push the FP32 kernel past 128 VGPRs and into
+// spills, which costs more than the extra barriers of shorter chunks.
+__host__ __device__ constexpr int layer_items_per_thread(bool) { return 1; }
+
 struct LpLayout {
     size_t flag, mu, wl, part;                         // persistent
     size_t F, in, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
@@ -376,23 +384,35 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const long long gl = (long long)tile * T + tid;
     uint32_t fl = 0u;
 
-    // this thread's item of the level and layer phases (the launch has PC T <= W):
-    // row iq of the chunk, lane il = (column ikk, lane ib of the column, bin irb)
-    const int iq = tid / T, il = tid - iq * T;
-    const int ikk = il / NB, ib = il - ikk * NB;
-    const int irb = NG == 1 ? ib : ib / NG;
-    const bool icol = c0 + ikk < C;
-    // this thread's level-temperature slot (row tq, column tkk)
-    const int tq = tid / K, tkk = tid - tq * K;
+    // this thread's items of the level and layer phases (the launch has
+    // PC T <= IT W): item k is tid + k W, row iq of the chunk, lane il =
+    // (column ikk, lane ib of the column, bin irb); and its level-temperature
+    // slots (row tq, column tkk)
+    constexpr int IT = layer_items_per_thread(MIXED);
+    int iq[IT], il[IT], ikk[IT], irb[IT], tq[IT], tkk[IT];
+    bool icol[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int e = tid + k * W;
+        iq[k] = e / T;
+        il[k] = e - iq[k] * T;
+        ikk[k] = il[k] / NB;
+        const int ib = il[k] - ikk[k] * NB;
+        irb[k] = NG == 1 ? ib : ib / NG;
+        icol[k] = c0 + ikk[k] < C;
+        tq[k] = e / K;
+        tkk[k] = e - tq[k] * K;
+    }
     // Item offset of this thread within a round of W items: the sweep threads
     // (tid < T) take the last T offsets, so in phase (d), where they are busy
     // with the elimination, a partial round leaves them out.
     const int rot = (tid + W - T) % W;
-    // this thread's two edge items (offsets rot and rot + W of a chunk's edges)
+    // this thread's edge items (offsets rot + k W of a chunk's edges; a chunk has
+    // at most 2 IT W of them: K (NBR + 1) <= 2 T per level)
     const int per = K * (NBR + 1);
-    int eq[2], eee[2], ekk[2];
+    int eq[2 * IT], eee[2 * IT], ekk[2 * IT];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 2 * IT; ++k) {
         const int e = rot + k * W, q = e / per, rem = e - q * per;
         eq[k] = q;
         eee[k] = rem / K;
@@ -432,7 +452,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // T_int when Ts is null.
     auto edges = [&](const double *Ts, int n) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 2 * IT; ++k) {
             if (eq[k] >= n) continue;
             const int q = eq[k], ee = eee[k], kk = ekk[k];
             const int cc = c0 + kk;
@@ -464,9 +484,12 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // barrier between: (1) P partial sums per (row, column), partial p over the
     // lanes p, p+P, ... in order; (2) the P partials in order.  Fixed order, so
     // repeated solves are bitwise identical.
+    // P balances the two serial steps (about sqrt(NB) each) within the threads.
+    int Psq = 1;
+    while ((Psq + 1) * (Psq + 1) <= NB) ++Psq;
     auto colsum_P = [&](int nrows) -> int {
-        int P = W / (nrows * K);
-        return P < 1 ? 1 : (P > NB ? NB : P);
+        const int cap = W / (nrows * K);
+        return Psq > cap ? (cap < 1 ? 1 : cap) : Psq;
     };
     auto colsum_partials = [&](const double *src, int rstride, int nrows, int P) {
         for (int t = tid; t < nrows * K * P; t += W) {
@@ -493,27 +516,33 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // 0..n-1 and T of levels s-1 .. s-n.  Loaded into registers first (one item
     // per thread) and stored to LDS later, so the loads overlap other work.
     struct Prefetch {
-        double dt, w, g, T;
+        double dt[IT], w[IT], g[IT], T[IT];
     };
     auto load_chunk = [&](int s, int n, Prefetch &pf) {
-        pf.dt = pf.w = pf.g = 0.0;
-        if (iq < n && icol) {
-            const long long idx = (long long)(s - 1 - iq) * LB + toff + il;
-            pf.dt = a.dtau[idx];
-            pf.w = a.w0[idx];
-            pf.g = a.g0[idx];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            pf.dt[k] = pf.w[k] = pf.g[k] = 0.0;
+            if (iq[k] < n && icol[k]) {
+                const long long idx = (long long)(s - 1 - iq[k]) * LB + toff + il[k];
+                pf.dt[k] = a.dtau[idx];
+                pf.w[k] = a.w0[idx];
+                pf.g[k] = a.g0[idx];
+            }
+            pf.T[k] = 1.0;
+            if (tq[k] < n && c0 + tkk[k] < C) pf.T[k] = T_at(s - 1 - tq[k], c0 + tkk[k]);
         }
-        pf.T = 1.0;
-        if (tq < n && c0 + tkk < C) pf.T = T_at(s - 1 - tq, c0 + tkk);
     };
     auto store_chunk = [&](int n, int buf, const Prefetch &pf) {
         double *in = s_in0 + (size_t)buf * 3 * PC * T;
-        if (iq < n) {
-            in[(0 * PC + iq) * T + il] = pf.dt;
-            in[(1 * PC + iq) * T + il] = pf.w;
-            in[(2 * PC + iq) * T + il] = pf.g;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (iq[k] < n) {
+                in[(0 * PC + iq[k]) * T + il[k]] = pf.dt[k];
+                in[(1 * PC + iq[k]) * T + il[k]] = pf.w[k];
+                in[(2 * PC + iq[k]) * T + il[k]] = pf.g[k];
+            }
+            if (tq[k] < n) s_T0[(size_t)buf * PC * K + tid + k * W] = pf.T[k];
         }
-        if (tq < n) s_T0[(size_t)buf * PC * K + tid] = pf.T;
     };
 
     // F_BOA = pi B_b(T_int) of the sweep lanes
@@ -530,15 +559,15 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     __syncthreads();
     edges(s_TN, 1);
     __syncthreads();
-    if (tid < T) {   // iq = 0, il = tid
+    if (tid < T) {   // item 0: iq = 0, il = tid
         R B = R(0);
         double Fb = 0.0;
-        if (icol) {
-            const double Tv = s_TN[ikk];
-            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk], (uint32_t)F_INVALID);
-            B = bin_B(0, ikk, irb, Tv);
-            const double mu = s_mu[ikk];
-            if (mu > 0.0) Fb = mu * a.F_star[irb];
+        if (icol[0]) {
+            const double Tv = s_TN[ikk[0]];
+            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk[0]], (uint32_t)F_INVALID);
+            B = bin_B(0, ikk[0], irb[0], Tv);
+            const double mu = s_mu[ikk[0]];
+            if (mu > 0.0) Fb = mu * a.F_star[irb[0]];
         }
         s_B[tid] = B;
         s_F[tid] = Fb;
@@ -576,19 +605,21 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         // LDS (the other buffer) at the end of the phase
         Prefetch pf;
         if (n2 > 0) load_chunk(s2, n2, pf);
-        if (iq < n) {
-            const int q = iq, l = il;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (iq[k] >= n) continue;
+            const int q = iq[k], l = il[k], kk = ikk[k], rb = irb[k];
             R B = R(0);
             double Fb = 0.0;
-            if (icol) {
-                const double Tv = s_Tc[q * K + ikk];
-                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk], (uint32_t)F_INVALID);
-                B = bin_B(q, ikk, irb, Tv);
-                const double mu = s_mu[ikk];
+            if (icol[k]) {
+                const double Tv = s_Tc[q * K + kk];
+                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+                B = bin_B(q, kk, rb, Tv);
+                const double mu = s_mu[kk];
                 if (mu > 0.0) {
                     double tau = s_tau[cur * T + l];
                     for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
-                    Fb = beam_at<MIXED>(mu * a.F_star[irb], tau, s_mu[K + ikk]);
+                    Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
                     if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
                 }
             }
@@ -600,14 +631,16 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
 
         // (c) layer items; the beam's partial column sums of rows 1..n
         colsum_partials(s_F + T, T, n, Pb);
-        if (iq < n) {
-            const int q = iq, l = il;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (iq[k] >= n) continue;
+            const int q = iq[k], l = il[k], kk = ikk[k];
             uint32_t f = 0u;
             Layer<R> Ly{};
-            if (icol) {
-                const double mu = s_mu[ikk];
+            if (icol[k]) {
+                const double mu = s_mu[kk];
                 const bool day = mu > 0.0;
-                const double inv_mu = s_mu[K + ikk];
+                const double inv_mu = s_mu[K + kk];
                 Ly = layer_item<MIXED, R>(s_in[(0 * PC + q) * T + l], s_in[(1 * PC + q) * T + l],
                                           s_in[(2 * PC + q) * T + l], day, mu, inv_mu,
                                           s_F[q * T + l], s_F[(q + 1) * T + l],
@@ -749,9 +782,6 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
 }
 
-// Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
-// three wavefronts per SIMD can hold; the FP32 items fit four.
-__host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ? 1024 : 768; }
 
 // Workgroup of request r with first[r] <= g < first[r+1] (batched launches).
 __device__ __forceinline__ int batch_slot(const int *first, int n, int g)
@@ -813,8 +843,8 @@ Geometry lane_geometry(int C, int NB, int K)
 }
 
 // Levels per chunk: the most work per barrier that fits LDS, with the items of
-// a chunk (PC x lanes) in one round of the workgroup: every thread prefetches
-// at most one item of the next chunk.
+// a chunk (PC x lanes) in at most layer_items_per_thread rounds of the
+// workgroup (each thread prefetches that many items of the next chunk).
 Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev)
 {
     Geometry g{};
@@ -830,12 +860,14 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     const int wmax = layer_max_threads(mixed);
     if (T > wmax) return Geometry{};
     double best = -1.0;
+    const int it = layer_items_per_thread(mixed);
     for (int pc = 1; pc <= 8; ++pc) {
-        if (pc * T > wmax) break;
+        if (pc * T > it * wmax) break;
         const LpLayout lo = lp_layout(K, NB, NB, pc, 1, mixed);
         if (lo.total > dev.lds) break;
-        const int W = round64(pc * T);
-        const double eff = double(pc * T) / W;
+        const int W = std::min(wmax, round64(pc * T));
+        const int rounds = (pc * T + W - 1) / W;
+        const double eff = double(pc * T) / (double(rounds) * W);
         const double score = eff * (1.0 - 0.15 / pc);
         if (score > best) {
             best = score;
