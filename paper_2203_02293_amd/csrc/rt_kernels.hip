@@ -330,14 +330,14 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     if ((size_t)PC * K > np) np = (size_t)PC * K;
     L.part = o; o += lp_align(8 * np);
     const size_t base = o;
-    L.F = o;    o += lp_align(8 * (PC + 1) * T);          // beam, rows = levels, row 0 = chunk top
+    L.F = o;    o += lp_align(8 * 2 * (PC + 1) * T);      // beam: 2 blocks of levels, row 0 = chunk top
     L.in = o;   o += lp_align(8 * 2 * 3 * PC * T);        // dtau, w0, g0 of a chunk's layers, 2 buffers
-    L.Tl = o;   o += lp_align(8 * 2 * (size_t)PC * K);    // T of a chunk's levels, 2 buffers
+    L.Tl = o;   o += lp_align(8 * 3 * (size_t)PC * K);    // T of a chunk's levels, 3 slots
     L.tau = o;  o += lp_align(8 * 2 * T);                 // optical depth at the chunk top (2 buffers)
-    L.B = o;    o += lp_align(rs * (PC + 1) * T);         // Planck bin radiance, rows as F
+    L.B = o;    o += lp_align(rs * 2 * (PC + 1) * T);     // Planck bin radiance, blocks as F
     L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
     L.rfl = o;  o += lp_align(4 * PC * T);                // flags per layer
-    L.edge = o; o += lp_align(rs * PC * K * (NBR + 1));   // Planck edge integrals
+    L.edge = o; o += lp_align(rs * 2 * PC * K * (NBR + 1));   // Planck edge integrals, 2 buffers
     L.front = o;
     size_t ob = base;
     L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
@@ -361,14 +361,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
     double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // partial column sums
-    double *s_F = reinterpret_cast<double *>(lds + Lo.F);             // [PC+1][T]
+    double *s_F0 = reinterpret_cast<double *>(lds + Lo.F);            // [2][PC+1][T]
     double *s_in0 = reinterpret_cast<double *>(lds + Lo.in);          // [2][3][PC][T]
-    double *s_T0 = reinterpret_cast<double *>(lds + Lo.Tl);           // [2][PC][K]
+    double *s_T0 = reinterpret_cast<double *>(lds + Lo.Tl);           // [3][PC][K]
     double *s_tau = reinterpret_cast<double *>(lds + Lo.tau);         // [2][T]
-    R *s_B = reinterpret_cast<R *>(lds + Lo.B);                       // [PC+1][T]
+    R *s_B0 = reinterpret_cast<R *>(lds + Lo.B);                      // [2][PC+1][T]
     R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
     uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
-    R *s_edge = reinterpret_cast<R *>(lds + Lo.edge);                 // [PC][K][NBR+1]
+    R *s_edge0 = reinterpret_cast<R *>(lds + Lo.edge);                // [2][PC][K][NBR+1]
     double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
 
     const int c0 = tile * K;                    // first column of the tile
@@ -447,10 +447,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         return iface + (long long)l * C + cc;
     };
 
-    // Planck edge integrals of n levels into edge rows 0..n-1, edge-major so a
-    // wavefront's lanes share one edge; temperatures from Ts[q][K] (LDS), or
-    // T_int when Ts is null.
-    auto edges = [&](const double *Ts, int n) {
+    // Planck edge integrals of n levels into rows 0..n-1 of edge buffer s_edge,
+    // edge-major so a wavefront's lanes share one edge; temperatures from
+    // Ts[q][K] (LDS), or T_int when Ts is null.
+    auto edges = [&](R *s_edge, const double *Ts, int n) {
 #pragma unroll
         for (int k = 0; k < 2 * IT; ++k) {
             if (eq[k] >= n) continue;
@@ -467,8 +467,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             s_edge[(q * K + kk) * (NBR + 1) + ee] = v;
         }
     };
-    // Bin radiance of (column kk, bin b) from edge row q at temperature Td.
-    auto bin_B = [&](int q, int kk, int b, double Td) -> R {
+    // Bin radiance of (column kk, bin b) from row q of edge buffer s_edge at
+    // temperature Td.
+    auto bin_B = [&](const R *s_edge, int q, int kk, int b, double Td) -> R {
         const R Tr = R(Td), T2 = Tr * Tr;
         const R *row = s_edge + (q * K + kk) * (NBR + 1);
         R I = planck_combine<R>(row[b], row[b + 1]);
@@ -532,6 +533,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (tq[k] < n && c0 + tkk[k] < C) pf.T[k] = T_at(s - 1 - tq[k], c0 + tkk[k]);
         }
     };
+    // The temperature of this thread's level slot of a chunk (1 if none).
+    auto load_T = [&](int s, int n) -> double {
+        return (tq[0] < n && c0 + tkk[0] < C) ? T_at(s - 1 - tq[0], c0 + tkk[0]) : 1.0;
+    };
     auto store_chunk = [&](int n, int buf, const Prefetch &pf) {
         double *in = s_in0 + (size_t)buf * 3 * PC * T;
 #pragma unroll
@@ -545,19 +550,66 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
     };
 
+    // Chunks of levels from the TOA: chunk c has top level s_c (s_0 = N) and n_c =
+    // min(PC, s_c) levels s_c - 1 .. s_c - n_c below it (and the layers between).
+    // Its levels live in row block c % 2 of s_B/s_F (row 0 = top level), its
+    // inputs in s_in buffer c % 2, its edge integrals in edge buffer c % 2 and its
+    // level temperatures in slot c % 3.
+    auto blockB = [&](int c) { return s_B0 + (size_t)(c & 1) * (PC + 1) * T; };
+    auto blockF = [&](int c) { return s_F0 + (size_t)(c & 1) * (PC + 1) * T; };
+    auto ebuf = [&](int c) { return s_edge0 + (size_t)(c & 1) * PC * K * (NBR + 1); };
+    auto tslot = [&](int c) { return s_T0 + (size_t)(c % 3) * PC * K; };
+    auto inbuf = [&](int c) { return s_in0 + (size_t)(c & 1) * 3 * PC * T; };
+
+    // Level items of chunk c (top level s, n levels): bin radiance from the
+    // edge integrals and the direct beam from the optical depth summed down
+    // from the TOA, into rows 1..n of the chunk's block.
+    auto level_items = [&](int c, int s, int n) {
+        if (iq[0] >= n) return;
+        const int q = iq[0], l = il[0], kk = ikk[0], rb = irb[0];
+        const double *in = inbuf(c);
+        R B = R(0);
+        double Fb = 0.0;
+        if (icol[0]) {
+            const double Tv = tslot(c)[q * K + kk];
+            if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
+            B = bin_B(ebuf(c), q, kk, rb, Tv);
+            const double mu = s_mu[kk];
+            if (mu > 0.0) {
+                double tau = s_tau[(c & 1) * T + l];
+                for (int qq = 0; qq <= q; ++qq) tau += in[qq * T + l];   // from the TOA down
+                Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
+                if (q == n - 1) s_tau[((c + 1) & 1) * T + l] = tau;
+            }
+        }
+        blockB(c)[(q + 1) * T + l] = B;
+        blockF(c)[(q + 1) * T + l] = Fb;
+    };
+
     // F_BOA = pi B_b(T_int) of the sweep lanes
-    edges(nullptr, 1);
+    edges(ebuf(0), nullptr, 1);
     __syncthreads();
     const double Fboa =
-        active ? double(kPI) * double(bin_B(0, kl, NG == 1 ? bl : bl / NG, a.Tint[c0 + kl]))
+        active ? double(kPI) * double(bin_B(ebuf(0), 0, kl, NG == 1 ? bl : bl / NG,
+                                            a.Tint[c0 + kl]))
                : 0.0;
     __syncthreads();
-    // level N: Planck and the unattenuated beam, row 0 (its temperatures
-    // through the level-temperature buffer 1, which the first chunk does not use)
-    double *s_TN = s_T0 + (size_t)PC * K;
+
+    // prologue: level N (top of chunk 0) and chunk 0's level items; temperatures
+    // of chunks 0 and 1 and inputs of chunk 0 into LDS
+    const int n0 = min(PC, N), s1 = N - n0, n1 = min(PC, s1);
+    {
+        Prefetch pf;
+        load_chunk(N, n0, pf);
+        store_chunk(n0, 0, pf);          // inputs and level temperatures of chunk 0
+        if (n1 > 0 && tq[0] < n1) tslot(1)[tid] = load_T(s1, n1);
+    }
+    double *s_TN = s_part;   // level N temperatures (the partial sums are not in use yet)
     for (int kk = tid; kk < K; kk += W) s_TN[kk] = c0 + kk < C ? T_at(N, c0 + kk) : 1.0;
+    if (tid < T) s_tau[tid] = 0.0;
     __syncthreads();
-    edges(s_TN, 1);
+    edges(ebuf(1), s_TN, 1);             // level N into edge buffer 1 (chunk 1 fills it later)
+    edges(ebuf(0), tslot(0), n0);
     __syncthreads();
     if (tid < T) {   // item 0: iq = 0, il = tid
         R B = R(0);
@@ -565,86 +617,56 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (icol[0]) {
             const double Tv = s_TN[ikk[0]];
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk[0]], (uint32_t)F_INVALID);
-            B = bin_B(0, ikk[0], irb[0], Tv);
+            B = bin_B(ebuf(1), 0, ikk[0], irb[0], Tv);
             const double mu = s_mu[ikk[0]];
             if (mu > 0.0) Fb = mu * a.F_star[irb[0]];
         }
-        s_B[tid] = B;
-        s_F[tid] = Fb;
-        s_tau[tid] = 0.0;
+        blockB(0)[tid] = B;
+        blockF(0)[tid] = Fb;
     }
+    level_items(0, N, n0);
     __syncthreads();
     {
         const int P = colsum_P(1);
-        colsum_partials(s_F, T, 1, P);
+        colsum_partials(blockF(0), T, 1, P);
+        if (n1 > 0) edges(ebuf(1), tslot(1), n1);   // level N is done with buffer 1
         __syncthreads();
         for (int kk = tid; kk < K; kk += W)
             if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, N, c0 + kk) = colsum_total(0, kk, P);
     }
-    // inputs and edge integrals of the first chunk (buffer 0)
-    {
-        Prefetch pf;
-        load_chunk(N, min(PC, N), pf);
-        store_chunk(min(PC, N), 0, pf);
-    }
-    __syncthreads();
-    edges(s_T0, min(PC, N));
     __syncthreads();
 
     ElimState st = elim_top(0.0);
     if (active && a.Ftoa) st = elim_top(a.Ftoa[toff + tid]);
-    int cur = 0;
-    for (int s = N; s > 0;) {
-        const int n = min(PC, s);          // layers s-1 .. s-n, levels s-1 .. s-n in rows 1..n
-        const int s2 = s - n, n2 = min(PC, s2);
-        const double *s_in = s_in0 + (size_t)cur * 3 * PC * T;   // this chunk's inputs
-        const double *s_Tc = s_T0 + (size_t)cur * PC * K;        // this chunk's level T
+    int c = 0;
+    for (int s = N; s > 0; ++c) {
+        const int n = min(PC, s);                     // this chunk
+        const int sA = s - n, nA = min(PC, sA);       // the next chunk
+        const int sB = sA - nA, nB = min(PC, sB);     // the one after
+        const double *in = inbuf(c);
+        const R *cB = blockB(c);
+        const double *cF = blockF(c);
         const int Pb = colsum_P(n);
 
-        // (b) level items; the next chunk's inputs are loaded first and land in
-        // LDS (the other buffer) at the end of the phase
+        // P1: layer items of this chunk and the partial beam sums of its levels;
+        // the next chunk's inputs and the level temperatures of the chunk after
+        // are loaded first and stored to LDS at the end of the phase
         Prefetch pf;
-        if (n2 > 0) load_chunk(s2, n2, pf);
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            if (iq[k] >= n) continue;
-            const int q = iq[k], l = il[k], kk = ikk[k], rb = irb[k];
-            R B = R(0);
-            double Fb = 0.0;
-            if (icol[k]) {
-                const double Tv = s_Tc[q * K + kk];
-                if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-                B = bin_B(q, kk, rb, Tv);
-                const double mu = s_mu[kk];
-                if (mu > 0.0) {
-                    double tau = s_tau[cur * T + l];
-                    for (int qq = 0; qq <= q; ++qq) tau += s_in[qq * T + l];   // from the TOA down
-                    Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
-                    if (q == n - 1) s_tau[(cur ^ 1) * T + l] = tau;
-                }
-            }
-            s_B[(q + 1) * T + l] = B;
-            s_F[(q + 1) * T + l] = Fb;
-        }
-        if (n2 > 0) store_chunk(n2, cur ^ 1, pf);
-        __syncthreads();
-
-        // (c) layer items; the beam's partial column sums of rows 1..n
-        colsum_partials(s_F + T, T, n, Pb);
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            if (iq[k] >= n) continue;
-            const int q = iq[k], l = il[k], kk = ikk[k];
+        load_chunk(sA, nA, pf);
+        const double tB = load_T(sB, nB);
+        colsum_partials(cF + T, T, n, Pb);
+        if (iq[0] < n) {
+            const int q = iq[0], l = il[0], kk = ikk[0];
             uint32_t f = 0u;
             Layer<R> Ly{};
-            if (icol[k]) {
+            if (icol[0]) {
                 const double mu = s_mu[kk];
                 const bool day = mu > 0.0;
                 const double inv_mu = s_mu[K + kk];
-                Ly = layer_item<MIXED, R>(s_in[(0 * PC + q) * T + l], s_in[(1 * PC + q) * T + l],
-                                          s_in[(2 * PC + q) * T + l], day, mu, inv_mu,
-                                          s_F[q * T + l], s_F[(q + 1) * T + l],
-                                          s_B[(q + 1) * T + l], s_B[q * T + l], a.o, inv_eps2, f);
+                Ly = layer_item<MIXED, R>(in[(0 * PC + q) * T + l], in[(1 * PC + q) * T + l],
+                                          in[(2 * PC + q) * T + l], day, mu, inv_mu,
+                                          cF[q * T + l], cF[(q + 1) * T + l],
+                                          cB[(q + 1) * T + l], cB[q * T + l], a.o, inv_eps2, f);
             }
             R *rp = s_rec + (size_t)q * 6 * T + l;
             rp[0] = Ly.t;
@@ -655,10 +677,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             rp[5 * T] = Ly.Sdn;
             s_rfl[q * T + l] = f;
         }
+        if (nA > 0) {
+            double *ni = s_in0 + (size_t)((c + 1) & 1) * 3 * PC * T;
+            if (iq[0] < nA) {
+                ni[(0 * PC + iq[0]) * T + il[0]] = pf.dt[0];
+                ni[(1 * PC + iq[0]) * T + il[0]] = pf.w[0];
+                ni[(2 * PC + iq[0]) * T + il[0]] = pf.g[0];
+            }
+        }
+        if (nB > 0 && tq[0] < nB) tslot(c + 2)[tid] = tB;
         __syncthreads();
 
-        // (d) elimination through the chunk (sweep threads); the beam sums and the
-        // next chunk's edge integrals meanwhile
+        // P2: elimination through this chunk (sweep threads), its beam sums, the
+        // carry of its last level to the top of the next block, the next chunk's
+        // level items and the edge integrals of the chunk after
         if (active) {
             for (int q = 0; q < n; ++q) {
                 const R *rp = s_rec + (size_t)q * 6 * T + tid;
@@ -678,19 +710,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, s - 1 - q, c0 + kk) = colsum_total(q, kk, Pb);
         }
         if (tid < T) {   // level s-n becomes the next chunk's top
-            s_B[tid] = s_B[(size_t)n * T + tid];
-            s_F[tid] = s_F[(size_t)n * T + tid];
+            blockB(c + 1)[tid] = cB[(size_t)n * T + tid];
+            blockF(c + 1)[tid] = cF[(size_t)n * T + tid];
         }
-        if (n2 > 0) edges(s_T0 + (size_t)(cur ^ 1) * PC * K, n2);
-        cur ^= 1;
-        s = s2;
+        if (nA > 0) level_items(c + 1, sA, nA);
+        if (nB > 0) edges(ebuf(c + 2), tslot(c + 2), nB);
+        s = sA;
         __syncthreads();
     }
 
-    // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0 (row 0 holds level 0 now)
+    // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0 (level 0 is the top row
+    // of the block after the last chunk)
     double Fu = 0.0, Fd = 0.0;
     if (active) {
-        elim_boa(st, Fboa, s_F[tid], Fu, Fd);
+        elim_boa(st, Fboa, blockF(c)[tid], Fu, Fd);
         if (fl) atomicOr(&s_flag[kl], fl);
     }
     __syncthreads();   // the bin-sum buffers alias the forward buffers
