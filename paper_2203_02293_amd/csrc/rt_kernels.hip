@@ -110,7 +110,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
         if constexpr (MIXED) {
             const R iT = rcp(T);
             const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
-            if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
+            if (planck_narrow(xa, xb)) I = planck_gl3<R>(xa, xb);
         }
         return R(kPref) * T2 * T2 * I;
     };
@@ -296,8 +296,10 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 //       next chunk's Planck edge integrals and the beam bin sums.
 // Items of (b) and (c) are spread over all threads of the workgroup, so the
 // transcendental work of a chunk runs at full occupancy even when the grid
-// holds few (column, bin) lanes.  The back-substitution and the bin sums
-// follow as in the lane kernel.
+// holds few (column, bin) lanes.  The records are 32 bytes per (layer, lane)
+// (G, H, c, d); the back-substitution reads them back in passes of 8
+// interfaces through a register ring, one pass ahead, and closes each pass
+// with its bin sums.
 // ---------------------------------------------------------------------------
 // Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
 // three wavefronts per SIMD can hold; the FP32 items fit four.
@@ -306,11 +308,14 @@ __host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ?
 // item's prefetch registers push the FP32 kernel past 128 VGPRs and into
 // spills, which costs more than the extra barriers of shorter chunks.
 __host__ __device__ constexpr int layer_items_per_thread(bool) { return 1; }
+// Back-substitution records (2 x 16 bytes per layer and lane) that one thread
+// stages per pass: bounds the interfaces per pass, CH, by 2 CH T <= kBackUnits W.
+constexpr int kBackUnits = 8;
 
 struct LpLayout {
     size_t flag, mu, wl, part;                         // persistent
     size_t F, in, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
-    size_t red, back;                                  // back-substitution (aliases the forward)
+    size_t red, brec, back;                            // back-substitution (aliases the forward)
     size_t total;
 };
 
@@ -327,6 +332,7 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.wl = o;   o += lp_align(8 * (size_t)NB);                 // weight of each lane of a column
     size_t np = 1024;                                          // partial sums of the column sums
     if ((size_t)2 * CH * K > np) np = (size_t)2 * CH * K;
+    if ((size_t)2 * K > np) np = (size_t)2 * K;                // (prologue: T_N, T_int per column)
     if ((size_t)PC * K > np) np = (size_t)PC * K;
     L.part = o; o += lp_align(8 * np);
     const size_t base = o;
@@ -337,10 +343,11 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.B = o;    o += lp_align(rs * 2 * (PC + 1) * T);     // Planck bin radiance, blocks as F
     L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
     L.rfl = o;  o += lp_align(4 * PC * T);                // flags per layer
-    L.edge = o; o += lp_align(rs * 2 * PC * K * (NBR + 1));   // Planck edge integrals, 2 buffers
+    L.edge = o; o += lp_align(rs * (2 * PC + 1) * K * (NBR + 1));   // Planck edge integrals, 2 buffers + T_int row
     L.front = o;
     size_t ob = base;
     L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
+    L.brec = ob; ob += lp_align(16 * 2 * (size_t)CH * T); // records of CH layers
     L.back = ob;
     L.total = L.front > L.back ? L.front : L.back;
     return L;
@@ -368,7 +375,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     R *s_B0 = reinterpret_cast<R *>(lds + Lo.B);                      // [2][PC+1][T]
     R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
     uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
-    R *s_edge0 = reinterpret_cast<R *>(lds + Lo.edge);                // [2][PC][K][NBR+1]
+    R *s_edge0 = reinterpret_cast<R *>(lds + Lo.edge);                // [2 PC + 1][K][NBR+1]
     double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
 
     const int c0 = tile * K;                    // first column of the tile
@@ -419,21 +426,6 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         ekk[k] = rem - eee[k] * K;
     }
 
-    for (int kk = tid; kk < K; kk += W) {
-        const int cc = c0 + kk;
-        double mu = 0.0;
-        uint32_t f0 = 0u;
-        if (cc < C) {
-            mu = a.mu[cc];
-            if (!isfinite(mu)) f0 |= F_INVALID;
-            const double ti = a.Tint[cc];
-            if (!(ti >= 0.0) || !isfinite(ti)) f0 |= F_INVALID;
-        }
-        s_mu[kk] = mu;
-        s_mu[K + kk] = mu > 0.0 ? 1.0 / mu : 0.0;
-        s_flag[kk] = f0;
-    }
-    for (int b = tid; b < NB; b += W) s_wl[b] = NG == 1 ? 1.0 : a.wg[b % NG];
 
     // Temperature of level l and the bin-summed output slot of level l: on the
     // sub-layer grid even levels are interfaces and odd levels layer centres.
@@ -449,7 +441,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
 
     // Planck edge integrals of n levels into rows 0..n-1 of edge buffer s_edge,
     // edge-major so a wavefront's lanes share one edge; temperatures from
-    // Ts[q][K] (LDS), or T_int when Ts is null.
+    // Ts[q][K] (LDS).
     auto edges = [&](R *s_edge, const double *Ts, int n) {
 #pragma unroll
         for (int k = 0; k < 2 * IT; ++k) {
@@ -458,7 +450,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
-                const double Tv = Ts ? Ts[q * K + kk] : a.Tint[cc];
+                const double Tv = Ts[q * K + kk];
                 R x;
                 if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
                 else x = a.c2_over_lam[ee] * rcp(Tv);
@@ -476,7 +468,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if constexpr (MIXED) {
             const R iT = rcp(Tr);
             const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
-            if (xb - xa <= R(0.5)) I = planck_gl3<R>(xa, xb);
+            if (planck_narrow(xa, xb)) I = planck_gl3<R>(xa, xb);
         }
         return R(kPref) * T2 * T2 * I;
     };
@@ -586,32 +578,53 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         blockF(c)[(q + 1) * T + l] = Fb;
     };
 
-    // F_BOA = pi B_b(T_int) of the sweep lanes
-    edges(ebuf(0), nullptr, 1);
-    __syncthreads();
-    const double Fboa =
-        active ? double(kPI) * double(bin_B(ebuf(0), 0, kl, NG == 1 ? bl : bl / NG,
-                                            a.Tint[c0 + kl]))
-               : 0.0;
-    __syncthreads();
-
-    // prologue: level N (top of chunk 0) and chunk 0's level items; temperatures
-    // of chunks 0 and 1 and inputs of chunk 0 into LDS
+    // Prologue.  Its global inputs are loaded at once: chunk 0's inputs and
+    // level temperatures, chunk 1's level temperatures, per column mu, T_int
+    // and T at level N, and the TOA downward flux of the sweep lanes.
     const int n0 = min(PC, N), s1 = N - n0, n1 = min(PC, s1);
+    double *s_TN = s_part;       // [K] T at level N, [K] T_int (the partial sums
+    double *s_Ti = s_part + K;   // are not in use before the first chunk)
+    R *ebuf_x = s_edge0 + (size_t)2 * PC * K * (NBR + 1);   // T_int edge row
+    const double ftoa = (active && a.Ftoa) ? a.Ftoa[toff + tid] : 0.0;
     {
         Prefetch pf;
         load_chunk(N, n0, pf);
+        const double t1 = load_T(s1, n1);
+        for (int kk = tid; kk < K; kk += W) {
+            const int cc = c0 + kk;
+            double mu = 0.0, ti = 1.0, tn = 1.0;
+            uint32_t f0 = 0u;
+            if (cc < C) {
+                mu = a.mu[cc];
+                ti = a.Tint[cc];
+                tn = T_at(N, cc);
+                if (!isfinite(mu)) f0 |= F_INVALID;
+                if (!(ti >= 0.0) || !isfinite(ti)) f0 |= F_INVALID;
+            }
+            s_mu[kk] = mu;
+            s_mu[K + kk] = mu > 0.0 ? 1.0 / mu : 0.0;
+            s_flag[kk] = f0;
+            s_TN[kk] = tn;
+            s_Ti[kk] = ti;
+        }
+        for (int b = tid; b < NB; b += W) s_wl[b] = NG == 1 ? 1.0 : a.wg[b % NG];
+        if (tid < T) s_tau[tid] = 0.0;
         store_chunk(n0, 0, pf);          // inputs and level temperatures of chunk 0
-        if (n1 > 0 && tq[0] < n1) tslot(1)[tid] = load_T(s1, n1);
+        if (n1 > 0 && tq[0] < n1) tslot(1)[tid] = t1;
     }
-    double *s_TN = s_part;   // level N temperatures (the partial sums are not in use yet)
-    for (int kk = tid; kk < K; kk += W) s_TN[kk] = c0 + kk < C ? T_at(N, c0 + kk) : 1.0;
-    if (tid < T) s_tau[tid] = 0.0;
     __syncthreads();
-    edges(ebuf(1), s_TN, 1);             // level N into edge buffer 1 (chunk 1 fills it later)
+    // edge integrals of T_int, of level N (row 0 of buffer 1, which chunk 1
+    // fills during the first chunk) and of chunk 0
+    edges(ebuf_x, s_Ti, 1);
+    edges(ebuf(1), s_TN, 1);
     edges(ebuf(0), tslot(0), n0);
     __syncthreads();
-    if (tid < T) {   // item 0: iq = 0, il = tid
+    // F_BOA = pi B_b(T_int) of the sweep lanes; level N (item 0: iq = 0, il =
+    // tid) and chunk 0's level items
+    const double Fboa =
+        active ? double(kPI) * double(bin_B(ebuf_x, 0, kl, NG == 1 ? bl : bl / NG, s_Ti[kl]))
+               : 0.0;
+    if (tid < T) {
         R B = R(0);
         double Fb = 0.0;
         if (icol[0]) {
@@ -626,18 +639,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
     level_items(0, N, n0);
     __syncthreads();
-    {
-        const int P = colsum_P(1);
-        colsum_partials(blockF(0), T, 1, P);
-        if (n1 > 0) edges(ebuf(1), tslot(1), n1);   // level N is done with buffer 1
-        __syncthreads();
-        for (int kk = tid; kk < K; kk += W)
-            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, N, c0 + kk) = colsum_total(0, kk, P);
-    }
-    __syncthreads();
 
-    ElimState st = elim_top(0.0);
-    if (active && a.Ftoa) st = elim_top(a.Ftoa[toff + tid]);
+    ElimState st = elim_top(ftoa);
     int c = 0;
     for (int s = N; s > 0; ++c) {
         const int n = min(PC, s);                     // this chunk
@@ -646,7 +649,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         const double *in = inbuf(c);
         const R *cB = blockB(c);
         const double *cF = blockF(c);
-        const int Pb = colsum_P(n);
+        // beam sums of the chunk's levels: rows 1..n, and row 0 (level N) in chunk 0
+        const int r0 = c == 0 ? 0 : 1, nr = n + 1 - r0;
+        const int Pb = colsum_P(nr);
 
         // P1: layer items of this chunk and the partial beam sums of its levels;
         // the next chunk's inputs and the level temperatures of the chunk after
@@ -654,7 +659,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         Prefetch pf;
         load_chunk(sA, nA, pf);
         const double tB = load_T(sB, nB);
-        colsum_partials(cF + T, T, n, Pb);
+        colsum_partials(cF + (size_t)r0 * T, T, nr, Pb);
+        if (c == 0 && nA > 0) edges(ebuf(1), tslot(1), nA);   // level N is done with buffer 1
         if (iq[0] < n) {
             const int q = iq[0], l = il[0], kk = ikk[0];
             uint32_t f = 0u;
@@ -698,16 +704,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 const BackRec rec = elim_step(st, double(rp[0]), double(rp[T]), double(rp[2 * T]),
                                               double(rp[3 * T]), double(rp[4 * T]),
                                               double(rp[5 * T]));
-                double *sp = a.scratch + (long long)(s - 1 - q) * 4 * L + gl;
-                sp[0] = rec.G;
-                sp[L] = rec.H;
-                sp[2 * L] = rec.c;
-                sp[3 * L] = rec.d;
+                double2 *sp = reinterpret_cast<double2 *>(a.scratch) + ((long long)(s - 1 - q) * L + gl) * 2;
+                sp[0] = make_double2(rec.G, rec.H);
+                sp[1] = make_double2(rec.c, rec.d);
             }
         }
-        for (int t = rot; t < n * K; t += W) {
+        for (int t = rot; t < nr * K; t += W) {
             const int q = t / K, kk = t - q * K;
-            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, s - 1 - q, c0 + kk) = colsum_total(q, kk, Pb);
+            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, s - r0 - q, c0 + kk) = colsum_total(q, kk, Pb);
         }
         if (tid < T) {   // level s-n becomes the next chunk's top
             blockB(c + 1)[tid] = cB[(size_t)n * T + tid];
@@ -728,29 +732,63 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
     __syncthreads();   // the bin-sum buffers alias the forward buffers
 
-    // back-substitution upward, bin sums in passes of CH levels; the next record
-    // is loaded one step ahead of its use
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-    if (active) {
-        const double *sp = a.scratch + gl;
-        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L];
+    // back-substitution upward in passes of CH interfaces, each closed by its
+    // bin sums.  A pass's records are staged in LDS (s_brec[ii][lane] = (G, H),
+    // (c, d) of the layer below interface i0 + ii): every thread loads its
+    // share of the next pass's records into registers while the sweep lanes
+    // run this pass, and stores them once this pass's records are used.  The
+    // loads are unconditional (index clamped to a valid record) so that none
+    // of them has to complete before the store.
+    constexpr int MU = kBackUnits;
+    double2 *s_brec = reinterpret_cast<double2 *>(lds + Lo.brec);   // [CH][T][2]
+    const double2 *rec2 = reinterpret_cast<const double2 *>(a.scratch);
+    const int units = 2 * CH * T;
+    int uii[MU], uoff[MU];   // level in the pass, offset (lane, half) of the unit
+#pragma unroll
+    for (int k = 0; k < MU; ++k) {
+        const int e = min(tid + k * W, units - 1);
+        uii[k] = e / (2 * T);
+        uoff[k] = (tile * T) * 2 + (e - uii[k] * 2 * T);
     }
+    double rx[MU], ry[MU];   // staged units (scalars, so that they stay in registers)
+    auto rec_fetch = [&](int i0n) {
+#pragma unroll
+        for (int k = 0; k < MU; ++k) {
+            int jl = i0n + uii[k] - 1;
+            if (jl < 0 || jl >= N) jl = 0;
+            const double2 v = rec2[(long long)jl * 2 * L + uoff[k]];
+            rx[k] = v.x;
+            ry[k] = v.y;
+        }
+    };
+    auto rec_store = [&]() {
+#pragma unroll
+        for (int k = 0; k < MU; ++k)
+            if (tid + k * W < units) s_brec[tid + k * W] = make_double2(rx[k], ry[k]);
+    };
+    rec_fetch(0);
+    rec_store();
+    __syncthreads();
+    const int P = colsum_P(2 * CH);
     for (int i0 = 0; i0 <= N; i0 += CH) {
         const int nch = min(CH, N + 1 - i0);
+        rec_fetch(i0 + CH);   // the next pass (clamped, unused, after the last)
+        // the beam flux of this thread's first bin-sum task, read ahead
+        double fbp = 0.0;
+        if (tid < K * nch) {
+            const int ii = tid / K, kk = tid - ii * K;
+            if (c0 + kk < C) fbp = *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk);
+        }
         for (int ii = 0; ii < nch; ++ii) {
             const int i = i0 + ii;
             if (active) {
                 if (i > 0) {
-                    const double G = r0, H = r1, cj = r2, dj = r3;
-                    if (i < N) {
-                        const double *sp = a.scratch + (long long)i * 4 * L + gl;
-                        r0 = sp[0]; r1 = sp[L]; r2 = sp[2 * L]; r3 = sp[3 * L];
-                    }
-                    back_step(G, H, cj, dj, Fu, Fd);
+                    const double2 gh = s_brec[(ii * T + tid) * 2], cd = s_brec[(ii * T + tid) * 2 + 1];
+                    back_step(gh.x, gh.y, cd.x, cd.y, Fu, Fd);
                 }
-                const long long k = (long long)i * LB + toff + tid;
-                if (a.F_up_bin) a.F_up_bin[k] = Fu;
-                if (a.F_dn_bin) a.F_dn_bin[k] = Fd;
+                const long long o = (long long)i * LB + toff + tid;
+                if (a.F_up_bin) a.F_up_bin[o] = Fu;
+                if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
                 if (i == N && a.F_up_toa_bin && NG == 1) a.F_up_toa_bin[toff + tid] = Fu;
             }
             if (sweep) {
@@ -759,36 +797,42 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             }
         }
         __syncthreads();
+        // outputs of level i0 + ii from its bin sums and the beam sum written
+        // by the forward sweep
+        auto level_out = [&](int ii, int kk, double su, double sd, double fb) {
+            const int lev = i0 + ii, cc = c0 + kk;
+            const double fn = su - sd - fb;
+            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
+            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
+            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
+            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
+        };
         // rows 0..nch-1 hold F_up, rows CH..CH+nch-1 F_dn: both as one block of
         // 2 CH rows (the unused rows of a short pass are summed and ignored)
-        const int P = colsum_P(2 * CH);
         colsum_partials(s_red, T, 2 * CH, P);
         // TOA spectrum per bin: the weighted sum over the bin's Gaussian points
         if (NG > 1 && a.F_up_toa_bin && i0 + nch == N + 1) {
             for (int task = tid; task < K * NBR; task += W) {
                 const int kk = task / NBR, rb = task - kk * NBR, cc = c0 + kk;
                 if (cc >= C) continue;
-                const double *ru = s_red + (0 * CH + (N - i0)) * T + kk * NB + rb * NG;
+                const double *ru_ = s_red + (0 * CH + (N - i0)) * T + kk * NB + rb * NG;
                 double sum = 0.0;
-                for (int g = 0; g < NG; ++g) sum += a.wg[g] * ru[g];
+                for (int g = 0; g < NG; ++g) sum += a.wg[g] * ru_[g];
                 a.F_up_toa_bin[(long long)cc * NBR + rb] = sum;
             }
         }
+        if (i0 + CH <= N) rec_store();   // this pass's records are used
         __syncthreads();
+        // (the next pass writes s_red, read above, and s_part only after its
+        // first barrier, so no barrier closes the pass)
         for (int task = tid; task < K * nch; task += W) {
-            const int ii = task / K, kk = task - ii * K, cc = c0 + kk;
-            if (cc >= C) continue;
-            const double su = colsum_total(ii, kk, P);
-            const double sd = colsum_total(CH + ii, kk, P);
-            const int lev = i0 + ii;
-            const double fn = su - sd - *out_at(a.F_beam, a.F_beam_c, lev, cc);   // written above
-            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
-            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
-            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
-            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
+            const int ii = task / K, kk = task - ii * K;
+            if (c0 + kk >= C) continue;
+            level_out(ii, kk, colsum_total(ii, kk, P), colsum_total(CH + ii, kk, P),
+                      task == tid ? fbp : *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk));
         }
-        __syncthreads();
     }
+    __syncthreads();   // every level's F_net is written before the heating reads it
 
     // heating of each layer from the net flux at its two interfaces (written above)
     const int NL = sub ? N / 2 : N;
@@ -909,10 +953,13 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
         }
     }
     if (best < 0.0) return Geometry{};
-    // interfaces per bin-sum pass: as many as fit in the forward sweep's bytes
-    const LpLayout lo = lp_layout(K, NB, NB, g.PC, 1, mixed);
+    // interfaces per back-substitution pass: as many as fit in the forward
+    // sweep's bytes and in the threads' staging registers
+    const size_t front = lp_layout(K, NB, NB, g.PC, 1, mixed).total;
     int ch = 1;
-    while (ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= lo.total) ++ch;
+    while (ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= front &&
+           2 * (ch + 1) * T <= kBackUnits * g.threads)
+        ++ch;
     g.CH = ch;
     g.K = K;
     g.blocks = (C + K - 1) / K;

@@ -90,14 +90,29 @@ __host__ __device__ __forceinline__ double rcp(double x)
 #endif
 }
 
+// FP32: the hardware reciprocal alone (within one ulp), enough for the FP32
+// coefficient build.
 __host__ __device__ __forceinline__ float rcp(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    float y = __builtin_amdgcn_rcpf(x);
-    return fma(y, fma(-x, y, 1.0f), y);
+    return __builtin_amdgcn_rcpf(x);
 #else
     return 1.0f / x;
 #endif
 }
+
+// Square root of a non-negative finite argument: the hardware instruction in
+// FP32 (within one ulp; the library sqrtf adds a correction to round it
+// correctly), the correctly rounded one in FP64.
+__host__ __device__ __forceinline__ float sqrt_nn(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ double sqrt_nn(double x) { return sqrt(x); }
 
 }  // namespace rtk

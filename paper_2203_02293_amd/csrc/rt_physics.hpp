@@ -190,6 +190,21 @@ __host__ __device__ __forceinline__ R planck_gl3(R xa, R xb)
     return h * acc;
 }
 
+// Whether the FP32 difference of the two edge values of bin [xa, xb] would
+// lose more than about 4 bits (edge value over bin integral above ~16), so
+// that the bin takes the quadrature above instead.  Below XS both edges are
+// integrals from 0 that grow like x^3/3, and the loss depends only on the
+// bin's relative width: (xa/xb)^3 > 15/16.  Above XS (and across it) the edge
+// values are at most pi^4/15 (large x: x^3 e^-x (1 + 3/x + ...)) against an
+// integral of about (xb - xa) times the integrand: xb - xa <= 0.3 bounds the
+// ratio by ~16.
+template <class R>
+__host__ __device__ __forceinline__ bool planck_narrow(R xa, R xb)
+{
+    if (xb > PCfg<R>::XS) return xb - xa <= R(0.3);
+    return xa * xa * xa > R(0.9375) * (xb * xb * xb);
+}
+
 // ---------------------------------------------------------------------------
 // Predicates in FP64, rounded exactly as the printed formulas read left to
 // right (no contraction), so that both precisions take the paper's branch
@@ -240,7 +255,7 @@ __host__ __device__ __forceinline__ R hfun(R u, R T)
         // (sinh u - u)/u^2 = u sum_{k>=1} u^{2(k-1)} / (2k+1)!
         return T * u * sinhc_horner<R, 1, ShCfg<R>::N>(u * u);
     }
-    return (R(0.5) * (R(1) - T * T) - u * T) / (u * u);
+    return (R(0.5) * (R(1) - T * T) - u * T) * rcp(u * u);
 }
 
 template <class R>
@@ -263,7 +278,7 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
     R kap = R(2) * Eom;
     const R iEom = rcp(Eom);
     R ik = R(0.5) * iEom;   // 1/kappa
-    R s = sqrt(Ew * iEom);
+    R s = sqrt_nn(Ew * iEom);
     R lam = kap * s;
     R u = lam * dtau;
     ExpEm1<R> ex = exp_em1(-u);
