@@ -313,8 +313,8 @@ __host__ __device__ constexpr int layer_items_per_thread(bool) { return 1; }
 constexpr int kBackUnits = 8;
 
 struct LpLayout {
-    size_t flag, mu, wl, part;                         // persistent
-    size_t F, in, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
+    size_t flag, mu, wl, part, np;                     // persistent
+    size_t F, dt, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
     size_t red, brec, back;                            // back-substitution (aliases the forward)
     size_t total;
 };
@@ -330,20 +330,22 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.flag = o; o += lp_align(4 * (size_t)K);
     L.mu = o;   o += lp_align(8 * 2 * (size_t)K);              // mu, 1/mu per column
     L.wl = o;   o += lp_align(8 * (size_t)NB);                 // weight of each lane of a column
-    size_t np = 1024;                                          // partial sums of the column sums
+    // partial sums of the column sums, 2 buffers: a chunk's beam partials
+    // (at most W of them) are written while the previous chunk's are summed
+    size_t np = 1024;
     if ((size_t)2 * CH * K > np) np = (size_t)2 * CH * K;
     if ((size_t)2 * K > np) np = (size_t)2 * K;                // (prologue: T_N, T_int per column)
-    if ((size_t)PC * K > np) np = (size_t)PC * K;
-    L.part = o; o += lp_align(8 * np);
+    L.np = np;
+    L.part = o; o += lp_align(8 * 2 * np);
     const size_t base = o;
     L.F = o;    o += lp_align(8 * 2 * (PC + 1) * T);      // beam: 2 blocks of levels, row 0 = chunk top
-    L.in = o;   o += lp_align(8 * 2 * 3 * PC * T);        // dtau, w0, g0 of a chunk's layers, 2 buffers
+    L.dt = o;   o += lp_align(8 * 2 * (size_t)PC * T);    // dtau of a chunk's layers, 2 buffers
     L.Tl = o;   o += lp_align(8 * 3 * (size_t)PC * K);    // T of a chunk's levels, 3 slots
     L.tau = o;  o += lp_align(8 * 2 * T);                 // optical depth at the chunk top (2 buffers)
     L.B = o;    o += lp_align(rs * 2 * (PC + 1) * T);     // Planck bin radiance, blocks as F
-    L.rec = o;  o += lp_align(rs * 6 * PC * T);           // t r omr A S_up S_dn per layer
-    L.rfl = o;  o += lp_align(4 * PC * T);                // flags per layer
-    L.edge = o; o += lp_align(rs * (2 * PC + 1) * K * (NBR + 1));   // Planck edge integrals, 2 buffers + T_int row
+    L.rec = o;  o += lp_align(rs * 2 * 6 * PC * T);       // t r omr A S_up S_dn per layer, 2 buffers
+    L.rfl = o;  o += lp_align(4 * 2 * PC * T);            // flags per layer, 2 buffers
+    L.edge = o; o += lp_align(rs * (2 * PC + 2) * K * (NBR + 1));   // Planck edge integrals, 2 buffers + T_int, T_N rows
     L.front = o;
     size_t ob = base;
     L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
@@ -367,15 +369,15 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
-    double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // partial column sums
+    double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // [2][np] partial column sums
     double *s_F0 = reinterpret_cast<double *>(lds + Lo.F);            // [2][PC+1][T]
-    double *s_in0 = reinterpret_cast<double *>(lds + Lo.in);          // [2][3][PC][T]
+    double *s_dt0 = reinterpret_cast<double *>(lds + Lo.dt);          // [2][PC][T]
     double *s_T0 = reinterpret_cast<double *>(lds + Lo.Tl);           // [3][PC][K]
     double *s_tau = reinterpret_cast<double *>(lds + Lo.tau);         // [2][T]
     R *s_B0 = reinterpret_cast<R *>(lds + Lo.B);                      // [2][PC+1][T]
-    R *s_rec = reinterpret_cast<R *>(lds + Lo.rec);                   // [PC][6][T]
-    uint32_t *s_rfl = reinterpret_cast<uint32_t *>(lds + Lo.rfl);     // [PC][T]
-    R *s_edge0 = reinterpret_cast<R *>(lds + Lo.edge);                // [2 PC + 1][K][NBR+1]
+    R *s_rec0 = reinterpret_cast<R *>(lds + Lo.rec);                  // [2][6][PC][T]
+    uint32_t *s_rfl0 = reinterpret_cast<uint32_t *>(lds + Lo.rfl);    // [2][PC][T]
+    R *s_edge0 = reinterpret_cast<R *>(lds + Lo.edge);                // [2 PC + 2][K][NBR+1]
     double *s_red = reinterpret_cast<double *>(lds + Lo.red);         // [2][CH][T]
 
     const int c0 = tile * K;                    // first column of the tile
@@ -484,7 +486,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         const int cap = W / (nrows * K);
         return Psq > cap ? (cap < 1 ? 1 : cap) : Psq;
     };
-    auto colsum_partials = [&](const double *src, int rstride, int nrows, int P) {
+    auto colsum_partials = [&](double *part, const double *src, int rstride, int nrows, int P) {
         for (int t = tid; t < nrows * K * P; t += W) {
             const int r = t / (K * P), rem = t - r * (K * P);
             const int kk = rem / P, p = rem - kk * P;
@@ -495,101 +497,157 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             } else {
                 for (int b = p; b < NB; b += P) sum += s_wl[b] * row[b];
             }
-            s_part[t] = sum;
+            part[t] = sum;
         }
     };
-    auto colsum_total = [&](int r, int kk, int P) -> double {
-        const double *pp = s_part + ((size_t)r * K + kk) * P;
+    auto colsum_total = [&](const double *part, int r, int kk, int P) -> double {
+        const double *pp = part + ((size_t)r * K + kk) * P;
         double sum = 0.0;
         for (int p = 0; p < P; ++p) sum += pp[p];
         return sum;
     };
 
-    // A chunk's inputs (buffer buf): dtau, w0, g0 of layers s-1 .. s-n in rows
-    // 0..n-1 and T of levels s-1 .. s-n.  Loaded into registers first (one item
-    // per thread) and stored to LDS later, so the loads overlap other work.
-    struct Prefetch {
-        double dt[IT], w[IT], g[IT], T[IT];
+    // Chunks of levels from the TOA: chunk m has top level s_m = N - m PC and
+    // n_m = min(PC, s_m) levels s_m - 1 .. s_m - n_m below it (and the layers
+    // between); NCH chunks in all.  Each chunk passes through
+    //   E(m)  Planck edge integrals of its levels,
+    //   V(m)  level items: bin radiance and direct beam of its levels (rows
+    //         1..n of its row block; row 0 is the last level of chunk m-1),
+    //   Y(m)  layer items: coefficients and normalised sources of its layers,
+    //   Z(m)  the FP64 elimination through its layers (sweep threads),
+    // and its beam bin sums (partials, then totals).  Phase m of the loop runs
+    // Z(m), Y(m+1), V(m+2) and E(m+3), the partials of chunk m+1 and the
+    // totals of chunk m, with one barrier at its end.  Buffers, by chunk
+    // parity unless noted: row blocks s_B/s_F, edge rows, layer records,
+    // dtau rows, beam partials; level temperatures in slot m % 3.  dtau, w0
+    // and g0 of an item are loaded by the thread that owns the item; w0 and
+    // g0 stay in its registers, dtau goes to LDS for the optical-depth sums.
+    const int NCH = (N + PC - 1) / PC;
+    auto ctop = [&](int m) { return N - m * PC; };
+    auto cn = [&](int m) { return m < NCH ? min(PC, N - m * PC) : 0; };
+    auto blockB = [&](int m) { return s_B0 + (size_t)(m & 1) * (PC + 1) * T; };
+    auto blockF = [&](int m) { return s_F0 + (size_t)(m & 1) * (PC + 1) * T; };
+    auto ebuf = [&](int m) { return s_edge0 + (size_t)(m & 1) * PC * K * (NBR + 1); };
+    auto tslot = [&](int m) { return s_T0 + (size_t)(m % 3) * PC * K; };
+    auto dbuf = [&](int m) { return s_dt0 + (size_t)(m & 1) * PC * T; };
+    auto rbuf = [&](int m) { return s_rec0 + (size_t)(m & 1) * 6 * PC * T; };
+    auto fbuf = [&](int m) { return s_rfl0 + (size_t)(m & 1) * PC * T; };
+    auto pbuf = [&](int m) { return s_part + (size_t)(m & 1) * Lo.np; };
+
+    // this thread's item of chunk m: input index, and its level-temperature slot
+    auto item_idx = [&](int m) -> long long {
+        return (long long)(ctop(m) - 1 - iq[0]) * LB + toff + il[0];
     };
-    auto load_chunk = [&](int s, int n, Prefetch &pf) {
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            pf.dt[k] = pf.w[k] = pf.g[k] = 0.0;
-            if (iq[k] < n && icol[k]) {
-                const long long idx = (long long)(s - 1 - iq[k]) * LB + toff + il[k];
-                pf.dt[k] = a.dtau[idx];
-                pf.w[k] = a.w0[idx];
-                pf.g[k] = a.g0[idx];
-            }
-            pf.T[k] = 1.0;
-            if (tq[k] < n && c0 + tkk[k] < C) pf.T[k] = T_at(s - 1 - tq[k], c0 + tkk[k]);
+    auto has_item = [&](int m) { return iq[0] < cn(m) && icol[0]; };
+    auto load_dt = [&](int m) -> double { return has_item(m) ? a.dtau[item_idx(m)] : 0.0; };
+    auto load_wg = [&](int m, double &w, double &g) {
+        w = g = 0.0;
+        if (has_item(m)) {
+            const long long idx = item_idx(m);
+            w = a.w0[idx];
+            g = a.g0[idx];
         }
     };
-    // The temperature of this thread's level slot of a chunk (1 if none).
-    auto load_T = [&](int s, int n) -> double {
-        return (tq[0] < n && c0 + tkk[0] < C) ? T_at(s - 1 - tq[0], c0 + tkk[0]) : 1.0;
+    auto load_T = [&](int m) -> double {
+        return (tq[0] < cn(m) && c0 + tkk[0] < C) ? T_at(ctop(m) - 1 - tq[0], c0 + tkk[0]) : 1.0;
     };
-    auto store_chunk = [&](int n, int buf, const Prefetch &pf) {
-        double *in = s_in0 + (size_t)buf * 3 * PC * T;
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            if (iq[k] < n) {
-                in[(0 * PC + iq[k]) * T + il[k]] = pf.dt[k];
-                in[(1 * PC + iq[k]) * T + il[k]] = pf.w[k];
-                in[(2 * PC + iq[k]) * T + il[k]] = pf.g[k];
-            }
-            if (tq[k] < n) s_T0[(size_t)buf * PC * K + tid + k * W] = pf.T[k];
+    auto store_dt = [&](int m, double v) { if (iq[0] < cn(m)) dbuf(m)[iq[0] * T + il[0]] = v; };
+    auto store_T = [&](int m, double v) { if (tq[0] < cn(m)) tslot(m)[tid] = v; };
+
+    // V(m): the carry of chunk m-1's last level into row 0, then this thread's
+    // level item (rows 1..n), and the optical depth at the top of chunk m+1
+    auto level_items = [&](int m) {
+        const int n = cn(m);
+        if (m > 0 && tid < T) {
+            blockB(m)[tid] = blockB(m - 1)[(size_t)cn(m - 1) * T + tid];
+            blockF(m)[tid] = blockF(m - 1)[(size_t)cn(m - 1) * T + tid];
         }
-    };
-
-    // Chunks of levels from the TOA: chunk c has top level s_c (s_0 = N) and n_c =
-    // min(PC, s_c) levels s_c - 1 .. s_c - n_c below it (and the layers between).
-    // Its levels live in row block c % 2 of s_B/s_F (row 0 = top level), its
-    // inputs in s_in buffer c % 2, its edge integrals in edge buffer c % 2 and its
-    // level temperatures in slot c % 3.
-    auto blockB = [&](int c) { return s_B0 + (size_t)(c & 1) * (PC + 1) * T; };
-    auto blockF = [&](int c) { return s_F0 + (size_t)(c & 1) * (PC + 1) * T; };
-    auto ebuf = [&](int c) { return s_edge0 + (size_t)(c & 1) * PC * K * (NBR + 1); };
-    auto tslot = [&](int c) { return s_T0 + (size_t)(c % 3) * PC * K; };
-    auto inbuf = [&](int c) { return s_in0 + (size_t)(c & 1) * 3 * PC * T; };
-
-    // Level items of chunk c (top level s, n levels): bin radiance from the
-    // edge integrals and the direct beam from the optical depth summed down
-    // from the TOA, into rows 1..n of the chunk's block.
-    auto level_items = [&](int c, int s, int n) {
         if (iq[0] >= n) return;
         const int q = iq[0], l = il[0], kk = ikk[0], rb = irb[0];
-        const double *in = inbuf(c);
+        const double *dt = dbuf(m);
         R B = R(0);
         double Fb = 0.0;
         if (icol[0]) {
-            const double Tv = tslot(c)[q * K + kk];
+            const double Tv = tslot(m)[q * K + kk];
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[kk], (uint32_t)F_INVALID);
-            B = bin_B(ebuf(c), q, kk, rb, Tv);
+            B = bin_B(ebuf(m), q, kk, rb, Tv);
             const double mu = s_mu[kk];
             if (mu > 0.0) {
-                double tau = s_tau[(c & 1) * T + l];
-                for (int qq = 0; qq <= q; ++qq) tau += in[qq * T + l];   // from the TOA down
+                double tau = s_tau[(m & 1) * T + l];
+                for (int qq = 0; qq <= q; ++qq) tau += dt[qq * T + l];   // from the TOA down
                 Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
-                if (q == n - 1) s_tau[((c + 1) & 1) * T + l] = tau;
+                if (q == n - 1) s_tau[((m + 1) & 1) * T + l] = tau;
             }
         }
-        blockB(c)[(q + 1) * T + l] = B;
-        blockF(c)[(q + 1) * T + l] = Fb;
+        blockB(m)[(q + 1) * T + l] = B;
+        blockF(m)[(q + 1) * T + l] = Fb;
+    };
+    // Y(m): this thread's layer item, w0 and g0 from its registers
+    auto layer_items = [&](int m, double w, double g) {
+        const int n = cn(m);
+        if (iq[0] >= n) return;
+        const int q = iq[0], l = il[0], kk = ikk[0];
+        const R *cB = blockB(m);
+        const double *cF = blockF(m);
+        uint32_t f = 0u;
+        Layer<R> Ly{};
+        if (icol[0]) {
+            const double mu = s_mu[kk];
+            Ly = layer_item<MIXED, R>(dbuf(m)[q * T + l], w, g, mu > 0.0, mu, s_mu[K + kk],
+                                      cF[q * T + l], cF[(q + 1) * T + l], cB[(q + 1) * T + l],
+                                      cB[q * T + l], a.o, inv_eps2, f);
+        }
+        R *rp = rbuf(m) + (size_t)q * T + l;
+        const size_t ps = (size_t)PC * T;
+        rp[0] = Ly.t;
+        rp[ps] = Ly.r;
+        rp[2 * ps] = Ly.omr;
+        rp[3 * ps] = Ly.A;
+        rp[4 * ps] = Ly.Sup;
+        rp[5 * ps] = Ly.Sdn;
+        fbuf(m)[q * T + l] = f;
+    };
+    // beam bin sums of chunk m's levels: rows 1..n (rows 0..n in chunk 0,
+    // whose row 0 is level N)
+    auto beam_rows = [&](int m, int &r0, int &nr) {
+        r0 = m == 0 ? 0 : 1;
+        nr = cn(m) + 1 - r0;
+    };
+    auto beam_partials = [&](int m) {
+        int r0, nr;
+        beam_rows(m, r0, nr);
+        colsum_partials(pbuf(m), blockF(m) + (size_t)r0 * T, T, nr, colsum_P(nr));
+    };
+    auto beam_totals = [&](int m) {
+        int r0, nr;
+        beam_rows(m, r0, nr);
+        const int P = colsum_P(nr);
+        for (int t = rot; t < nr * K; t += W) {
+            const int q = t / K, kk = t - q * K;
+            if (c0 + kk < C)
+                *out_at(a.F_beam, a.F_beam_c, ctop(m) - r0 - q, c0 + kk) = colsum_total(pbuf(m), q, kk, P);
+        }
     };
 
-    // Prologue.  Its global inputs are loaded at once: chunk 0's inputs and
-    // level temperatures, chunk 1's level temperatures, per column mu, T_int
-    // and T at level N, and the TOA downward flux of the sweep lanes.
-    const int n0 = min(PC, N), s1 = N - n0, n1 = min(PC, s1);
+    // Prologue.  Its global inputs are loaded at once: per column mu, T_int
+    // and T at level N, the level temperatures of chunks 0..3, dtau of chunks
+    // 0..2, w0 and g0 of chunks 0 and 1, and the TOA downward flux of the
+    // sweep lanes.  Then E(0), E(1); V(0); V(1), Y(0), E(2) and chunk 0's beam
+    // partials, each step behind a barrier.
     double *s_TN = s_part;       // [K] T at level N, [K] T_int (the partial sums
-    double *s_Ti = s_part + K;   // are not in use before the first chunk)
+    double *s_Ti = s_part + K;   // are not in use before the last prologue step)
     R *ebuf_x = s_edge0 + (size_t)2 * PC * K * (NBR + 1);   // T_int edge row
+    R *ebuf_n = ebuf_x + (size_t)K * (NBR + 1);             // level N edge row
     const double ftoa = (active && a.Ftoa) ? a.Ftoa[toff + tid] : 0.0;
+    double w_c, g_c, w_n, g_n;   // w0, g0 of this thread's items of the next two Y phases
+    double dt_p, T_p;            // dtau and level temperature loaded ahead, stored later
     {
-        Prefetch pf;
-        load_chunk(N, n0, pf);
-        const double t1 = load_T(s1, n1);
+        const double d0 = load_dt(0), d1 = load_dt(1);
+        const double t0 = load_T(0), t1 = load_T(1), t2 = load_T(2);
+        load_wg(0, w_c, g_c);
+        load_wg(1, w_n, g_n);
+        dt_p = load_dt(2);
+        T_p = load_T(3);
         for (int kk = tid; kk < K; kk += W) {
             const int cc = c0 + kk;
             double mu = 0.0, ti = 1.0, tn = 1.0;
@@ -609,18 +667,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         }
         for (int b = tid; b < NB; b += W) s_wl[b] = NG == 1 ? 1.0 : a.wg[b % NG];
         if (tid < T) s_tau[tid] = 0.0;
-        store_chunk(n0, 0, pf);          // inputs and level temperatures of chunk 0
-        if (n1 > 0 && tq[0] < n1) tslot(1)[tid] = t1;
+        store_dt(0, d0);
+        store_dt(1, d1);
+        store_T(0, t0);
+        store_T(1, t1);
+        store_T(2, t2);
     }
     __syncthreads();
-    // edge integrals of T_int, of level N (row 0 of buffer 1, which chunk 1
-    // fills during the first chunk) and of chunk 0
     edges(ebuf_x, s_Ti, 1);
-    edges(ebuf(1), s_TN, 1);
-    edges(ebuf(0), tslot(0), n0);
+    edges(ebuf_n, s_TN, 1);
+    edges(ebuf(0), tslot(0), cn(0));
+    edges(ebuf(1), tslot(1), cn(1));
     __syncthreads();
-    // F_BOA = pi B_b(T_int) of the sweep lanes; level N (item 0: iq = 0, il =
-    // tid) and chunk 0's level items
+    // F_BOA = pi B_b(T_int) of the sweep lanes; level N (row 0 of block 0:
+    // item iq = 0, il = tid) and V(0)
     const double Fboa =
         active ? double(kPI) * double(bin_B(ebuf_x, 0, kl, NG == 1 ? bl : bl / NG, s_Ti[kl]))
                : 0.0;
@@ -630,104 +690,67 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (icol[0]) {
             const double Tv = s_TN[ikk[0]];
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk[0]], (uint32_t)F_INVALID);
-            B = bin_B(ebuf(1), 0, ikk[0], irb[0], Tv);
+            B = bin_B(ebuf_n, 0, ikk[0], irb[0], Tv);
             const double mu = s_mu[ikk[0]];
             if (mu > 0.0) Fb = mu * a.F_star[irb[0]];
         }
         blockB(0)[tid] = B;
         blockF(0)[tid] = Fb;
     }
-    level_items(0, N, n0);
+    level_items(0);
+    __syncthreads();
+    if (NCH > 1) level_items(1);
+    layer_items(0, w_c, g_c);
+    if (NCH > 2) edges(ebuf(2), tslot(2), cn(2));
+    beam_partials(0);
+    store_dt(2, dt_p);   // (after this thread's Y(0) read of its chunk 0 dtau)
+    store_T(3, T_p);
+    w_c = w_n;
+    g_c = g_n;
     __syncthreads();
 
     ElimState st = elim_top(ftoa);
-    int c = 0;
-    for (int s = N; s > 0; ++c) {
-        const int n = min(PC, s);                     // this chunk
-        const int sA = s - n, nA = min(PC, sA);       // the next chunk
-        const int sB = sA - nA, nB = min(PC, sB);     // the one after
-        const double *in = inbuf(c);
-        const R *cB = blockB(c);
-        const double *cF = blockF(c);
-        // beam sums of the chunk's levels: rows 1..n, and row 0 (level N) in chunk 0
-        const int r0 = c == 0 ? 0 : 1, nr = n + 1 - r0;
-        const int Pb = colsum_P(nr);
-
-        // P1: layer items of this chunk and the partial beam sums of its levels;
-        // the next chunk's inputs and the level temperatures of the chunk after
-        // are loaded first and stored to LDS at the end of the phase
-        Prefetch pf;
-        load_chunk(sA, nA, pf);
-        const double tB = load_T(sB, nB);
-        colsum_partials(cF + (size_t)r0 * T, T, nr, Pb);
-        if (c == 0 && nA > 0) edges(ebuf(1), tslot(1), nA);   // level N is done with buffer 1
-        if (iq[0] < n) {
-            const int q = iq[0], l = il[0], kk = ikk[0];
-            uint32_t f = 0u;
-            Layer<R> Ly{};
-            if (icol[0]) {
-                const double mu = s_mu[kk];
-                const bool day = mu > 0.0;
-                const double inv_mu = s_mu[K + kk];
-                Ly = layer_item<MIXED, R>(in[(0 * PC + q) * T + l], in[(1 * PC + q) * T + l],
-                                          in[(2 * PC + q) * T + l], day, mu, inv_mu,
-                                          cF[q * T + l], cF[(q + 1) * T + l],
-                                          cB[(q + 1) * T + l], cB[q * T + l], a.o, inv_eps2, f);
-            }
-            R *rp = s_rec + (size_t)q * 6 * T + l;
-            rp[0] = Ly.t;
-            rp[T] = Ly.r;
-            rp[2 * T] = Ly.omr;
-            rp[3 * T] = Ly.A;
-            rp[4 * T] = Ly.Sup;
-            rp[5 * T] = Ly.Sdn;
-            s_rfl[q * T + l] = f;
-        }
-        if (nA > 0) {
-            double *ni = s_in0 + (size_t)((c + 1) & 1) * 3 * PC * T;
-            if (iq[0] < nA) {
-                ni[(0 * PC + iq[0]) * T + il[0]] = pf.dt[0];
-                ni[(1 * PC + iq[0]) * T + il[0]] = pf.w[0];
-                ni[(2 * PC + iq[0]) * T + il[0]] = pf.g[0];
-            }
-        }
-        if (nB > 0 && tq[0] < nB) tslot(c + 2)[tid] = tB;
-        __syncthreads();
-
-        // P2: elimination through this chunk (sweep threads), its beam sums, the
-        // carry of its last level to the top of the next block, the next chunk's
-        // level items and the edge integrals of the chunk after
+    for (int m = 0; m < NCH; ++m) {
+        const int s = ctop(m), n = cn(m);
+        // loads for later phases: w0, g0 of Y(m+2), dtau of V(m+3), T of E(m+4)
+        load_wg(m + 2, w_n, g_n);
+        dt_p = load_dt(m + 3);
+        T_p = load_T(m + 4);
+        // Z(m)
         if (active) {
+            const R *rb0 = rbuf(m);
+            const uint32_t *fb0 = fbuf(m);
+            const size_t ps = (size_t)PC * T;
             for (int q = 0; q < n; ++q) {
-                const R *rp = s_rec + (size_t)q * 6 * T + tid;
-                fl |= s_rfl[q * T + tid];
-                const BackRec rec = elim_step(st, double(rp[0]), double(rp[T]), double(rp[2 * T]),
-                                              double(rp[3 * T]), double(rp[4 * T]),
-                                              double(rp[5 * T]));
+                const R *rp = rb0 + (size_t)q * T + tid;
+                fl |= fb0[q * T + tid];
+                const BackRec rec = elim_step(st, double(rp[0]), double(rp[ps]), double(rp[2 * ps]),
+                                              double(rp[3 * ps]), double(rp[4 * ps]),
+                                              double(rp[5 * ps]));
                 double2 *sp = reinterpret_cast<double2 *>(a.scratch) + ((long long)(s - 1 - q) * L + gl) * 2;
                 sp[0] = make_double2(rec.G, rec.H);
                 sp[1] = make_double2(rec.c, rec.d);
             }
         }
-        for (int t = rot; t < nr * K; t += W) {
-            const int q = t / K, kk = t - q * K;
-            if (c0 + kk < C) *out_at(a.F_beam, a.F_beam_c, s - r0 - q, c0 + kk) = colsum_total(q, kk, Pb);
+        beam_totals(m);
+        if (m + 1 < NCH) {
+            beam_partials(m + 1);
+            layer_items(m + 1, w_c, g_c);
         }
-        if (tid < T) {   // level s-n becomes the next chunk's top
-            blockB(c + 1)[tid] = cB[(size_t)n * T + tid];
-            blockF(c + 1)[tid] = cF[(size_t)n * T + tid];
-        }
-        if (nA > 0) level_items(c + 1, sA, nA);
-        if (nB > 0) edges(ebuf(c + 2), tslot(c + 2), nB);
-        s = sA;
+        if (m + 2 < NCH) level_items(m + 2);
+        if (m + 3 < NCH) edges(ebuf(m + 3), tslot(m + 3), cn(m + 3));
+        store_dt(m + 3, dt_p);   // (after this thread's Y(m+1) read of its dtau)
+        store_T(m + 4, T_p);
+        w_c = w_n;
+        g_c = g_n;
         __syncthreads();
     }
 
-    // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0 (level 0 is the top row
-    // of the block after the last chunk)
+    // BOA condition: F_up_0 - F_dn_0 = F_BOA + F_beam_0 (level 0: the last row
+    // of the last chunk's block)
     double Fu = 0.0, Fd = 0.0;
     if (active) {
-        elim_boa(st, Fboa, blockF(c)[tid], Fu, Fd);
+        elim_boa(st, Fboa, blockF(NCH - 1)[(size_t)cn(NCH - 1) * T + tid], Fu, Fd);
         if (fl) atomicOr(&s_flag[kl], fl);
     }
     __syncthreads();   // the bin-sum buffers alias the forward buffers
@@ -809,7 +832,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         };
         // rows 0..nch-1 hold F_up, rows CH..CH+nch-1 F_dn: both as one block of
         // 2 CH rows (the unused rows of a short pass are summed and ignored)
-        colsum_partials(s_red, T, 2 * CH, P);
+        colsum_partials(s_part, s_red, T, 2 * CH, P);
         // TOA spectrum per bin: the weighted sum over the bin's Gaussian points
         if (NG > 1 && a.F_up_toa_bin && i0 + nch == N + 1) {
             for (int task = tid; task < K * NBR; task += W) {
@@ -828,7 +851,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         for (int task = tid; task < K * nch; task += W) {
             const int ii = task / K, kk = task - ii * K;
             if (c0 + kk >= C) continue;
-            level_out(ii, kk, colsum_total(ii, kk, P), colsum_total(CH + ii, kk, P),
+            level_out(ii, kk, colsum_total(s_part, ii, kk, P), colsum_total(s_part, CH + ii, kk, P),
                       task == tid ? fbp : *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk));
         }
     }
