@@ -286,20 +286,21 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 
 // ---------------------------------------------------------------------------
 // Layer kernel.  A workgroup holds K whole columns (T = K NB lanes) and walks
-// the levels from the TOA in chunks of PC.  Per chunk:
-//   (b) level items (level, lane): Planck bin radiance from the edge integrals
-//       and the direct beam from the optical depth summed down from the TOA;
-//   (c) layer items (layer, lane): coefficients and normalised sources, into
-//       LDS; the next chunk's dtau/w0/g0 are loaded meanwhile;
-//   (d) the T sweep threads run the FP64 elimination through the chunk and
-//       write the back-substitution records; the other threads compute the
-//       next chunk's Planck edge integrals and the beam bin sums.
-// Items of (b) and (c) are spread over all threads of the workgroup, so the
-// transcendental work of a chunk runs at full occupancy even when the grid
-// holds few (column, bin) lanes.  The records are 32 bytes per (layer, lane)
-// (G, H, c, d); the back-substitution reads them back in passes of 8
-// interfaces through a register ring, one pass ahead, and closes each pass
-// with its bin sums.
+// the levels from the TOA in chunks of PC.  Each chunk goes through
+//   E  Planck edge integrals of its levels (per column and bin edge),
+//   V  level items (level, lane): bin radiance from the edge integrals and the
+//      direct beam from the optical depth summed down from the TOA,
+//   Y  layer items (layer, lane): coefficients and normalised sources,
+//   Z  the FP64 elimination through its layers, one sweep thread per lane,
+//      which writes the back-substitution records,
+// in a software pipeline with one barrier per chunk: phase m runs Z of chunk
+// m, Y of m+1, V of m+2 and E of m+3, so the elimination's dependent chain
+// overlaps the other threads' transcendental work.  Items of E, V and Y are
+// spread over all threads of the workgroup, so that work runs at full
+// occupancy even when the grid holds few (column, bin) lanes.  The records
+// are 32 bytes per (layer, lane) (G, H, c, d); the back-substitution reads
+// them back in passes of CH interfaces, staged in LDS one pass ahead by all
+// threads, and closes each pass with its bin sums.
 // ---------------------------------------------------------------------------
 // Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
 // three wavefronts per SIMD can hold; the FP32 items fit four.
@@ -412,9 +413,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         tq[k] = e / K;
         tkk[k] = e - tq[k] * K;
     }
-    // Item offset of this thread within a round of W items: the sweep threads
-    // (tid < T) take the last T offsets, so in phase (d), where they are busy
-    // with the elimination, a partial round leaves them out.
+    // Item offset of this thread within a round of W items (edge integrals,
+    // beam totals): the sweep threads (tid < T) take the last T offsets, so a
+    // partial round leaves them, busy with the elimination, out.
     const int rot = (tid + W - T) % W;
     // this thread's edge items (offsets rot + k W of a chunk's edges; a chunk has
     // at most 2 IT W of them: K (NBR + 1) <= 2 T per level)
