@@ -302,6 +302,39 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 // them back in passes of CH interfaces, staged in LDS one pass ahead by all
 // threads, and closes each pass with its bin sums.
 // ---------------------------------------------------------------------------
+// Sum of v over aligned groups of `width` lanes (a power of two <= 64), all
+// by DPP moves, every lane of the wavefront taking part, in a fixed order.
+// Within a 16-lane row the lanes 1, 2, 4, 8 apart are paired (quad permutes
+// and the row mirrors, which pair the same sets), so every lane of a group of
+// up to 16 holds its sum; a 32-lane group adds row 0's sum into row 1 (lanes
+// 16..31 hold it), a 64-lane group then row 1's into row 3 (lanes 48..63).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// the DPP move into the rows of ROWS only (0 elsewhere)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double seg_sum(double v, int width)
+{
+    if (width > 1) v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+    if (width > 2) v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+    if (width > 4) v += dpp_move<0x141>(v);       // row_half_mirror
+    if (width > 8) v += dpp_move<0x140>(v);       // row_mirror
+    if (width > 16) v += dpp_rows<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
+    if (width > 32) v += dpp_rows<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
 // three wavefronts per SIMD can hold; the FP32 items fit four.
 __host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ? 1024 : 768; }
@@ -323,7 +356,22 @@ struct LpLayout {
 __host__ __device__ inline size_t lp_align(size_t x) { return (x + 15) & ~size_t(15); }
 
 // NB: lanes per column (bins x Gaussian points), NBR: bins (Planck edges NBR+1)
-__host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, int CH, bool mixed)
+// Whether the back-substitution sums bins within wavefronts: 8..64 lanes per
+// column, padded to a power of two NBp, with K NBp <= W.
+__host__ __device__ inline int pow2_at_least(int n)
+{
+    int p = 1;
+    while (p < n) p *= 2;
+    return p;
+}
+__host__ __device__ inline bool layer_wsum(int K, int NB, int W)
+{
+    const int NBp = pow2_at_least(NB);
+    return NB >= 8 && NBp <= 64 && K * NBp <= W;
+}
+
+__host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, int CH, bool mixed,
+                                              bool wsum = false)
 {
     const size_t T = (size_t)K * NB, rs = mixed ? 4 : 8;
     LpLayout L;
@@ -349,8 +397,13 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.edge = o; o += lp_align(rs * (2 * PC + 2) * K * (NBR + 1));   // Planck edge integrals, 2 buffers + T_int, T_N rows
     L.front = o;
     size_t ob = base;
-    L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
-    L.brec = ob; ob += lp_align(16 * 2 * (size_t)CH * T); // records of CH layers
+    if (wsum) {   // records in registers: only the level-0 fluxes pass through LDS
+        L.red = ob;
+        L.brec = ob; ob += lp_align(8 * 2 * T);
+    } else {
+        L.red = ob;  ob += lp_align(8 * 2 * (size_t)CH * T);  // F_up, F_dn of CH levels
+        L.brec = ob; ob += lp_align(16 * 2 * (size_t)CH * T); // records of CH layers
+    }
     L.back = ob;
     L.total = L.front > L.back ? L.front : L.back;
     return L;
@@ -366,7 +419,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const int NG = a.NG, NBR = NB / NG;   // lanes per column = bins x Gaussian points
     const int T = K * NB;
     const int tid = threadIdx.x, W = blockDim.x;
-    const LpLayout Lo = lp_layout(K, NB, NBR, PC, CH, MIXED);
+    const bool wsum = layer_wsum(K, NB, W);
+    const LpLayout Lo = lp_layout(K, NB, NBR, PC, CH, MIXED, wsum);
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
     double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
@@ -756,6 +810,93 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     }
     __syncthreads();   // the bin-sum buffers alias the forward buffers
 
+    if (wsum) {
+        // Back-substitution on a padded layout: thread kk NBp + b takes lane
+        // (kk, b), NBp the power of two >= NB, so a column's lanes share a
+        // wavefront and the bin sums of each level are wavefront sums
+        // (seg_sum) with no barrier.  Each lane keeps the records of its next 8
+        // layers in registers (slot k: the layer below interface i0 + k),
+        // loaded 8 steps ahead of their use; the loads are unconditional (layer
+        // index clamped, a valid lane for the padding) so no slot waits for
+        // its load before it is used.  The level-0 fluxes move to the padded
+        // layout through LDS; F_net follows in the pass after.
+        const int NBp = pow2_at_least(NB);
+        const int yk = tid / NBp, yb = tid - yk * NBp, yl = yk * NB + yb;
+        const bool yslot = yk < K, yact = yslot && yb < NB && c0 + yk < C;
+        double *s_x = reinterpret_cast<double *>(lds + Lo.brec);   // [2][T]
+        if (sweep) {
+            s_x[tid] = Fu;
+            s_x[T + tid] = Fd;
+        }
+        __syncthreads();
+        Fu = yact ? s_x[yl] : 0.0;
+        Fd = yact ? s_x[T + yl] : 0.0;
+        const double wgt = yact ? s_wl[yb] : 0.0;   // bin-sum weight (0 on padding lanes)
+        // the lane of a column segment that holds its sums (seg_sum) and writes them
+        const int ol = NBp <= 16 ? 0 : (NBp == 32 ? 16 : 48);
+        const bool outc = yslot && yb == ol && c0 + yk < C;
+        // only the wavefronts that hold back-substitution lanes run the steps
+        if (wave_uniform(tid >> 6) * 64 < K * NBp) {
+            const double2 *rp = reinterpret_cast<const double2 *>(a.scratch) +
+                                ((long long)tile * T + (yact ? yl : 0)) * 2;
+            double rG[8], rH[8], rc[8], rd[8];
+            auto ld = [&](int j, int k) {
+                const double2 *q = rp + (long long)min(j, N - 1) * 2 * L;
+                const double2 x = q[0], y = q[1];
+                rG[k] = x.x;
+                rH[k] = x.y;
+                rc[k] = y.x;
+                rd[k] = y.y;
+            };
+#pragma unroll
+            for (int k = 1; k < 8; ++k) ld(k - 1, k);
+            rG[0] = rH[0] = rc[0] = rd[0] = 0.0;
+            for (int i0 = 0; i0 <= N; i0 += 8) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = i0 + k;
+                    if (i > N) break;
+                    if (yact && i > 0) back_step(rG[k], rH[k], rc[k], rd[k], Fu, Fd);
+                    ld(i + 7, k);   // the layer below interface i + 8
+                    if (yact) {
+                        const long long o = (long long)i * LB + toff + yl;
+                        if (a.F_up_bin) a.F_up_bin[o] = Fu;
+                        if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
+                        if (i == N && a.F_up_toa_bin) {
+                            if (NG == 1) a.F_up_toa_bin[toff + yl] = Fu;
+                            else s_part[yl] = Fu;   // TOA spectrum, below
+                        }
+                    }
+                    const double su = seg_sum(wgt * Fu, NBp), sd = seg_sum(wgt * Fd, NBp);
+                    if (outc) {
+                        *out_at(a.F_up, a.F_up_c, i, c0 + yk) = su;
+                        *out_at(a.F_dn, a.F_dn_c, i, c0 + yk) = sd;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // TOA spectrum per bin: the weighted sum over the bin's Gaussian points
+        if (NG > 1 && a.F_up_toa_bin) {
+            for (int task = tid; task < K * NBR; task += W) {
+                const int kk = task / NBR, rb_ = task - kk * NBR, cc = c0 + kk;
+                if (cc >= C) continue;
+                const double *ru_ = s_part + kk * NB + rb_ * NG;
+                double sum = 0.0;
+                for (int g = 0; g < NG; ++g) sum += a.wg[g] * ru_[g];
+                a.F_up_toa_bin[(long long)cc * NBR + rb_] = sum;
+            }
+        }
+        // net flux of every level (F_up, F_dn and F_beam written above)
+        for (int task = tid; task < (N + 1) * K; task += W) {
+            const int lev = task / K, kk = task - lev * K, cc = c0 + kk;
+            if (cc >= C) continue;
+            const double fn = *out_at(a.F_up, a.F_up_c, lev, cc) - *out_at(a.F_dn, a.F_dn_c, lev, cc) -
+                              *out_at(a.F_beam, a.F_beam_c, lev, cc);
+            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
+            if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
+        }
+    } else {
     // back-substitution upward in passes of CH interfaces, each closed by its
     // bin sums.  A pass's records are staged in LDS (s_brec[ii][lane] = (G, H),
     // (c, d) of the layer below interface i0 + ii): every thread loads its
@@ -785,13 +926,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             ry[k] = v.y;
         }
     };
-    auto rec_store = [&]() {
+    auto rec_store = [&](double2 *dst) {
 #pragma unroll
         for (int k = 0; k < MU; ++k)
-            if (tid + k * W < units) s_brec[tid + k * W] = make_double2(rx[k], ry[k]);
+            if (tid + k * W < units) dst[tid + k * W] = make_double2(rx[k], ry[k]);
     };
     rec_fetch(0);
-    rec_store();
+    rec_store(s_brec);
     __syncthreads();
     const int P = colsum_P(2 * CH);
     for (int i0 = 0; i0 <= N; i0 += CH) {
@@ -845,7 +986,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 a.F_up_toa_bin[(long long)cc * NBR + rb] = sum;
             }
         }
-        if (i0 + CH <= N) rec_store();   // this pass's records are used
+        if (i0 + CH <= N) rec_store(s_brec);   // this pass's records are used
         __syncthreads();
         // (the next pass writes s_red, read above, and s_part only after its
         // first barrier, so no barrier closes the pass)
@@ -855,6 +996,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             level_out(ii, kk, colsum_total(s_part, ii, kk, P), colsum_total(s_part, CH + ii, kk, P),
                       task == tid ? fbp : *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk));
         }
+    }
     }
     __syncthreads();   // every level's F_net is written before the heating reads it
 
@@ -979,16 +1121,18 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     if (best < 0.0) return Geometry{};
     // interfaces per back-substitution pass: as many as fit in the forward
     // sweep's bytes and in the threads' staging registers
+    // (none with wavefront bin sums, which stage no records in LDS)
     const size_t front = lp_layout(K, NB, NB, g.PC, 1, mixed).total;
+    const bool ws = layer_wsum(K, NB, g.threads);
     int ch = 1;
-    while (ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= front &&
+    while (!ws && ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= front &&
            2 * (ch + 1) * T <= kBackUnits * g.threads)
         ++ch;
     g.CH = ch;
     g.K = K;
     g.blocks = (C + K - 1) / K;
     g.lanes = (long long)g.blocks * T;
-    g.lds = lp_layout(K, NB, NB, g.PC, g.CH, mixed).total;
+    g.lds = lp_layout(K, NB, NB, g.PC, g.CH, mixed, ws).total;
     return g;
 }
 

@@ -115,4 +115,15 @@ __host__ __device__ __forceinline__ float sqrt_nn(float x)
 
 __host__ __device__ __forceinline__ double sqrt_nn(double x) { return sqrt(x); }
 
+// A value that is the same in every lane of the wavefront, moved to a scalar
+// register so that branches on it are uniform.
+__host__ __device__ __forceinline__ int wave_uniform(int x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(x);
+#else
+    return x;
+#endif
+}
+
 }  // namespace rtk
