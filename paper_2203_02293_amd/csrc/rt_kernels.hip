@@ -377,13 +377,13 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     LpLayout L;
     size_t o = 0;
     L.flag = o; o += lp_align(4 * (size_t)K);
-    L.mu = o;   o += lp_align(8 * 2 * (size_t)K);              // mu, 1/mu per column
+    L.mu = o;   o += lp_align(8 * 3 * (size_t)K);              // mu, 1/mu, T_int per column
     L.wl = o;   o += lp_align(8 * (size_t)NB);                 // weight of each lane of a column
     // partial sums of the column sums, 2 buffers: a chunk's beam partials
     // (at most W of them) are written while the previous chunk's are summed
     size_t np = 1024;
     if ((size_t)2 * CH * K > np) np = (size_t)2 * CH * K;
-    if ((size_t)2 * K > np) np = (size_t)2 * K;                // (prologue: T_N, T_int per column)
+    if ((size_t)K > np) np = (size_t)K;                        // (prologue: T at level N per column)
     L.np = np;
     L.part = o; o += lp_align(8 * 2 * np);
     const size_t base = o;
@@ -422,7 +422,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     const bool wsum = layer_wsum(K, NB, W);
     const LpLayout Lo = lp_layout(K, NB, NBR, PC, CH, MIXED, wsum);
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
-    double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [2][K]: mu, 1/mu
+    double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [3][K]: mu, 1/mu, T_int
     double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
     double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // [2][np] partial column sums
     double *s_F0 = reinterpret_cast<double *>(lds + Lo.F);            // [2][PC+1][T]
@@ -689,8 +689,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // 0..2, w0 and g0 of chunks 0 and 1, and the TOA downward flux of the
     // sweep lanes.  Then E(0), E(1); V(0); V(1), Y(0), E(2) and chunk 0's beam
     // partials, each step behind a barrier.
-    double *s_TN = s_part;       // [K] T at level N, [K] T_int (the partial sums
-    double *s_Ti = s_part + K;   // are not in use before the last prologue step)
+    double *s_TN = s_part;       // [K] T at level N (the partial sums are not in use
+                                 // before the last prologue step)
+    double *s_Ti = s_mu + 2 * K; // [K] T_int
     R *ebuf_x = s_edge0 + (size_t)2 * PC * K * (NBR + 1);   // T_int edge row
     R *ebuf_n = ebuf_x + (size_t)K * (NBR + 1);             // level N edge row
     const double ftoa = (active && a.Ftoa) ? a.Ftoa[toff + tid] : 0.0;
@@ -729,16 +730,37 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         store_T(2, t2);
     }
     __syncthreads();
-    edges(ebuf_x, s_Ti, 1);
-    edges(ebuf_n, s_TN, 1);
-    edges(ebuf(0), tslot(0), cn(0));
-    edges(ebuf(1), tslot(1), cn(1));
+    // edge integrals of T_int, level N, and chunks 0 and 1, spread evenly over
+    // the threads: row 0 T_int, row 1 level N, then the chunks' level rows
+    {
+        const int n0 = cn(0), nrow = 2 + n0 + cn(1);
+        for (int e = rot; e < nrow * per; e += W) {
+            const int r = e / per, rem = e - r * per, ee = rem / K, kk = rem - ee * K;
+            const double *Ts;
+            R *dst;
+            if (r == 0) {
+                Ts = s_Ti;
+                dst = ebuf_x;
+            } else if (r == 1) {
+                Ts = s_TN;
+                dst = ebuf_n;
+            } else {
+                const int m = r - 2 < n0 ? 0 : 1, q = r - 2 - (m ? n0 : 0);
+                Ts = tslot(m) + q * K;
+                dst = ebuf(m) + (size_t)q * K * (NBR + 1);
+            }
+            R v = R(0);
+            if (c0 + kk < C) {
+                R x;
+                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Ts[kk]));
+                else x = a.c2_over_lam[ee] * rcp(Ts[kk]);
+                v = planck_edge<R>(x);
+            }
+            dst[kk * (NBR + 1) + ee] = v;
+        }
+    }
     __syncthreads();
-    // F_BOA = pi B_b(T_int) of the sweep lanes; level N (row 0 of block 0:
-    // item iq = 0, il = tid) and V(0)
-    const double Fboa =
-        active ? double(kPI) * double(bin_B(ebuf_x, 0, kl, NG == 1 ? bl : bl / NG, s_Ti[kl]))
-               : 0.0;
+    // level N (row 0 of block 0: item iq = 0, il = tid) and V(0)
     if (tid < T) {
         R B = R(0);
         double Fb = 0.0;
@@ -805,6 +827,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // of the last chunk's block)
     double Fu = 0.0, Fd = 0.0;
     if (active) {
+        // F_BOA = pi B_b(T_int) (the T_int edge row stays in LDS)
+        const double Fboa = double(kPI) * double(bin_B(ebuf_x, 0, kl, NG == 1 ? bl : bl / NG, s_Ti[kl]));
         elim_boa(st, Fboa, blockF(NCH - 1)[(size_t)cn(NCH - 1) * T + tid], Fu, Fd);
         if (fl) atomicOr(&s_flag[kl], fl);
     }

@@ -72,8 +72,7 @@ template <> struct PCfg<double> {
 template <> struct PCfg<float> {
     static constexpr float XS = 2.5f;
     static constexpr int NQ = 10;
-    static constexpr int NP = 8;
-    static constexpr float TAIL = 1e-8f;
+    static constexpr int NP = 8;        // exponential terms: e^-20 < 2e-9
     static constexpr float XCUT = 104.0f;
 };
 
@@ -148,18 +147,35 @@ __host__ __device__ __forceinline__ R planck_edge(R x)
         return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + poly * x2);
     }
     if (!(x < Cfg::XCUT)) return R(-0.0);   // e^{-x} underflows (includes T = 0)
-    // term n+1 over term 1 is about e^{-nx}: stop once that is below the last bit
+    // sum_{n>=1} y^n q_n, y = e^{-x}, q_n = x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4
     const R y = exp_em1(-x).e;
-    R yn = y, sum = R(0);
-    for (int n = 0; n < Cfg::NP; ++n) {
-        const R t = R(tb.inv_n[n]);
-        // (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4) = t (x^3 + t (3x^2 + t (6x + 6t)))
-        const R poly = t * fma(t, fma(t, R(6) * (x + t), R(3) * x * x), x * x * x);
-        sum = fma(yn, poly, sum);
-        yn *= y;
-        if (yn < Cfg::TAIL * y) break;   // next term relative to the first
+    if constexpr (sizeof(R) == 4) {
+        // FP32: Horner in y from the smallest term over a fixed number of terms
+        // (term NP+1 over term 1 is below e^{-NP XS}, under the last bit); no
+        // data-dependent exit, so the lanes of a wavefront stay together
+        const R x2 = x * x, x3 = x2 * x;
+        R acc = R(0);
+#pragma unroll
+        for (int n = Cfg::NP; n >= 1; --n) {
+            const double in = 1.0 / n;
+            const R q = fma(x3, R(in), fma(x2, R(3 * in * in), fma(x, R(6 * in * in * in), R(6 * in * in * in * in))));
+            acc = fma(acc, y, q);
+        }
+        return -(y * acc);
+    } else {
+        // FP64: forward, stopping once term n+1 over term 1 (about e^{-nx}) is
+        // below the last bit: few terms at the large x that most edges have
+        R yn = y, sum = R(0);
+        for (int n = 0; n < Cfg::NP; ++n) {
+            const R t = R(tb.inv_n[n]);
+            // (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4) = t (x^3 + t (3x^2 + t (6x + 6t)))
+            const R poly = t * fma(t, fma(t, R(6) * (x + t), R(3) * x * x), x * x * x);
+            sum = fma(yn, poly, sum);
+            yn *= y;
+            if (yn < R(Cfg::TAIL) * y) break;   // next term relative to the first
+        }
+        return -sum;
     }
-    return -sum;
 }
 
 // int_{x_a}^{x_b} t^3/(e^t-1) dt from the two edge values (x_b > x_a):
