@@ -76,15 +76,14 @@ __host__ __device__ __forceinline__ ExpEm1<R> exp_em1(R x)
     return out;
 }
 
-// 1/x to about one ulp: hardware reciprocal refined by Newton steps.
+// 1/x: the hardware reciprocal (relative error below 5e-8 on gfx950) refined
+// by one Newton step, which squares the error: within about 2e-15 (measured
+// 2.1e-15 over 2^20 arguments spanning e^-12..e^12), ten ulp at most.
 __host__ __device__ __forceinline__ double rcp(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
 #else
     return 1.0 / x;
 #endif
@@ -101,19 +100,29 @@ __host__ __device__ __forceinline__ float rcp(float x)
 #endif
 }
 
-// Square root of a non-negative finite argument: the hardware instruction in
-// FP32 (within one ulp; the library sqrtf adds a correction to round it
-// correctly), the correctly rounded one in FP64.
-__host__ __device__ __forceinline__ float sqrt_nn(float x)
+// 1/sqrt(x) of a positive finite argument: in FP32 the hardware instruction
+// (within one ulp); in FP64 the hardware estimate refined by two Newton steps
+// y (3 - x y^2) / 2, each squaring the relative error.
+__host__ __device__ __forceinline__ float rsqrt_pos(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_sqrtf(x);
+    return __builtin_amdgcn_rsqf(x);
 #else
-    return sqrtf(x);
+    return 1.0f / sqrtf(x);
 #endif
 }
 
-__host__ __device__ __forceinline__ double sqrt_nn(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ double rsqrt_pos(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    return y * fma(-hx * y, y, 1.5);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
 
 // A value that is the same in every lane of the wavefront, moved to a scalar
 // register so that branches on it are uniform.

@@ -14,6 +14,8 @@
 #include "rt_internal.hpp"
 #include "rt_math.hpp"
 
+#include <limits>
+
 namespace rtk {
 
 constexpr double kPI = 3.141592653589793238462643383279502884;
@@ -294,13 +296,18 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
     R kap = R(2) * Eom;
     const R iEom = rcp(Eom);
     R ik = R(0.5) * iEom;   // 1/kappa
-    R s = sqrt_nn(Ew * iEom);
+    // s = sqrt(Ew/Eom) and 1/s from one reciprocal square root (Ew = 0: s = 0;
+    // Ew < 0, E below w0 in the unclamped fit: NaN, as sqrt gives)
+    const R s2 = Ew * iEom;
+    const bool spos = s2 > R(0);
+    const R is = spos ? rsqrt_pos(s2) : (s2 == R(0) ? R(0) : std::numeric_limits<R>::quiet_NaN());
+    R s = s2 * is;
     R lam = kap * s;
     R u = lam * dtau;
     ExpEm1<R> ex = exp_em1(-u);
     R Tr = ex.e, omT = -ex.em1;
     R zp = half * (one + s), zm = half * (one - s);
-    R p = (s > R(0)) ? omT * rcp(s) : kap * dtau;
+    R p = spos ? omT * is : kap * dtau;
     R q = p * (one + Tr);
     R den = fma(zm * zm, q, one);
     R id = rcp(den);
