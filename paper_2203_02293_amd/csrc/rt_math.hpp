@@ -36,17 +36,58 @@ constexpr double inv_fact(int n)
     return 1.0 / f;
 }
 
-template <class R, int K, int DEG>
-__host__ __device__ __forceinline__ R taylor_em1_tail(R r)
+
+// sum_{j=0}^{N-1} C::coef(j) y^j as two interleaved Horner chains in y^2
+// (even and odd powers), halving the dependent chain; coefficients folded at
+// compile time.
+template <class R, class C, int J, int N>
+__host__ __device__ __forceinline__ R horner_y2(R y2)
 {
-    // 1/K! + r/(K+1)! + ... + r^(DEG-K)/DEG!, coefficients folded at compile time
-    constexpr double ck = inv_fact(K);
-    if constexpr (K == DEG) {
-        return R(ck);
+    constexpr double cj = C::coef(J);
+    if constexpr (J + 2 >= N) {
+        return R(cj);
     } else {
-        return fma(taylor_em1_tail<R, K + 1, DEG>(r), r, R(ck));
+        return fma(horner_y2<R, C, J + 2, N>(y2), y2, R(cj));
     }
 }
+
+template <class R, class C, int N>
+__host__ __device__ __forceinline__ R poly_eo(R y)
+{
+    if constexpr (N == 1) {
+        return R(C::coef(0));
+    } else {
+        const R y2 = y * y;
+        return fma(horner_y2<R, C, 1, N>(y2), y, horner_y2<R, C, 0, N>(y2));
+    }
+}
+
+// sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain
+template <class R, class C, int J, int N>
+__host__ __device__ __forceinline__ R horner_y(R y)
+{
+    constexpr double cj = C::coef(J);
+    if constexpr (J + 1 >= N) {
+        return R(cj);
+    } else {
+        return fma(horner_y<R, C, J + 1, N>(y), y, R(cj));
+    }
+}
+
+// The polynomial by two chains in FP32 (shorter dependent chains); in FP64
+// by one (each extra FP64 constant and partial sum takes two registers, which
+// the FP64 kernel does not have to spare).
+template <class R, class C, int N>
+__host__ __device__ __forceinline__ R poly(R y)
+{
+    if constexpr (sizeof(R) == 4) return poly_eo<R, C, N>(y);
+    else return horner_y<R, C, 0, N>(y);
+}
+
+// coefficients 1/(j+1)! of (e^r - 1)/r
+struct ExpTailCoef {
+    static constexpr double coef(int j) { return inv_fact(j + 1); }
+};
 
 template <class R>
 struct ExpEm1 {
@@ -69,7 +110,7 @@ __host__ __device__ __forceinline__ ExpEm1<R> exp_em1(R x)
     R r = fma(-k, R(Cfg::LN2_HI), x);
     r = fma(-k, R(Cfg::LN2_LO), r);
     // q = e^r - 1 = r (1 + r/2 + r^2/6 + ...)
-    R q = r * taylor_em1_tail<R, 1, Cfg::DEG>(r);
+    R q = r * poly<R, ExpTailCoef, Cfg::DEG>(r);
     int ki = int(k);
     out.e = ldexp(R(1) + q, ki);
     out.em1 = ldexp(q, ki) + (ldexp(R(1), ki) - R(1));

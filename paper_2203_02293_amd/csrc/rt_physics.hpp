@@ -78,16 +78,6 @@ template <> struct PCfg<float> {
     static constexpr float XCUT = 104.0f;
 };
 
-template <class R, int K, int NQ>
-__host__ __device__ __forceinline__ R bern_horner(R x2)
-{
-    constexpr double cK = bern_coef(K);   // forced compile-time evaluation
-    if constexpr (K == NQ) {
-        return R(cK);
-    } else {
-        return fma(bern_horner<R, K + 1, NQ>(x2), x2, R(cK));
-    }
-}
 
 constexpr double inv_factorial(int n)
 {
@@ -96,20 +86,17 @@ constexpr double inv_factorial(int n)
     return 1.0 / f;
 }
 
-template <class R, int K, int N>
-__host__ __device__ __forceinline__ R sinhc_horner(R u2)
-{
-    // sum_{k=K..N} u^{2(k-K)} / (2k+1)!, Horner in u^2, coefficients folded
-    constexpr double ck = inv_factorial(2 * K + 1);
-    if constexpr (K == N) {
-        return R(ck);
-    } else {
-        return fma(sinhc_horner<R, K + 1, N>(u2), u2, R(ck));
-    }
-}
+// coefficients 1/(2j+3)! of (sinh u - u)/u^3 as a series in u^2
+struct SinhcCoef {
+    static constexpr double coef(int j) { return inv_factorial(2 * j + 3); }
+};
+// coefficients c_k = B_2k/((2k+3)(2k)!) of the small-x Planck series, k >= 1
+struct BernCoef {
+    static constexpr double coef(int j) { return bern_coef(j + 1); }
+};
 
-// Series coefficient tables (compile-time values, read with uniform loads):
-// c_k = B_2k/((2k+3)(2k)!) for the small-x series, 1/n for the large-x series.
+// Series coefficient tables for FP64 (compile-time values, read with uniform
+// loads): c_k for the small-x series, 1/n for the large-x series.
 struct SeriesTables {
     double bern[28];
     double inv_n[14];
@@ -143,10 +130,15 @@ __host__ __device__ __forceinline__ R planck_edge(R x)
     const SeriesTables &tb = series_tables();
     if (x <= Cfg::XS) {
         const R x2 = x * x;
-        R poly = R(tb.bern[Cfg::NQ - 1]);
+        R pb;
+        if constexpr (sizeof(R) == 4) {
+            pb = poly_eo<R, BernCoef, Cfg::NQ>(x2);
+        } else {   // FP64: coefficients by uniform loads from the table
+            pb = R(tb.bern[Cfg::NQ - 1]);
 #pragma unroll 4
-        for (int k = Cfg::NQ - 2; k >= 0; --k) poly = fma(poly, x2, R(tb.bern[k]));
-        return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + poly * x2);
+            for (int k = Cfg::NQ - 2; k >= 0; --k) pb = fma(pb, x2, R(tb.bern[k]));
+        }
+        return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + pb * x2);
     }
     if (!(x < Cfg::XCUT)) return R(-0.0);   // e^{-x} underflows (includes T = 0)
     // sum_{n>=1} y^n q_n, y = e^{-x}, q_n = x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4
@@ -271,7 +263,7 @@ __host__ __device__ __forceinline__ R hfun(R u, R T)
 {
     if (u < R(2)) {
         // (sinh u - u)/u^2 = u sum_{k>=1} u^{2(k-1)} / (2k+1)!
-        return T * u * sinhc_horner<R, 1, ShCfg<R>::N>(u * u);
+        return T * u * poly<R, SinhcCoef, ShCfg<R>::N>(u * u);
     }
     return (R(0.5) * (R(1) - T * T) - u * T) * rcp(u * u);
 }
