@@ -47,10 +47,17 @@ typedef int32_t rt_status;
  * shapes).  LANE: one thread per (column, bin) runs the whole sweep of its
  * lane.  LAYER: the Planck, beam and coefficient work of a tile is spread over
  * (layer, column, bin) items shared by the workgroup; only the FP64
- * elimination runs per lane.  AUTO picks LAYER. */
+ * elimination runs per lane.  DEEP: each column's layers are split into
+ * segments on separate workgroups and the Thomas recurrence (Section 2.2.2)
+ * is composed per segment and joined by scans over segments: for few, deep
+ * columns; several launches on the stream, rt_solve_fluxes only (rt_submit:
+ * RT_EINVAL), cols_per_block must be 0.  AUTO picks DEEP for a stream-ordered
+ * solve of at least 128 slabs with at most one column per 4 compute units,
+ * else LAYER (serving: LAYER). */
 #define RT_KERNEL_AUTO  0
 #define RT_KERNEL_LANE  1
 #define RT_KERNEL_LAYER 2
+#define RT_KERNEL_DEEP  3
 
 /* per-column condition bits written to rt_request.flags */
 #define RT_FLAG_GUARD    1u  /* G+- resonance guard (Section 2.2.1) replaced D by 2 mu_star */
@@ -154,7 +161,7 @@ typedef struct {
                                      must fit the kernel: K*NB <= 512 (lane
                                      kernel), K*NB <= 1024 and its LDS within the
                                      device's (layer kernel), else RT_EINVAL      */
-    int32_t kernel;               /* RT_KERNEL_AUTO, RT_KERNEL_LANE or RT_KERNEL_LAYER */
+    int32_t kernel;               /* RT_KERNEL_AUTO, _LANE, _LAYER or _DEEP */
     int32_t reserved;             /* must be 0 */
     const double *p_iface, *T_iface;
     const double *dtau, *w0, *g0;
@@ -250,9 +257,9 @@ typedef struct {
 rt_status rt_optical_properties(rt_handle *h, const rt_optics_request *req, void *hip_stream);
 
 /*
- * Device bytes of library-owned work buffer one solve of this shape needs
- * (what the serving path reserves from its budget per admitted request);
- * -1 on bad arguments.
+ * Device bytes of work buffer the serving path reserves from its budget for
+ * one request of this shape (default tile of the layer kernel); -1 on bad
+ * arguments.  Stream-ordered solves grow the handle's own buffer as needed.
  */
 int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers);
 

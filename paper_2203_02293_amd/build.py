@@ -9,7 +9,7 @@ PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "librt_mi355x.so"
-SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_optics.hip", CSRC / "rt_api.hip"]
+SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_deep.hip", CSRC / "rt_optics.hip", CSRC / "rt_api.hip"]
 HEADERS = [CSRC / "rt_internal.hpp", CSRC / "rt_math.hpp", CSRC / "rt_physics.hpp",
            ROOT / "include" / "rt.h"]
 

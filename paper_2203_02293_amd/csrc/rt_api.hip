@@ -25,6 +25,10 @@ constexpr double kH = 6.62607015e-34, kC = 299792458.0, kKB = 1.380649e-23;
 constexpr int kMaxBins = 512;
 constexpr int kMaxBinPoints = 768;   // bins x Gaussian points: lanes of one column
 constexpr int kMaxLayers = 4096;
+// AUTO takes the deep kernel from this many slabs, for at most one column per
+// this many compute units
+constexpr int kDeepMinSlabs = 128;
+constexpr int kDeepColsPerCu = 4;
 constexpr int kStreams = 4;
 constexpr size_t kAlign = 256;
 
@@ -179,6 +183,14 @@ extern "C" const char *rt_status_string(rt_status s)
     }
 }
 
+// AUTO on a stream-ordered solve: the deep kernel where the layer kernel's
+// workgroups (about one per column up to one per compute unit) would leave
+// most of the chip idle for a long sweep.
+static bool prefer_deep(const rt_handle *h, int C, int N)
+{
+    return N >= kDeepMinSlabs && (long long)C * kDeepColsPerCu <= h->dev.n_cu;
+}
+
 extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers)
 {
     if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
@@ -244,7 +256,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
         }
         h->dev.n_cu = n_cu;
         h->dev.lds = (size_t)lds;
-        if (rtk::prepare_kernels(h->dev) != hipSuccess) {
+        if (rtk::prepare_kernels(h->dev) != hipSuccess ||
+            rtk::prepare_deep_kernels(h->dev) != hipSuccess) {
             delete h;
             return RT_EDEVICE;
         }
@@ -308,11 +321,17 @@ extern "C" rt_status rt_destroy(rt_handle *h)
 // Slabs of a request: one per layer, two on the sub-layer grid.
 static int request_slabs(const rt_request *r) { return r->T_center ? 2 * r->n_layers : r->n_layers; }
 
-static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
+// serving: batched launches run the lane or layer kernel only
+static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r, bool serving = false)
 {
+    const int N = request_slabs(r);
+    if (r->kernel == RT_KERNEL_DEEP ||
+        (r->kernel == RT_KERNEL_AUTO && !serving && r->cols_per_block == 0 &&
+         prefer_deep(h, r->n_cols, N)))
+        return rtk::deep_geometry(r->n_cols, N, h->NBG, h->dev);
     const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
-    return rtk::solve_geometry(r->n_cols, request_slabs(r), h->NBG, r->cols_per_block, kernel,
-                               r->precision, h->dev);
+    return rtk::solve_geometry(r->n_cols, N, h->NBG, r->cols_per_block, kernel, r->precision,
+                               h->dev);
 }
 
 static rt_status validate(rt_handle *h, const rt_request *r)
@@ -323,8 +342,10 @@ static rt_status validate(rt_handle *h, const rt_request *r)
         return fail(h, RT_EINVAL, "n_layers must be in [1, %d] (got %d)", kMaxLayers, r->n_layers);
     if (r->precision != RT_FP64 && r->precision != RT_MIXED)
         return fail(h, RT_EINVAL, "precision must be RT_FP64 or RT_MIXED");
-    if (r->kernel < RT_KERNEL_AUTO || r->kernel > RT_KERNEL_LAYER)
-        return fail(h, RT_EINVAL, "kernel must be RT_KERNEL_AUTO, _LANE or _LAYER");
+    if (r->kernel < RT_KERNEL_AUTO || r->kernel > RT_KERNEL_DEEP)
+        return fail(h, RT_EINVAL, "kernel must be RT_KERNEL_AUTO, _LANE, _LAYER or _DEEP");
+    if (r->kernel == RT_KERNEL_DEEP && r->cols_per_block != 0)
+        return fail(h, RT_EINVAL, "the deep kernel takes no tile (cols_per_block must be 0)");
     if (r->reserved != 0) return fail(h, RT_EINVAL, "reserved must be 0");
     if (h->NG > 1 && r->kernel == RT_KERNEL_LANE)
         return fail(h, RT_EINVAL, "Gaussian points per bin need the layer kernel");
@@ -537,7 +558,9 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
         h->scratch_bytes = need;
     }
     rtk::SolveArgs a = make_args(h, r, h->d_scratch);
-    hipError_t e = rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);
+    hipError_t e = g.kernel == rtk::KERNEL_DEEP
+                       ? rtk::launch_deep(a, g, r->precision, (hipStream_t)stream)
+                       : rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(h, e, "solve launch");
     return RT_OK;
 }
@@ -647,6 +670,8 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     if (!h || !ticket) return RT_EINVAL;
     rt_status st = validate(h, r);
     if (st != RT_OK) return st;
+    if (r->kernel == RT_KERNEL_DEEP)
+        return fail(h, RT_EINVAL, "the deep kernel runs through rt_solve_fluxes only");
     (void)hipSetDevice(h->cfg.device);
     if ((st = ensure_serving(h)) != RT_OK) return st;
     if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight) {
@@ -657,7 +682,7 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
-    j.g = request_geometry(h, r);
+    j.g = request_geometry(h, r, true);
     j.bytes = j.g.scratch;
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);

@@ -19,6 +19,8 @@ enum Kernel : int {
     KERNEL_LANE = 1,    // one thread per (column, bin) does everything for its lane
     KERNEL_LAYER = 2,   // Planck, beam and coefficients as (layer, column, bin) items
                         // shared by the workgroup; only the elimination is per lane
+    KERNEL_DEEP = 3,    // a column's layers split into segments on separate
+                        // workgroups, the recurrences composed per segment
 };
 
 // Everything one solve kernel needs (passed by value).
@@ -56,7 +58,7 @@ struct DeviceLimits {
 
 // Launch geometry of a solve for a problem shape.
 struct Geometry {
-    int kernel;     // KERNEL_LANE or KERNEL_LAYER
+    int kernel;     // KERNEL_LANE, KERNEL_LAYER or KERNEL_DEEP
     int K;          // columns per workgroup
     int PC, CH;     // layer kernel: levels per chunk, interfaces per bin-sum pass
     int threads;    // workgroup size (multiple of 64)
@@ -75,6 +77,11 @@ constexpr int kMaxTileLanes = 1024;    // (column, bin) lanes of one layer-kerne
 Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
                         const DeviceLimits &dev);
 hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s);
+// Layer-parallel path for deep columns (several launches on stream s): K =
+// segments per column, PC = slabs per segment; scratch sized for it.
+Geometry deep_geometry(int C, int N, int NB, const DeviceLimits &dev);
+hipError_t launch_deep(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s);
+hipError_t prepare_deep_kernels(const DeviceLimits &dev);
 // Several requests with the same kernel, tile, bins and precision in one launch:
 // device arrays d_reqs[n] (K, PC, CH, L filled in) and d_first[n] (first
 // workgroup of each).

@@ -268,16 +268,24 @@ __host__ __device__ __forceinline__ R hfun(R u, R T)
     return (R(0.5) * (R(1) - T * T) - u * T) * rcp(u * u);
 }
 
+// omt = 1 - t, formed without subtraction: with omr, the complements of t
+// and r keep their relative precision where t or r is close to 1.
 template <class R>
 struct Layer {
-    R t, r, omr, A, Sup, Sdn;
+    R t, r, omr, A, Sup, Sdn, omt;
 };
 
 // Coefficients and normalised sources of one layer (see the file header).
 // Differences near 1 (1 - w0, E - w0, 1 - w0 g0) arrive already formed in
 // FP64 by the caller: in FP32 they would lose up to ~2 digits for cloud layers.
 // Fup and Flo are the direct beam at the layer's top and bottom interfaces.
-template <class R>
+// THIN: the beam-source differences f (1 - t beta) and f (beta - t) formed
+// from exponentials of exponent sums and differences (three more exponentials
+// per day layer) instead of from f, t and f beta, where, for a layer thin to
+// the beam and to the diffuse flux, they are O(dtau) differences of O(1)
+// values: in FP32 their rounding, accumulated over thousands of thin layers,
+// reaches ~1e-5 of the fluxes.
+template <class R, bool THIN = false>
 __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R omw, R Ew, R om,
                                                      bool day, R mu, R inv_mu, R Dres,
                                                      bool guard, R Fup, R Flo, R Blo, R Bup,
@@ -307,6 +315,7 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
     R r = zp * zm * q * id;
     R A = omT * (zp - zm * Tr) * id;
     L.t = t;
+    L.omt = (omT + zm * zm * q) * id;   // (den - T) / den
     L.r = r;
     L.A = A;
     L.omr = (zp + zm * Tr * Tr) * id;
@@ -334,8 +343,22 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
             R Gp = half * (P * (ik - mu) + Qc);
             R Gm = -half * (P * (ik + mu) + Qc);
             // f [r G- - G+ (1 - t beta)] and f [r beta G+ - G- (beta - t)], f beta = Flo
-            sb_up = r * Gm * Fup - Gp * (Fup - t * Flo);
-            sb_dn = r * Gp * Flo - Gm * (Flo - t * Fup);
+            if constexpr (THIN) {
+                // 1 - t beta = (1 - T beta + zm^2 q) / den,
+                // beta - t = (beta - T + beta zm^2 q) / den, with
+                // beta - T = beta (1 - e^-(lambda-a)dtau) or T (e^-(a-lambda)dtau - 1)
+                const R a = inv_mu, zq = zm * zm * q;
+                const R beta = exp_em1(-dtau * a).e;
+                const R obt = -exp_em1(-(a + lam) * dtau).em1;
+                const R dl = (lam - a) * dtau;
+                const R em = exp_em1(-fabs(dl)).em1;
+                const R bmT = dl >= R(0) ? -beta * em : Tr * em;
+                sb_up = Fup * (r * Gm - Gp * (obt + zq) * id);
+                sb_dn = r * Gp * Flo - Gm * Fup * (bmT + beta * zq) * id;
+            } else {
+                sb_up = r * Gm * Fup - Gp * (Fup - t * Flo);
+                sb_dn = r * Gp * Flo - Gm * (Flo - t * Fup);
+            }
         } else {
             // resonance-regularised: X, Yh = Y (a - lambda) are finite at mu lambda = 1
             R a = inv_mu;
@@ -372,7 +395,7 @@ __host__ __device__ __forceinline__ double beam_at(double mu_Fstar, double tau, 
 // paper's branch decisions in FP64, the coefficients in R.  Fb_up and Fb_lo
 // are the beam at the top and bottom interfaces; Blo, Bup the Planck bin
 // radiances there.
-template <bool MIXED, class R>
+template <bool MIXED, class R, bool THIN = false>
 __host__ __device__ __forceinline__ Layer<R> layer_item(double dt, double w, double g, bool day,
                                                         double mu, double inv_mu, double Fb_up,
                                                         double Fb_lo, R Blo, R Bup, const Opts &o,
@@ -391,7 +414,7 @@ __host__ __device__ __forceinline__ Layer<R> layer_item(double dt, double w, dou
     const bool iso = !o.noniso || dt < o.e_tau;
     if (o.noniso && dt < o.e_tau) fl |= F_ETAU;
     Layer<R> Ly;
-    layer_terms<R>(R(dt), R(w), R(g), R(E), R(1.0 - w), R(E - w), R(1.0 - w * g), day, R(mu),
+    layer_terms<R, THIN>(R(dt), R(w), R(g), R(E), R(1.0 - w), R(E - w), R(1.0 - w * g), day, R(mu),
                    R(inv_mu), R(D), guard, R(Fb_up), R(Fb_lo), Blo, Bup, iso, R(inv_eps2), Ly);
     return Ly;
 }

@@ -17,7 +17,7 @@ LIB_PATH = pathlib.Path(__file__).resolve().parent / "librt_mi355x.so"
 RT_OK, RT_PENDING = 0, 1
 RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EDOMAIN, RT_EBUSY, RT_ENOTFOUND = -1, -2, -3, -4, -5, -6
 RT_FP64, RT_MIXED = 0, 1
-RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER = 0, 1, 2
+RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER, RT_KERNEL_DEEP = 0, 1, 2, 3
 FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
 
 #: every symbol include/rt.h declares
@@ -340,7 +340,8 @@ _tuning = None
 
 def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int) -> tuple[int, int]:
     """(kernel, tile width) chosen by the autotuner (``tune.py``) for the nearest
-    measured shape with the same bins and precision; (0, 0) = library defaults."""
+    measured shape with the same bins and precision, if within a factor e in
+    columns and layers together; else (0, 0) = library defaults."""
     global _tuning
     if _tuning is None:
         import json
@@ -350,7 +351,7 @@ def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int) -> tup
         if e["n_bins"] != n_bins or e["precision"] != precision:
             continue
         d = abs(np.log(e["n_cols"] / n_cols)) + abs(np.log(e["n_layers"] / n_layers))
-        if dist is None or d < dist:
+        if d <= 1.0 and (dist is None or d < dist):
             best, dist = (e.get("kernel", 0), e["cols_per_block"]), d
     kernel, K = best
     if K > n_cols:

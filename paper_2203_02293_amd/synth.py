@@ -102,6 +102,7 @@ class Spec:
     name: str
     g_level: int = 4            # icosahedral refinement -> columns
     n_cols: int | None = None   # explicit column count (first n points)
+    col_offset: int = 0         # index of the first icosahedral point used
     n_layers: int = 40
     n_bins: int = 30
     lam_min_um: float = 0.3
@@ -139,6 +140,13 @@ SPECS: dict[str, Spec] = {
                  cloud_g0_hi=0.98, seed=1004),
 }
 SPECS["cfg2"] = dataclasses.replace(SPECS["cfg1"], name="cfg2")
+#: Few deep columns (the grids that split columns into layer segments): one
+#: dayside column (mu_star 0.85) of 4096 layers; 16 columns of 1000 layers at
+#: the first icosahedral points (day and night), about half with cloud decks.
+SPECS["deep1"] = Spec(name="deep1", g_level=4, n_cols=1, col_offset=5, n_layers=4096,
+                      cloud="fraction", cloud_fraction=0.5, seed=1005)
+SPECS["deep16"] = Spec(name="deep16", g_level=4, n_cols=16, n_layers=1000, cloud="fraction",
+                       cloud_fraction=0.5, seed=1006)
 
 
 def stellar_spectrum(lam_edges: np.ndarray, t_star: float, f_bol: float) -> np.ndarray:
@@ -175,6 +183,7 @@ def make(spec: Spec | str, n_cols: int | None = None, mu_star: np.ndarray | None
     mu_all = columns_from_points(lat, lon)
     C = n_cols if n_cols is not None else (spec.n_cols or mu_all.size)
     if mu_star is None:
+        mu_all = np.roll(mu_all, -spec.col_offset)
         if C <= mu_all.size:
             mu = mu_all[:C].copy()
         else:

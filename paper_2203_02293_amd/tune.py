@@ -1,4 +1,4 @@
-"""Autotuner of the solve launch: kernel (lane or layer) and tile width.
+"""Autotuner of the solve launch: kernel (lane, layer or deep) and tile width.
 
 For each representative shape (columns, layers, bins) and precision it times
 rt_solve_fluxes with each kernel and every admissible tile width K and
@@ -19,16 +19,17 @@ import numpy as np
 
 from . import rt, synth
 
-SHAPES = [  # (columns, layers, bins): GCM size, serving mix corners, high resolution
+SHAPES = [  # (columns, layers, bins): GCM size, serving mix corners, high resolution,
+    # few deep columns
     (2562, 40, 30), (512, 40, 30), (4096, 120, 30), (256, 80, 100), (2048, 60, 100),
-    (1024, 80, 300), (4096, 120, 300),
+    (1024, 80, 300), (4096, 120, 300), (1, 4096, 30), (16, 1000, 30), (64, 400, 30),
 ]
 
 
 def candidates(nb: int, n_cols: int) -> list[tuple[int, int]]:
     """(kernel, K) pairs: the layer kernel's default tile and a spread around it,
-    and the lane kernel's tiles (K * bins <= 512)."""
-    out = [(rt.RT_KERNEL_LAYER, 0)]
+    the lane kernel's tiles (K * bins <= 512) and the deep kernel."""
+    out = [(rt.RT_KERNEL_LAYER, 0), (rt.RT_KERNEL_DEEP, 0)]
     out += [(rt.RT_KERNEL_LAYER, k) for k in (1, 2, 3, 4, 6, 8, 10, 11, 12, 16, 24, 32)
             if k * nb <= 1024 and k <= n_cols]
     out += [(rt.RT_KERNEL_LANE, k) for k in (1, 2, 4, 8, 16)
@@ -78,7 +79,8 @@ def main(argv=None):
             best = min(times, key=times.get)
             entries.append(dict(n_cols=C, n_layers=N, n_bins=NB, precision=prec,
                                 kernel=best[0], cols_per_block=best[1], ms=times[best]))
-            name = {rt.RT_KERNEL_LANE: "lane", rt.RT_KERNEL_LAYER: "layer"}
+            name = {rt.RT_KERNEL_LANE: "lane", rt.RT_KERNEL_LAYER: "layer",
+                    rt.RT_KERNEL_DEEP: "deep"}
             report.append(dict(shape=[C, N, NB], precision=prec,
                                ms={f"{name[kk]}:{k}": round(v, 4) for (kk, k), v in times.items()},
                                best=[name[best[0]], best[1]]))

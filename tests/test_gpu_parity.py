@@ -42,8 +42,8 @@ def rt(torch):
     return r
 
 
-KERNELS = [1, 2]               # RT_KERNEL_LANE, RT_KERNEL_LAYER
-KERNEL_IDS = ["lane", "layer"]
+KERNELS = [1, 2, 3]            # RT_KERNEL_LANE, RT_KERNEL_LAYER, RT_KERNEL_DEEP
+KERNEL_IDS = ["lane", "layer", "deep"]
 
 
 def gpu_solve(rt, torch, w, precision, per_bin=False, opts=None, F_toa=None, kernel=None,
