@@ -52,7 +52,7 @@ typedef int32_t rt_status;
  * is composed per segment and joined by scans over segments: for few, deep
  * columns; several launches on the stream, rt_solve_fluxes only (rt_submit:
  * RT_EINVAL), cols_per_block must be 0.  AUTO picks DEEP for a stream-ordered
- * solve of at least 128 slabs with at most one column per 4 compute units,
+ * solve of at least 40 slabs with at most one column per 2 compute units,
  * else LAYER (serving: LAYER). */
 #define RT_KERNEL_AUTO  0
 #define RT_KERNEL_LANE  1
@@ -185,6 +185,13 @@ typedef struct {
  * one stream, or synchronise between streams.
  */
 rt_status rt_solve_fluxes(rt_handle *h, const rt_request *req, void *hip_stream);
+
+/*
+ * The kernel rt_solve_fluxes would run for req (RT_KERNEL_LANE, _LAYER or
+ * _DEEP: AUTO resolved), checking req as rt_solve_fluxes does but launching
+ * nothing; RT_EINVAL (negative) on a bad request.
+ */
+int32_t rt_request_kernel(rt_handle *h, const rt_request *req);
 
 /*
  * Serving path: enqueue a request and return at once with *ticket.  The

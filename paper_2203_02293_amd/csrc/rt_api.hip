@@ -26,9 +26,10 @@ constexpr int kMaxBins = 512;
 constexpr int kMaxBinPoints = 768;   // bins x Gaussian points: lanes of one column
 constexpr int kMaxLayers = 4096;
 // AUTO takes the deep kernel from this many slabs, for at most one column per
-// this many compute units
-constexpr int kDeepMinSlabs = 128;
-constexpr int kDeepColsPerCu = 4;
+// this many compute units (measured crossover: 128 columns at 40 to 400 layers
+// on 256 compute units)
+constexpr int kDeepMinSlabs = 40;
+constexpr int kDeepColsPerCu = 2;
 constexpr int kStreams = 4;
 constexpr size_t kAlign = 256;
 
@@ -563,6 +564,18 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
                        : rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(h, e, "solve launch");
     return RT_OK;
+}
+
+extern "C" int32_t rt_request_kernel(rt_handle *h, const rt_request *r)
+{
+    if (!h) return RT_EINVAL;
+    const rt_status st = validate(h, r);
+    if (st != RT_OK) return st;
+    switch (request_geometry(h, r).kernel) {
+    case rtk::KERNEL_LANE: return RT_KERNEL_LANE;
+    case rtk::KERNEL_DEEP: return RT_KERNEL_DEEP;
+    default: return RT_KERNEL_LAYER;
+    }
 }
 
 // ---------------------------------------------------------------- serving

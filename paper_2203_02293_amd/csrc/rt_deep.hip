@@ -23,7 +23,7 @@
 //                 the BOA condition, F_up at every segment bottom.
 //   k_deep_back   per segment: the back-substitution, bin sums and net flux of
 //                 its levels.
-//   k_deep_final  per column: heating rates and the condition bits.
+//   k_deep_final  per (layer, column): heating rates.
 //
 // The elimination carries c_j and eps_j = 1 - c_j.  With A = 1 - r - t, one
 // layer maps (c, eps) above it to (c', eps') below it as the 2x2 matrix
@@ -53,7 +53,8 @@ namespace {
 //   fb   [N+1][L]         direct beam at every level
 //   seg  [SG_COUNT][S][L] per segment (fields below)
 //   lane [3][L]           F_BOA, F_up and F_dn at level 0
-//   flag [2][S][C]        uint32: condition bits of the items and back kernels
+// The condition bits go straight to the flags output: k_deep_tau clears them,
+// the later kernels OR into them (one atomic per workgroup).
 enum SegField : int {
     SG_TAU = 0,                    // optical-depth sum of the segment's slabs
     SG_P00, SG_P01, SG_P10, SG_P11, // (c, eps) map of the segment
@@ -69,14 +70,13 @@ struct DeepLayout {
     long long L;
     int S, Ls;
     double *coef, *rec, *fb, *seg, *lane;
-    uint32_t *flag;
 };
 
 __host__ __device__ __forceinline__ size_t deep_scratch_doubles(int C, int N, int NB, int S)
 {
     const size_t L = (size_t)C * NB;
-    return (size_t)N * 12 * L + (size_t)(N + 1) * L + (size_t)SG_COUNT * S * L + 3 * L +
-           (size_t)S * C;   // the flags: 2 S C uint32
+    (void)C;
+    return (size_t)N * 12 * L + (size_t)(N + 1) * L + (size_t)SG_COUNT * S * L + 3 * L;
 }
 
 __device__ __forceinline__ DeepLayout deep_layout(const SolveArgs &a)
@@ -90,7 +90,6 @@ __device__ __forceinline__ DeepLayout deep_layout(const SolveArgs &a)
     d.fb = d.rec + (long long)a.N * 6 * d.L;
     d.seg = d.fb + (long long)(a.N + 1) * d.L;
     d.lane = d.seg + (long long)SG_COUNT * d.S * d.L;
-    d.flag = reinterpret_cast<uint32_t *>(d.lane + 3 * d.L);
     return d;
 }
 
@@ -147,11 +146,20 @@ __host__ __device__ inline ItemsLds items_lds(int NB, int NBR, int QL, bool mixe
     return o;
 }
 
-// Levels per pass of the back-substitution kernel: its LDS within 64 KiB.
+// Workgroup size bound of the per-lane kernels: one thread per lane of a
+// column, at most 768 lanes (bins x Gaussian points).
+constexpr int kDeepLaneThreads = 768;
+
+// Layers of one run of the elimination and levels of one pass of the
+// back-substitution whose records a thread loads at once.
+constexpr int kDeepRun = 8;
+
+// Levels per pass of the back-substitution kernel: at most kDeepRun, its LDS
+// within 64 KiB.
 __host__ __device__ inline int back_chunk(int NB)
 {
     const int c = (8192 - NB - 64) / (3 * NB);
-    return c < 1 ? 1 : (c > 8 ? 8 : c);
+    return c < 1 ? 1 : (c > kDeepRun ? kDeepRun : c);
 }
 
 __host__ __device__ inline size_t back_lds(int NB, int CH)
@@ -159,18 +167,41 @@ __host__ __device__ inline size_t back_lds(int NB, int CH)
     return ((size_t)3 * CH * NB + NB + 3 * CH) * 8 + 8;
 }
 
+// OR the workgroup's condition bits (gathered in LDS word *s_flag) into the
+// column's flags
+__device__ __forceinline__ void flags_out(const SolveArgs &a, int c, const uint32_t *s_flag)
+{
+    if (threadIdx.x == 0 && a.flags && *s_flag) atomicOr(&a.flags[c], *s_flag);
+}
+
+// Sum of p[k * stride] for k = 0 .. n-1 in that order, the loads issued in
+// groups of 8 (adding 0 past the end is exact).
+__device__ __forceinline__ double sum_strided(const double *p, long long stride, int n)
+{
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = k0 + q < n ? p[(long long)(k0 + q) * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------ k_deep_tau
-__global__ void __launch_bounds__(kMaxThreads) k_deep_tau(const SolveArgs a)
+// Optical-depth sum of each segment and lane, from the top down; clears the
+// flags.
+__global__ void __launch_bounds__(kDeepLaneThreads) k_deep_tau(const SolveArgs a)
 {
     const DeepLayout d = deep_layout(a);
     const int c = blockIdx.x / d.S, s = blockIdx.x - c * d.S, b = threadIdx.x;
+    if (s == 0 && b == 0 && a.flags) a.flags[c] = 0u;
     if (b >= a.NB) return;
     int top, bot;
     seg_range(a, d, s, top, bot);
     const long long l = (long long)c * a.NB + b;
-    double tau = 0.0;
-    for (int j = top - 1; j >= bot; --j) tau += a.dtau[(long long)j * d.L + l];   // from the top down
-    seg_at(d, SG_TAU, s, l) = tau;
+    seg_at(d, SG_TAU, s, l) = sum_strided(a.dtau + (long long)(top - 1) * d.L + l, -d.L, top - bot);
 }
 
 // ---------------------------------------------------------------- k_deep_items
@@ -220,11 +251,10 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
     // QL partial sums per lane (loads in parallel), then added in order
     {
         const int grp = tid / NB, b = tid - grp * NB;
-        if (grp < QL) {
-            double part = 0.0;
-            for (int s2 = grp; s2 < s; s2 += QL) part += seg_at(d, SG_TAU, s2, lc + b);
-            s_M[grp * NB + b] = part;
-        }
+        if (grp < QL)
+            s_M[grp * NB + b] = grp < s ? sum_strided(&seg_at(d, SG_TAU, grp, lc + b),
+                                                      (long long)QL * d.L, (s - grp + QL - 1) / QL)
+                                        : 0.0;
     }
     __syncthreads();
     const bool lane_thr = tid < NB;
@@ -264,10 +294,18 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         if (boa && q0 == 0)
             for (int e = tid; e <= NBR; e += W) s_edge[QL * (NBR + 1) + e] = edge_val(e, a.Tint[c]);
         if (lane_thr) {
-            for (int q = 0; q < n; ++q) {
-                const int lev = hi - q;
-                if (lev < top) tau += a.dtau[(long long)lev * d.L + lc + tid];   // slab above level lev
-                s_tau[q * NB + tid] = tau;
+            for (int q0 = 0; q0 < n; q0 += 8) {   // loads in groups of 8
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int lev = hi - q0 - q;   // slab lev lies above level lev
+                    v[q] = q0 + q < n && lev < top ? a.dtau[(long long)lev * d.L + lc + tid] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    tau += v[q];
+                    if (q0 + q < n) s_tau[(q0 + q) * NB + tid] = tau;
+                }
             }
         }
         __syncthreads();
@@ -350,7 +388,7 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
     }
     if (fl) atomicOr(s_flag, fl);
     __syncthreads();
-    if (tid == 0) d.flag[(long long)s * a.C + c] = *s_flag;
+    flags_out(a, c, s_flag);
 }
 
 // ------------------------------------------------------------------- scans
@@ -489,7 +527,7 @@ __global__ void __launch_bounds__(kScanThreads) k_deep_scan(const SolveArgs a)
 }
 
 // ----------------------------------------------------------------- k_deep_elim
-__global__ void __launch_bounds__(kMaxThreads) k_deep_elim(const SolveArgs a)
+__global__ void __launch_bounds__(kDeepLaneThreads) k_deep_elim(const SolveArgs a)
 {
     const DeepLayout d = deep_layout(a);
     const int c = blockIdx.x / d.S, s = blockIdx.x - c * d.S, b = threadIdx.x;
@@ -502,41 +540,46 @@ __global__ void __launch_bounds__(kMaxThreads) k_deep_elim(const SolveArgs a)
     // d at the segment top: the TOA value on the first segment, else symbolic
     double d0 = s == 0 ? (a.Ftoa ? a.Ftoa[l] : 0.0) : 0.0, ds = s == 0 ? 0.0 : 1.0;
     double gam = 1.0, eta0 = 0.0, etas = 0.0;
-    // coefficients of the next layer, loaded one layer ahead of their use
-    double nt = 0.0, nr = 0.0, no = 0.0, nA = 0.0, nu = 0.0, nd = 0.0;
-    auto load = [&](int j) {
-        const double *cp = d.coef + (long long)j * 6 * d.L + l;
-        nt = cp[0];
-        nr = cp[d.L];
-        no = cp[2 * d.L];
-        nA = cp[3 * d.L];
-        nu = cp[4 * d.L];
-        nd = cp[5 * d.L];
-    };
-    if (top > bot) load(top - 1);
-    for (int j = top - 1; j >= bot; --j) {
-        const double t = nt, r = nr, omr = no, A = nA, Sup = nu, Sdn = nd;
-        if (j > bot) load(j - 1);
-        const double inv = rcp(omr + r * eps);   // 1 / (1 - r c)
-        const double G = t * inv, H0 = (r * d0 + Sup) * inv, Hs = r * ds * inv;
-        double *rp = d.rec + (long long)j * 6 * d.L + l;
-        rp[0] = G;
-        rp[d.L] = H0;
-        rp[2 * d.L] = Hs;
-        rp[3 * d.L] = cc;
-        rp[4 * d.L] = d0;
-        rp[5 * d.L] = ds;
-        eta0 += gam * H0;
-        etas += gam * Hs;
-        gam *= G;
-        const double cn = r + t * t * cc * inv;
-        const double en = (A * (omr + t) + eps * (r * omr + t * t)) * inv;
-        const double dn0 = Sdn + t * (d0 + cc * Sup) * inv;
-        const double dns = t * ds * inv;
-        cc = cn;
-        eps = en;
-        d0 = dn0;
-        ds = dns;
+    // runs of kDeepRun layers: the run's coefficients are loaded at once
+    // (indices clamped into the segment, so every load is unconditional)
+    for (int j0 = top - 1; j0 >= bot; j0 -= kDeepRun) {
+        double ct[kDeepRun], cr[kDeepRun], co[kDeepRun], cA[kDeepRun], cu[kDeepRun], cd[kDeepRun];
+#pragma unroll
+        for (int q = 0; q < kDeepRun; ++q) {
+            const double *cp = d.coef + (long long)max(j0 - q, bot) * 6 * d.L + l;
+            ct[q] = cp[0];
+            cr[q] = cp[d.L];
+            co[q] = cp[2 * d.L];
+            cA[q] = cp[3 * d.L];
+            cu[q] = cp[4 * d.L];
+            cd[q] = cp[5 * d.L];
+        }
+#pragma unroll
+        for (int q = 0; q < kDeepRun; ++q) {
+            const int j = j0 - q;
+            if (j < bot) break;
+            const double t = ct[q], r = cr[q], omr = co[q], A = cA[q], Sup = cu[q], Sdn = cd[q];
+            const double inv = rcp(omr + r * eps);   // 1 / (1 - r c)
+            const double G = t * inv, H0 = (r * d0 + Sup) * inv, Hs = r * ds * inv;
+            double *rp = d.rec + (long long)j * 6 * d.L + l;
+            rp[0] = G;
+            rp[d.L] = H0;
+            rp[2 * d.L] = Hs;
+            rp[3 * d.L] = cc;
+            rp[4 * d.L] = d0;
+            rp[5 * d.L] = ds;
+            eta0 += gam * H0;
+            etas += gam * Hs;
+            gam *= G;
+            const double cn = r + t * t * cc * inv;
+            const double en = (A * (omr + t) + eps * (r * omr + t * t)) * inv;
+            const double dn0 = Sdn + t * (d0 + cc * Sup) * inv;
+            const double dns = t * ds * inv;
+            cc = cn;
+            eps = en;
+            d0 = dn0;
+            ds = dns;
+        }
     }
     seg_at(d, SG_D0, s, l) = d0;
     seg_at(d, SG_DS, s, l) = ds;
@@ -551,7 +594,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_deep_elim(const SolveArgs a)
 // Levels (bot, top] of the segment, and level 0 on the bottom segment, in
 // passes of CH levels: per-lane fluxes into LDS, then the bin sums of each
 // (quantity, level) by one thread over the lanes in order, then the net flux.
-__global__ void __launch_bounds__(kMaxThreads) k_deep_back(const SolveArgs a)
+__global__ void __launch_bounds__(kDeepLaneThreads) k_deep_back(const SolveArgs a)
 {
     extern __shared__ double smem[];
     const DeepLayout d = deep_layout(a);
@@ -571,28 +614,31 @@ __global__ void __launch_bounds__(kMaxThreads) k_deep_back(const SolveArgs a)
     const double dtop = act ? seg_at(d, SG_D_TOP, s, l) : 0.0;
     double Fu = act ? seg_at(d, SG_FU_BOT, s, l) : 0.0, Fd = 0.0;
     const int lev0 = bot == 0 ? 0 : bot + 1;   // first level this segment writes
-    // the record of the next layer, loaded one level ahead of its use
-    double rG = 0.0, rH = 0.0, rc = 0.0, rd = 0.0;
-    auto load = [&](int j) {
-        const double *rp = d.rec + (long long)j * 6 * d.L + l;
-        rG = rp[0];
-        rH = rp[d.L] + rp[2 * d.L] * dtop;
-        rc = rp[3 * d.L];
-        rd = rp[4 * d.L] + rp[5 * d.L] * dtop;
-    };
-    if (act && lev0 > 0) load(lev0 - 1);
     for (int c0 = lev0; c0 <= top; c0 += CH) {
         const int nl = min(CH, top + 1 - c0);
         if (act) {
-            for (int q = 0; q < nl; ++q) {
+            // the pass's records (slab lev - 1 below level lev) and beam, loaded
+            // at once (indices clamped, every load unconditional)
+            double rG[kDeepRun], rH[kDeepRun], rc[kDeepRun], rd[kDeepRun], rb[kDeepRun];
+#pragma unroll
+            for (int q = 0; q < kDeepRun; ++q) {
+                const int lev = min(c0 + q, top);
+                const double *rp = d.rec + (long long)max(lev - 1, 0) * 6 * d.L + l;
+                rG[q] = rp[0];
+                rH[q] = rp[d.L] + rp[2 * d.L] * dtop;
+                rc[q] = rp[3 * d.L];
+                rd[q] = rp[4 * d.L] + rp[5 * d.L] * dtop;
+                rb[q] = d.fb[(long long)lev * d.L + l];
+            }
+#pragma unroll
+            for (int q = 0; q < kDeepRun; ++q) {
+                if (q >= nl) break;
                 const int lev = c0 + q;
-                const double G = rG, H = rH, cj = rc, dj = rd;   // slab lev - 1 below this level
-                if (lev < top) load(lev);
                 if (lev == 0) {
                     Fu = d.lane[d.L + l];
                     Fd = d.lane[2 * d.L + l];
                 } else {
-                    back_step(G, H, cj, dj, Fu, Fd);
+                    back_step(rG[q], rH[q], rc[q], rd[q], Fu, Fd);
                 }
                 const long long o = (long long)lev * d.L + l;
                 if (a.F_up_bin) a.F_up_bin[o] = Fu;
@@ -600,7 +646,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_deep_back(const SolveArgs a)
                 if (lev == a.N && a.F_up_toa_bin && NG == 1) a.F_up_toa_bin[l] = Fu;
                 s_v[(0 * CH + q) * NB + b] = Fu;
                 s_v[(1 * CH + q) * NB + b] = Fd;
-                s_v[(2 * CH + q) * NB + b] = d.fb[o];
+                s_v[(2 * CH + q) * NB + b] = rb[q];
             }
         }
         __syncthreads();
@@ -632,41 +678,32 @@ __global__ void __launch_bounds__(kMaxThreads) k_deep_back(const SolveArgs a)
         // the next pass writes s_v before its barrier and s_sum after it
     }
     __syncthreads();
-    if (tid == 0) d.flag[(long long)(d.S + s) * a.C + c] = *s_flag;
+    flags_out(a, c, s_flag);
 }
 
 // ---------------------------------------------------------------- k_deep_final
-// Heating of each layer from the net flux at its two interfaces, and the
-// column's condition bits: the kernels' bits and the pressure checks.
-constexpr int kFinalThreads = 128;
+// Heating of each layer from the net flux at its two interfaces, one thread
+// per (layer, column), and the pressure checks into the column's flags.
+constexpr int kFinalThreads = 256;
 
 __global__ void __launch_bounds__(kFinalThreads) k_deep_final(const SolveArgs a)
 {
-    __shared__ uint32_t s_flag;
-    const DeepLayout d = deep_layout(a);
-    const int c = blockIdx.x, tid = threadIdx.x, C = a.C;
-    if (tid == 0) s_flag = 0u;
-    __syncthreads();
-    uint32_t fl = 0u;
-    for (int s = tid; s < 2 * d.S; s += kFinalThreads) fl |= d.flag[(long long)s * C + c];
-    const int NL = a.sub ? a.N / 2 : a.N;
-    for (int j = tid; j < NL; j += kFinalThreads) {
-        const long long o = (long long)j * C + c;
-        const double p0 = a.p[o], p1 = a.p[o + C];
-        const double dp = p0 - p1;
-        bool bad = !(dp > 0.0);
-        if (a.sub) {
-            const double pm = a.pc[o];
-            bad = bad || !(p0 > pm && pm > p1);
-        }
-        if (bad) fl |= F_INVALID;
-        const double qh = a.o.gravity * (a.F_net[o] - a.F_net[o + C]) / dp;
-        a.heat[o] = qh;
-        if (a.dTdt) a.dTdt[o] = qh / a.o.cp;
+    const long long e = (long long)blockIdx.x * kFinalThreads + threadIdx.x;
+    const int C = a.C, NL = a.sub ? a.N / 2 : a.N;
+    if (e >= (long long)NL * C) return;
+    const int j = (int)(e / C), c = (int)(e - (long long)j * C);
+    const long long o = (long long)j * C + c;
+    const double p0 = a.p[o], p1 = a.p[o + C];
+    const double dp = p0 - p1;
+    bool bad = !(dp > 0.0);
+    if (a.sub) {
+        const double pm = a.pc[o];
+        bad = bad || !(p0 > pm && pm > p1);
     }
-    if (fl) atomicOr(&s_flag, fl);
-    __syncthreads();
-    if (tid == 0 && a.flags) a.flags[c] = s_flag;
+    if (bad && a.flags) atomicOr(&a.flags[c], (uint32_t)F_INVALID);
+    const double qh = a.o.gravity * (a.F_net[o] - a.F_net[o + C]) / dp;
+    a.heat[o] = qh;
+    if (a.dTdt) a.dTdt[o] = qh / a.o.cp;
 }
 
 }  // namespace
@@ -675,7 +712,7 @@ Geometry deep_geometry(int C, int N, int NB, const DeviceLimits &dev)
 {
     Geometry g{};
     g.kernel = KERNEL_DEEP;
-    if (C < 1 || N < 1 || NB < 1 || NB > deep_items_max_threads(false)) return g;
+    if (C < 1 || N < 1 || NB < 1 || NB > kDeepLaneThreads) return g;
     const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
     // about two workgroups per compute unit, segments of at least 8 slabs,
     // at most 256 segments (one scan workgroup's width)
@@ -731,7 +768,9 @@ hipError_t launch_deep(const SolveArgs &a, const Geometry &g, int precision, hip
     hipLaunchKernelGGL(k_deep_elim, dim3(g.blocks), dim3(g.threads), 0, s, b);
     hipLaunchKernelGGL(k_deep_scan, dim3(scan_blocks), dim3(kScanThreads), 0, s, b);
     hipLaunchKernelGGL(k_deep_back, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
-    hipLaunchKernelGGL(k_deep_final, dim3(a.C), dim3(kFinalThreads), 0, s, b);
+    const long long nlay = (long long)(a.sub ? a.N / 2 : a.N) * a.C;
+    hipLaunchKernelGGL(k_deep_final, dim3((unsigned)((nlay + kFinalThreads - 1) / kFinalThreads)),
+                       dim3(kFinalThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1,
 #: every symbol include/rt.h declares
 SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes", "rt_submit",
            "rt_poll", "rt_wait", "rt_work_bytes", "rt_last_error", "rt_status_string",
-           "rt_set_opacities", "rt_optical_properties")
+           "rt_set_opacities", "rt_optical_properties", "rt_request_kernel")
 
 
 class RtConfig(ct.Structure):
@@ -88,6 +88,8 @@ def lib() -> ct.CDLL:
         L.rt_destroy.restype = ct.c_int32
         L.rt_solve_fluxes.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.c_void_p]
         L.rt_solve_fluxes.restype = ct.c_int32
+        L.rt_request_kernel.argtypes = [ct.c_void_p, ct.POINTER(RtRequest)]
+        L.rt_request_kernel.restype = ct.c_int32
         L.rt_submit.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.POINTER(ct.c_uint64)]
         L.rt_set_opacities.argtypes = [ct.c_void_p, ct.POINTER(RtOpacities)]
         L.rt_set_opacities.restype = ct.c_int32
@@ -143,6 +145,13 @@ def _check(h, st, what):
 
 def rt_solve_fluxes(h: int, req: RtRequest, stream: int | None) -> int:
     return _check(h, lib().rt_solve_fluxes(h, ct.byref(req), stream), "rt_solve_fluxes")
+
+
+def rt_request_kernel(h: int, req: RtRequest) -> int:
+    k = lib().rt_request_kernel(h, ct.byref(req))
+    if k < 0:
+        _check(h, k, "rt_request_kernel")
+    return k
 
 
 def rt_set_opacities(h: int, op: RtOpacities) -> int:
@@ -276,6 +285,11 @@ class Solver:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         rt_solve_fluxes(self.h, req, s.cuda_stream)
         return out
+
+    def kernel_for(self, inp: dict, out: dict, precision: int = RT_FP64,
+                   cols_per_block: int | None = None, kernel: int | None = None) -> int:
+        """The kernel ``solve`` would run (RT_KERNEL_LANE, _LAYER or _DEEP)."""
+        return rt_request_kernel(self.h, self.request(inp, out, precision, cols_per_block, kernel))
 
     def submit(self, inp: dict, out: dict, precision: int = RT_FP64,
                cols_per_block: int | None = None, kernel: int | None = None) -> int:

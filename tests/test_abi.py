@@ -87,5 +87,6 @@ def test_null_arguments(lib):
     assert lib.rt_create(None, ct.byref(h)) == rt.RT_EINVAL
     assert lib.rt_destroy(None) == rt.RT_OK
     assert lib.rt_solve_fluxes(None, None, None) == rt.RT_EINVAL
+    assert lib.rt_request_kernel(None, None) == rt.RT_EINVAL
     assert lib.rt_poll(None, 1) == rt.RT_EINVAL
     assert lib.rt_last_error(None) == b"null handle"
