@@ -50,10 +50,9 @@ typedef int32_t rt_status;
  * elimination runs per lane.  DEEP: each column's layers are split into
  * segments on separate workgroups and the Thomas recurrence (Section 2.2.2)
  * is composed per segment and joined by scans over segments: for few, deep
- * columns; several launches on the stream, rt_solve_fluxes only (rt_submit:
- * RT_EINVAL), cols_per_block must be 0.  AUTO picks DEEP for a stream-ordered
- * solve of at least 40 slabs with at most one column per 2 compute units,
- * else LAYER (serving: LAYER). */
+ * columns; several launches on the stream (serving: a launch sequence of its
+ * own per request), cols_per_block must be 0.  AUTO picks DEEP for at least 40
+ * slabs with at most one column per 2 compute units, else LAYER. */
 #define RT_KERNEL_AUTO  0
 #define RT_KERNEL_LANE  1
 #define RT_KERNEL_LAYER 2
@@ -196,11 +195,12 @@ int32_t rt_request_kernel(rt_handle *h, const rt_request *req);
 /*
  * Serving path: enqueue a request and return at once with *ticket.  The
  * library admits queued requests onto the device in arrival order when its
- * memory budget allows; requests of the same precision and tile width that are
- * admitted together run as one batched launch (each workgroup finds its
- * request and column tile in a descriptor table), up to 64 per launch and 16
- * launches in flight on 4 library-owned streams.  Results equal those of
- * rt_solve_fluxes bit for bit.  Requests retire in any order.  The inputs must
+ * memory budget allows; requests of the same kernel, precision and tile width
+ * that are admitted together run as one batched launch (each workgroup finds
+ * its request and column tile in a descriptor table), up to 64 per launch; a
+ * request on the deep kernel runs as its own launch sequence; 16 batches in
+ * flight on 4 library-owned streams.  Results equal those of rt_solve_fluxes
+ * (same request) bit for bit.  Requests retire in any order.  The inputs must
  * be complete on the device before the call (the library's streams do not wait
  * on the caller's), and the request's buffers must stay valid, and must not be
  * touched, until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:
@@ -264,9 +264,9 @@ typedef struct {
 rt_status rt_optical_properties(rt_handle *h, const rt_optics_request *req, void *hip_stream);
 
 /*
- * Device bytes of work buffer the serving path reserves from its budget for
- * one request of this shape (default tile of the layer kernel); -1 on bad
- * arguments.  Stream-ordered solves grow the handle's own buffer as needed.
+ * Device bytes of work buffer one solve of this shape needs with the default
+ * choices (RT_KERNEL_AUTO, default tile, no sub-layer grid): what the serving
+ * path reserves from its budget for such a request; -1 on bad arguments.
  */
 int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_layers);
 

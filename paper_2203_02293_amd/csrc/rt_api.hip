@@ -196,7 +196,9 @@ extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_l
 {
     if (!h || n_cols < 1 || n_layers < 1 || n_layers > kMaxLayers) return -1;
     const rtk::Geometry g =
-        rtk::solve_geometry(n_cols, n_layers, h->NBG, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
+        prefer_deep(h, n_cols, n_layers)
+            ? rtk::deep_geometry(n_cols, n_layers, h->NBG, h->dev)
+            : rtk::solve_geometry(n_cols, n_layers, h->NBG, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
     return g.threads > 0 ? (int64_t)g.scratch : -1;
 }
 
@@ -322,13 +324,11 @@ extern "C" rt_status rt_destroy(rt_handle *h)
 // Slabs of a request: one per layer, two on the sub-layer grid.
 static int request_slabs(const rt_request *r) { return r->T_center ? 2 * r->n_layers : r->n_layers; }
 
-// serving: batched launches run the lane or layer kernel only
-static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r, bool serving = false)
+static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
 {
     const int N = request_slabs(r);
     if (r->kernel == RT_KERNEL_DEEP ||
-        (r->kernel == RT_KERNEL_AUTO && !serving && r->cols_per_block == 0 &&
-         prefer_deep(h, r->n_cols, N)))
+        (r->kernel == RT_KERNEL_AUTO && r->cols_per_block == 0 && prefer_deep(h, r->n_cols, N)))
         return rtk::deep_geometry(r->n_cols, N, h->NBG, h->dev);
     const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
     return rtk::solve_geometry(r->n_cols, N, h->NBG, r->cols_per_block, kernel, r->precision,
@@ -630,6 +630,28 @@ static void pump(rt_handle *h)
         Batch &b = h->slots[slot];
         const int prec = h->queued.front().req.precision;
         const rtk::Geometry g0 = h->queued.front().g;
+        hipStream_t s = h->streams[b.stream];
+        if (g0.kernel == rtk::KERNEL_DEEP) {
+            // a deep request is a sequence of launches of its own
+            Job j = h->queued.front();
+            size_t off;
+            if (!h->arena.alloc(j.bytes, &off)) return;   // head request waits for memory
+            j.off = off;
+            h->queued.pop_front();
+            const rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
+            hipError_t e = rtk::launch_deep(a, j.g, prec, s);
+            if (e == hipSuccess) e = hipEventRecord(b.done, s);
+            if (e != hipSuccess) {
+                hip_fail(h, e, "serving launch");
+                h->arena.release(j.off, j.bytes);
+                h->finished[j.ticket] = RT_EDEVICE;
+                return;
+            }
+            b.jobs.push_back(j);
+            b.busy = true;
+            h->running[j.ticket] = slot;
+            continue;
+        }
         int blocks = 0;
         for (auto it = h->queued.begin(); it != h->queued.end() && (int)b.jobs.size() < kMaxBatch;) {
             // one launch shape per batch: same kernel, precision, tile, threads and LDS
@@ -656,7 +678,6 @@ static void pump(rt_handle *h)
         }
         if (b.jobs.empty()) return;                 // head request waits for memory
         const int n = (int)b.jobs.size();
-        hipStream_t s = h->streams[b.stream];
         hipError_t e = hipMemcpyAsync(b.d_args, b.h_args, sizeof(rtk::SolveArgs) * n,
                                       hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
@@ -683,8 +704,6 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     if (!h || !ticket) return RT_EINVAL;
     rt_status st = validate(h, r);
     if (st != RT_OK) return st;
-    if (r->kernel == RT_KERNEL_DEEP)
-        return fail(h, RT_EINVAL, "the deep kernel runs through rt_solve_fluxes only");
     (void)hipSetDevice(h->cfg.device);
     if ((st = ensure_serving(h)) != RT_OK) return st;
     if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight) {
@@ -695,7 +714,7 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
-    j.g = request_geometry(h, r, true);
+    j.g = request_geometry(h, r);
     j.bytes = j.g.scratch;
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);

@@ -97,6 +97,8 @@ def test_deep_request_errors(rt, torch):
     out = s.outputs(2, 300)
     with pytest.raises(rt.RtError, match="cols_per_block"):
         s.solve(inp, out=out, kernel=DEEP, cols_per_block=2)
-    with pytest.raises(rt.RtError, match="rt_solve_fluxes only"):
-        s.submit(inp, out, kernel=DEEP)
+    with pytest.raises(rt.RtError, match="cols_per_block"):
+        s.submit(inp, out, kernel=DEEP, cols_per_block=2)
+    assert s.kernel_for(inp, out) == DEEP
+    assert s.kernel_for(inp, out, kernel=rt.RT_KERNEL_LAYER) == rt.RT_KERNEL_LAYER
     s.close()

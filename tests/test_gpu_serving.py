@@ -47,7 +47,7 @@ def host(out):
     return res
 
 
-@pytest.mark.parametrize("kernel", [1, 2], ids=["lane", "layer"])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3], ids=["auto", "lane", "layer", "deep"])
 @pytest.mark.parametrize("nb", [30, 100])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_mix_equals_alone(rt, torch, nb, precision, kernel):
