@@ -42,6 +42,10 @@ WORKLOADS = {
                    "sub-layer grid (80 slabs) x 30 bins x 20 Gaussian points; optical "
                    "properties from a synthetic 60 T x 28 p k-table with Rayleigh and "
                    "condensates, then the solve",
+    "deep1": "one deep column: 1 dayside column (mu_star 0.85) x 4096 layers x 30 bins, "
+             "cloud deck",
+    "deep16": "few deep columns: 16 columns x 1000 layers x 30 bins, day and night, about "
+              "half with cloud decks",
 }
 METRIC = "two-stream column·bin solves/s (FP64 vs mixed, ≤1e-5 rel err); p50/p99 latency"
 
@@ -55,9 +59,11 @@ def algorithmic_bytes(C: int, N: int, NB: int) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the lane and layer kernels are compiled from."""
     h = hashlib.sha256()
-    for p in sorted((ROOT / "paper_2203_02293_amd" / "csrc").glob("*")):
-        h.update(p.read_bytes())
+    csrc = ROOT / "paper_2203_02293_amd" / "csrc"
+    for name in ("rt_internal.hpp", "rt_kernels.hip", "rt_math.hpp", "rt_physics.hpp"):
+        h.update((csrc / name).read_bytes())
     return h.hexdigest()[:16]
 
 
@@ -74,8 +80,8 @@ def traffic_from_profiles(kernel: str) -> float | None:
     return None if k is None else float(k["bytes_per_launch"])
 
 
-KERNEL_IDS = {"auto": None, "lane": 1, "layer": 2}
-KERNEL_NAMES = {1: "k_solve_lane", 2: "k_solve_layer"}
+KERNEL_IDS = {"auto": None, "lane": 1, "layer": 2, "deep": 3}
+KERNEL_NAMES = {1: "k_solve_lane", 2: "k_solve_layer", 3: "k_deep_*"}
 
 
 def time_path(s, inp, out, precision, steps, warmup, torch, kernel=None, pre=None):
@@ -269,9 +275,10 @@ def main():
     print(f"[bench] {WORKLOAD} {C}x{N}x{NB} resident; timing FP64", file=sys.stderr, flush=True)
 
     kernel = KERNEL_IDS[args.kernel]
-    # the kernel that runs: explicit, else the tuned choice, else the library's (layer)
-    used = kernel if kernel is not None else (rt.tuned_launch(NB, rt.RT_FP64, C, N)[0] or 2)
-    used_m = kernel if kernel is not None else (rt.tuned_launch(NB, rt.RT_MIXED, C, N)[0] or 2)
+    # the kernel that runs, as the library resolves the request time_path makes
+    kw = {} if kernel is None else {"kernel": kernel, "cols_per_block": 0}
+    used = s.kernel_for(inp, out, rt.RT_FP64, **kw)
+    used_m = s.kernel_for(inp, out, rt.RT_MIXED, **kw)
     kname, kname_m = KERNEL_NAMES[used] + "<false>", KERNEL_NAMES[used_m] + "<true>"
     wall, tot, per = time_path(s, inp, out, rt.RT_FP64, args.steps, args.warmup, torch, kernel,
                                pre)
