@@ -62,7 +62,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources the lane and layer kernels are compiled from."""
     h = hashlib.sha256()
     csrc = ROOT / "paper_2203_02293_amd" / "csrc"
-    for name in ("rt_internal.hpp", "rt_kernels.hip", "rt_math.hpp", "rt_physics.hpp"):
+    for name in ("rt_internal.hpp", "rt_kernels.hip", "rt_math.hpp", "rt_physics.hpp", "rt_wave.hpp"):
         h.update((csrc / name).read_bytes())
     return h.hexdigest()[:16]
 

@@ -11,7 +11,7 @@ CSRC = PKG / "csrc"
 LIB = PKG / "librt_mi355x.so"
 SOURCES = [CSRC / "rt_kernels.hip", CSRC / "rt_deep.hip", CSRC / "rt_optics.hip", CSRC / "rt_api.hip"]
 HEADERS = [CSRC / "rt_internal.hpp", CSRC / "rt_math.hpp", CSRC / "rt_physics.hpp",
-           ROOT / "include" / "rt.h"]
+           CSRC / "rt_wave.hpp", ROOT / "include" / "rt.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -30,6 +30,7 @@
 #include "rt_internal.hpp"
 #include "rt_math.hpp"
 #include "rt_physics.hpp"
+#include "rt_wave.hpp"
 
 #include <math.h>
 #include <algorithm>
@@ -302,39 +303,6 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
 // them back in passes of CH interfaces, staged in LDS one pass ahead by all
 // threads, and closes each pass with its bin sums.
 // ---------------------------------------------------------------------------
-// Sum of v over aligned groups of `width` lanes (a power of two <= 64), all
-// by DPP moves, every lane of the wavefront taking part, in a fixed order.
-// Within a 16-lane row the lanes 1, 2, 4, 8 apart are paired (quad permutes
-// and the row mirrors, which pair the same sets), so every lane of a group of
-// up to 16 holds its sum; a 32-lane group adds row 0's sum into row 1 (lanes
-// 16..31 hold it), a 64-lane group then row 1's into row 3 (lanes 48..63).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-// the DPP move into the rows of ROWS only (0 elsewhere)
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_rows(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double seg_sum(double v, int width)
-{
-    if (width > 1) v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
-    if (width > 2) v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
-    if (width > 4) v += dpp_move<0x141>(v);       // row_half_mirror
-    if (width > 8) v += dpp_move<0x140>(v);       // row_mirror
-    if (width > 16) v += dpp_rows<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
-    if (width > 32) v += dpp_rows<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
-    return v;
-}
-
 // Workgroup size bound of the layer kernel: FP64 items need ~170 VGPRs, which
 // three wavefronts per SIMD can hold; the FP32 items fit four.
 __host__ __device__ constexpr int layer_max_threads(bool mixed) { return mixed ? 1024 : 768; }
