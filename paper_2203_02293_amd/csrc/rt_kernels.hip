@@ -1135,6 +1135,13 @@ Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
 {
     Geometry g = (kernel == KERNEL_LANE) ? lane_geometry(C, NB, K)
                                          : layer_geometry(C, NB, K, precision == 1, dev);
+    // the default tile of the layer kernel: narrower until its LDS fits
+    if (g.threads == 0 && kernel != KERNEL_LANE && K <= 0) {
+        const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
+        for (int k = std::min((C + n_cu - 1) / n_cu, layer_max_threads(precision == 1) / NB) - 1;
+             k >= 1 && g.threads == 0; --k)
+            g = layer_geometry(C, NB, k, precision == 1, dev);
+    }
     if (g.threads > 0)
         g.scratch = (size_t)N * (g.kernel == KERNEL_LANE ? 5 : 4) * (size_t)g.lanes * sizeof(double);
     return g;

@@ -126,6 +126,18 @@ def test_cfg1_sampled(rt, torch, kernel):
         np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
 
 
+def test_default_tile_fits_lds(rt, torch):
+    """2048 columns x 100 bins in FP64: the first default tile (7 columns of
+    100 lanes) exceeds the LDS, so AUTO narrows it rather than failing."""
+    w = small(C=2048, N=12, NB=100, seed=23)
+    cols = np.linspace(0, 2047, 40).astype(int)
+    ws = subset(w, cols)
+    ref = O.solve(ws, extended=True)
+    out = gpu_solve(rt, torch, w, rt.RT_FP64, kernel=0, cols_per_block=0)
+    assert_close(out, ref, ws["p_iface"], FP64_TOL, floor=FLOOR[0], cols=cols)
+    np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
+
+
 def test_toa_diffuse_flux(rt, torch):
     w = small(C=6, N=8, NB=5, seed=21)
     F_toa = np.random.Generator(np.random.PCG64(3)).uniform(0, 50, (6, 5))
