@@ -29,6 +29,9 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles
+# (16 lanes wide), at 2.4 GHz
+VALU_ISSUE_PEAK_G = 256 * 4 / 4 * 2.4
 WORKLOADS = {
     "cfg1": "GCM size: 2562 icosahedral columns x 40 layers x 30 bins log-spaced 0.3-30 um, "
             "night-side cloud deck",
@@ -67,17 +70,33 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str) -> float | None:
-    """HBM bytes per launch from the committed PMC summary, if it was taken
-    on the current kernel sources."""
+def _profiled(kernel: str) -> dict | None:
+    """The committed PMC summary of a kernel at 2562x40x30, if it was taken on
+    the current kernel sources."""
     f = ROOT / "profiles" / "traffic_cfg1.json"
     if not f.exists():
         return None
     d = json.loads(f.read_text())
     if d.get("source_hash") != kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    return d.get("kernels", {}).get(kernel)
+
+
+def traffic_from_profiles(kernel: str) -> float | None:
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size)."""
+    k = _profiled(kernel)
     return None if k is None else float(k["bytes_per_launch"])
+
+
+def valu_issue(kernel: str, ms: float) -> dict | None:
+    """VALU wave-instructions per launch (SQ_INSTS_VALU) over the launch time,
+    against the issue peak: the limit this kernel actually runs into."""
+    k = _profiled(kernel)
+    if k is None or "valu_insts_per_launch" not in k:
+        return None
+    rate = k["valu_insts_per_launch"] / (ms * 1e-3) / 1e9
+    return {"valu_insts": k["valu_insts_per_launch"], "achieved": rate, "peak": VALU_ISSUE_PEAK_G,
+            "unit": "G wave-instructions/s", "frac": rate / VALU_ISSUE_PEAK_G}
 
 
 KERNEL_IDS = {"auto": None, "lane": 1, "layer": 2, "deep": 3}
@@ -301,6 +320,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": abytes,
                      "kernel": kname, "kernel_ms": ms},
     }
+    if WORKLOAD == "cfg1":
+        line["valu_issue"] = valu_issue(kname, ms)
     if not args.no_mixed:
         print("[bench] timing mixed", file=sys.stderr, flush=True)
         wall_m, tot_m, per_m = time_path(s, inp, out, rt.RT_MIXED, args.steps, args.warmup,
@@ -315,6 +336,8 @@ def main():
                                       "traffic": (traffic_from_profiles(kname_m)
                                                   if WORKLOAD == "cfg1" else None),
                                       "kernel": kname_m}}
+        if WORKLOAD == "cfg1":
+            line["mixed"]["valu_issue"] = valu_issue(kname_m, ms_m)
     if args.compare_kernels:
         cmp = {}
         for kid, kn in KERNEL_NAMES.items():
