@@ -206,12 +206,15 @@ __global__ void __launch_bounds__(kDeepLaneThreads) k_deep_tau(const SolveArgs a
 
 // ---------------------------------------------------------------- k_deep_items
 // The segment's levels top .. bot in chunks of QL = blockDim / NB levels:
-//   1  Planck edge integrals of the chunk's levels (level, bin edge); the
-//      optical depth at each level, summed down the lane by its own thread
-//   2  level items (level, lane): bin radiance and direct beam
-//   3  layer items (layer, lane): coefficients into the work buffer, and each
+//   1  per (level, lane) item thread: the slab above its level (dtau into LDS
+//      for the optical-depth sums; dtau, w0, g0 kept for its layer item); the
+//      Planck edge integrals of the chunk's levels (level, bin edge); on the
+//      first chunk QL partial sums per lane of the segments above
+//   2  per lane: the optical depth down the lane, in order
+//   3  level items (level, lane): bin radiance and direct beam
+//   4  layer items (layer, lane): coefficients into the work buffer, and each
 //      layer's (c, eps) map into LDS
-//   4  per lane: the maps composed into the segment's map
+//   5  per lane: the maps composed into the segment's map
 // Thread b < NB owns lane b's running optical depth and map.
 template <bool MIXED>
 __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(const SolveArgs a)
@@ -246,23 +249,11 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         const double ti = a.Tint[c];
         if (!(ti >= 0.0) || !isfinite(ti)) fl |= F_INVALID;
     }
-
-    // optical depth at the segment top: the sums of the segments above, in
-    // QL partial sums per lane (loads in parallel), then added in order
-    {
-        const int grp = tid / NB, b = tid - grp * NB;
-        if (grp < QL)
-            s_M[grp * NB + b] = grp < s ? sum_strided(&seg_at(d, SG_TAU, grp, lc + b),
-                                                      (long long)QL * d.L, (s - grp + QL - 1) / QL)
-                                        : 0.0;
-    }
-    __syncthreads();
     const bool lane_thr = tid < NB;
     double tau = 0.0;
     double P00 = 1.0, P01 = 0.0, P10 = 0.0, P11 = 1.0;   // (c, eps) map of the layers so far
-    if (lane_thr)
-        for (int g = 0; g < QL; ++g) tau += s_M[g * NB + tid];
-    __syncthreads();   // s_M is reused by the layer items
+    // this thread's (level, lane) item of a chunk: level hi - iq, lane ib
+    const int iq = tid / NB, ib = tid - iq * NB;
 
     auto bin_B = [&](const R *row, int rb, double Td) -> R {
         const R Tr = R(Td), T2 = Tr * Tr;
@@ -284,7 +275,22 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
 
     for (int q0 = 0; q0 < nlev; q0 += QL) {
         const int hi = top - q0, n = min(QL, nlev - q0);
-        // 1: edge integrals; optical depth down the lane
+        // 1: the item's slab inputs (loads first, so they overlap the edge
+        // integrals), the edge integrals, the partial sums above the segment
+        const bool item = iq < n;
+        const int ilev = hi - iq;
+        const bool slab = item && ilev < top;   // slab ilev lies above level ilev
+        double xdt = 0.0, xw = 0.0, xg = 0.0;
+        if (slab) {
+            const long long idx = (long long)ilev * d.L + lc + ib;
+            xdt = a.dtau[idx];
+            xw = a.w0[idx];
+            xg = a.g0[idx];
+        }
+        if (q0 == 0 && iq < QL)
+            s_M[iq * NB + ib] = iq < s ? sum_strided(&seg_at(d, SG_TAU, iq, lc + ib), (long long)QL * d.L,
+                                                     (s - iq + QL - 1) / QL)
+                                       : 0.0;
         for (int e = tid; e < n * (NBR + 1); e += W) {
             const int q = e / (NBR + 1), k = e - q * (NBR + 1);
             const double Tv = T_level(a, hi - q, c);
@@ -293,23 +299,20 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         }
         if (boa && q0 == 0)
             for (int e = tid; e <= NBR; e += W) s_edge[QL * (NBR + 1) + e] = edge_val(e, a.Tint[c]);
+        if (item) s_tau[iq * NB + ib] = xdt;
+        __syncthreads();
+        // 2: optical depth down the lane: the segments above (first chunk),
+        // then each slab in order from the top
         if (lane_thr) {
-            for (int q0 = 0; q0 < n; q0 += 8) {   // loads in groups of 8
-                double v[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int lev = hi - q0 - q;   // slab lev lies above level lev
-                    v[q] = q0 + q < n && lev < top ? a.dtau[(long long)lev * d.L + lc + tid] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    tau += v[q];
-                    if (q0 + q < n) s_tau[(q0 + q) * NB + tid] = tau;
-                }
+            if (q0 == 0)
+                for (int g = 0; g < QL; ++g) tau += s_M[g * NB + tid];
+            for (int q = 0; q < n; ++q) {
+                tau += s_tau[q * NB + tid];
+                s_tau[q * NB + tid] = tau;
             }
         }
         __syncthreads();
-        // 2: level items
+        // 3: level items
         for (int it = tid; it < n * NB; it += W) {
             const int q = it / NB, b = it - q * NB, lev = hi - q;
             const double Tv = T_level(a, lev, c);
@@ -326,15 +329,13 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         if (boa && q0 == 0 && lane_thr)
             d.lane[lc + tid] = double(kPI) * double(bin_B(s_edge + QL * (NBR + 1), tid / NG, a.Tint[c]));
         __syncthreads();
-        // 3: layer items, layer lev between level lev+1 (row q) and level lev (row q+1)
-        for (int it = tid; it < n * NB; it += W) {
-            const int q = it / NB, b = it - q * NB, lev = hi - q;
-            if (lev == top) continue;
-            const long long idx = (long long)lev * d.L + lc + b;
-            const Layer<R> Ly = layer_item<MIXED, R, MIXED>(a.dtau[idx], a.w0[idx], a.g0[idx], day, mu, inv_mu,
-                                                     s_Fb[q * NB + b], s_Fb[(q + 1) * NB + b],
-                                                     s_B[(q + 1) * NB + b], s_B[q * NB + b], a.o,
-                                                     inv_eps2, fl);
+        // 4: layer items, layer ilev between level ilev+1 (row iq) and level ilev (row iq+1)
+        if (slab) {
+            const int q = iq, b = ib;
+            const Layer<R> Ly = layer_item<MIXED, R, MIXED>(xdt, xw, xg, day, mu, inv_mu,
+                                                            s_Fb[q * NB + b], s_Fb[(q + 1) * NB + b],
+                                                            s_B[(q + 1) * NB + b], s_B[q * NB + b], a.o,
+                                                            inv_eps2, fl);
             // t and 1 - r from whichever of a value and its complement is the
             // smaller (both relatively exact): thin layers keep 1 - t and r to
             // the coefficients' relative precision, so FP32 rounding of t near
@@ -343,7 +344,7 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
             const double r = double(Ly.r);
             const double omr = Ly.r < R(0.5) ? 1.0 - r : double(Ly.omr);
             const double A = double(Ly.A);
-            double *cp = d.coef + (long long)lev * 6 * d.L + lc + b;
+            double *cp = d.coef + (long long)ilev * 6 * d.L + lc + b;
             cp[0] = t;
             cp[d.L] = r;
             cp[2 * d.L] = omr;
@@ -358,7 +359,7 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
             mp[3 * NB] = at + rt;
         }
         __syncthreads();
-        // 4: compose the lane's maps (later layers on the left); carry the
+        // 5: compose the lane's maps (later layers on the left); carry the
         // chunk's last level to row 0 for the next chunk's first layer
         if (lane_thr) {
             for (int q = 0; q < n; ++q) {
@@ -377,7 +378,8 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
             s_B[tid] = s_B[n * NB + tid];
             s_Fb[tid] = s_Fb[n * NB + tid];
         }
-        // the next chunk's phase 1 touches none of what phase 4 reads or writes
+        // the next chunk's phases 1 and 2 touch none of what phase 5 reads or
+        // writes (s_M is rewritten only in phase 4, behind two barriers)
     }
     if (lane_thr) {
         const long long l = lc + tid;
@@ -754,7 +756,7 @@ hipError_t launch_deep(const SolveArgs &a, const Geometry &g, int precision, hip
     const int NB = a.NB, NBR = a.NB / a.NG;
     // items: (Ls + 1) levels x NB lanes per segment, as many per pass as the workgroup holds
     const int wi = std::min(deep_items_max_threads(mixed),
-                            std::max(g.threads, ((g.PC + 1) * NB + 63) / 64 * 64));
+                            std::max(g.threads, ((g.PC + 1) * std::max(NB, NBR + 1) + 63) / 64 * 64));
     const size_t lds_items = items_lds(NB, NBR, wi / NB, mixed).total;
     int Sp = 1;
     while (Sp < g.K) Sp <<= 1;
