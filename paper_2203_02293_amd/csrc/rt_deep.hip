@@ -708,6 +708,16 @@ __global__ void __launch_bounds__(kFinalThreads) k_deep_final(const SolveArgs a)
     if (a.dTdt) a.dTdt[o] = qh / a.o.cp;
 }
 
+// Workgroup size of the items kernel for segments of Ls slabs: (Ls + 1)
+// levels x NB lanes (and x NBR + 1 edges) in one round if the bound allows.
+__host__ __device__ inline int items_threads(int Ls, int NB, int NBR, bool mixed)
+{
+    const int lanes = (NB + 63) / 64 * 64;
+    const int want = ((Ls + 1) * (NB > NBR + 1 ? NB : NBR + 1) + 63) / 64 * 64;
+    const int w = want > lanes ? want : lanes;
+    return w < deep_items_max_threads(mixed) ? w : deep_items_max_threads(mixed);
+}
+
 }  // namespace
 
 Geometry deep_geometry(int C, int N, int NB, const DeviceLimits &dev)
@@ -731,6 +741,11 @@ Geometry deep_geometry(int C, int N, int NB, const DeviceLimits &dev)
     g.lanes = (long long)C * NB;
     g.lds = back_lds(NB, g.CH);
     g.scratch = deep_scratch_doubles(C, N, NB, S) * sizeof(double);
+    // the items kernel's LDS (largest with one bin per lane) within the device's
+    for (int mixed = 0; mixed < 2; ++mixed) {
+        const int wi = items_threads(Ls, NB, NB, mixed != 0);
+        if (items_lds(NB, NB, wi / NB, mixed != 0).total > dev.lds) return Geometry{};
+    }
     return g;
 }
 
@@ -754,9 +769,7 @@ hipError_t launch_deep(const SolveArgs &a, const Geometry &g, int precision, hip
     b.L = g.lanes;
     const bool mixed = precision == 1;
     const int NB = a.NB, NBR = a.NB / a.NG;
-    // items: (Ls + 1) levels x NB lanes per segment, as many per pass as the workgroup holds
-    const int wi = std::min(deep_items_max_threads(mixed),
-                            std::max(g.threads, ((g.PC + 1) * std::max(NB, NBR + 1) + 63) / 64 * 64));
+    const int wi = items_threads(g.PC, NB, NBR, mixed);
     const size_t lds_items = items_lds(NB, NBR, wi / NB, mixed).total;
     int Sp = 1;
     while (Sp < g.K) Sp <<= 1;

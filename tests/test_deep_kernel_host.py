@@ -86,6 +86,15 @@ def test_kdist_bins():
         check(w, mixed, 32)
 
 
+def test_most_lanes_per_column():
+    """256 bins x 3 Gaussian points = 768 lanes, the most a column may hold:
+    the per-lane kernels at their workgroup bound, one item per pass."""
+    w = synth.make_kdist(synth.Spec(name="k", g_level=3, n_layers=9, n_bins=256, cloud="night",
+                                    seed=93), n_cols=1, n_gauss=3)
+    g = check(w, False, 256)
+    assert g["threads"] == 768
+
+
 def test_modes_and_edges():
     from tests.test_gpu_parity import edge_workload
     w = edge_workload()
