@@ -62,7 +62,12 @@ __host__ __device__ __forceinline__ R poly_eo(R y)
     }
 }
 
-// sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain
+// sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain.  On the device in
+// FP64 each step is a three-operand v_fma_f64 with the coefficient in a
+// register pair: written as fma() with a literal coefficient it compiles to a
+// 64-bit copy of the coefficient into the accumulator and the two-operand
+// v_fmac_f64 (one extra move per step; 3 % of the FP64 solve at 2562 columns
+// x 40 layers x 30 bins).  Same operation, same rounding.
 template <class R, class C, int J, int N>
 __host__ __device__ __forceinline__ R horner_y(R y)
 {
@@ -70,6 +75,15 @@ __host__ __device__ __forceinline__ R horner_y(R y)
     if constexpr (J + 1 >= N) {
         return R(cj);
     } else {
+#if defined(__HIP_DEVICE_COMPILE__)
+        if constexpr (sizeof(R) == 8) {
+            const R p = horner_y<R, C, J + 1, N>(y);
+            const R c = R(cj);
+            R out;
+            asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(y), "v"(c));
+            return out;
+        }
+#endif
         return fma(horner_y<R, C, J + 1, N>(y), y, R(cj));
     }
 }
