@@ -806,7 +806,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         // Back-substitution on a padded layout: thread kk NBp + b takes lane
         // (kk, b), NBp the power of two >= NB, so a column's lanes share a
         // wavefront and the bin sums of each level are wavefront sums
-        // (seg_sum) with no barrier.  Each lane keeps the records of its next 8
+        // (seg_sum2) with no barrier.  Each lane keeps the records of its next 8
         // layers in registers (slot k: the layer below interface i0 + k),
         // loaded 8 steps ahead of their use; the loads are unconditional (layer
         // index clamped, a valid lane for the padding) so no slot waits for
@@ -824,7 +824,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         Fu = yact ? s_x[yl] : 0.0;
         Fd = yact ? s_x[T + yl] : 0.0;
         const double wgt = yact ? s_wl[yb] : 0.0;   // bin-sum weight (0 on padding lanes)
-        // the lane of a column segment that holds its sums (seg_sum) and writes them
+        // the lane of a column segment that holds its sums (seg_sum2) and writes them
         const int ol = NBp <= 16 ? 0 : (NBp == 32 ? 16 : 48);
         const bool outc = yslot && yb == ol && c0 + yk < C;
         // only the wavefronts that hold back-substitution lanes run the steps
@@ -843,27 +843,47 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
 #pragma unroll
             for (int k = 1; k < 8; ++k) ld(k - 1, k);
             rG[0] = rH[0] = rc[0] = rd[0] = 0.0;
-            for (int i0 = 0; i0 <= N; i0 += 8) {
+            // The steps of every level.  NBW: the group width NBp of the bin
+            // sums as a compile-time constant (no branches between the DPP
+            // steps, so the sums of F_up and F_dn interleave), or 0 for the
+            // run-time width.  The mixed kernel keeps the run-time width: its
+            // four fixed-width copies of the loop overflow its 128 VGPRs.
+            auto levels = [&](auto NBW) {
+                constexpr int NW = decltype(NBW)::value;
+                for (int i0 = 0; i0 <= N; i0 += 8) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int i = i0 + k;
-                    if (i > N) break;
-                    if (yact && i > 0) back_step(rG[k], rH[k], rc[k], rd[k], Fu, Fd);
-                    ld(i + 7, k);   // the layer below interface i + 8
-                    if (yact) {
-                        const long long o = (long long)i * LB + toff + yl;
-                        if (a.F_up_bin) a.F_up_bin[o] = Fu;
-                        if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
-                        if (i == N && a.F_up_toa_bin) {
-                            if (NG == 1) a.F_up_toa_bin[toff + yl] = Fu;
-                            else s_part[yl] = Fu;   // TOA spectrum, below
+                    for (int k = 0; k < 8; ++k) {
+                        const int i = i0 + k;
+                        if (i > N) break;
+                        if (yact && i > 0) back_step(rG[k], rH[k], rc[k], rd[k], Fu, Fd);
+                        ld(i + 7, k);   // the layer below interface i + 8
+                        if (yact) {
+                            const long long o = (long long)i * LB + toff + yl;
+                            if (a.F_up_bin) a.F_up_bin[o] = Fu;
+                            if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
+                            if (i == N && a.F_up_toa_bin) {
+                                if (NG == 1) a.F_up_toa_bin[toff + yl] = Fu;
+                                else s_part[yl] = Fu;   // TOA spectrum, below
+                            }
+                        }
+                        double su = wgt * Fu, sd = wgt * Fd;
+                        if constexpr (NW == 0) seg_sum2(su, sd, NBp);
+                        else seg_sum2<NW>(su, sd);
+                        if (outc) {
+                            *out_at(a.F_up, a.F_up_c, i, c0 + yk) = su;
+                            *out_at(a.F_dn, a.F_dn_c, i, c0 + yk) = sd;
                         }
                     }
-                    const double su = seg_sum(wgt * Fu, NBp), sd = seg_sum(wgt * Fd, NBp);
-                    if (outc) {
-                        *out_at(a.F_up, a.F_up_c, i, c0 + yk) = su;
-                        *out_at(a.F_dn, a.F_dn_c, i, c0 + yk) = sd;
-                    }
+                }
+            };
+            if (MIXED) {
+                levels(std::integral_constant<int, 0>{});
+            } else {
+                switch (NBp) {   // 8..64 (layer_wsum)
+                case 8: levels(std::integral_constant<int, 8>{}); break;
+                case 16: levels(std::integral_constant<int, 16>{}); break;
+                case 32: levels(std::integral_constant<int, 32>{}); break;
+                default: levels(std::integral_constant<int, 64>{}); break;
                 }
             }
         }

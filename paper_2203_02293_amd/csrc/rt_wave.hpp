@@ -38,4 +38,56 @@ __device__ __forceinline__ double seg_sum(double v, int width)
     return v;
 }
 
+// Two sums over groups of W lanes (W a power of two, 8..64, fixed at compile
+// time: no branches between the steps), the steps of the two interleaved.  Each
+// is the same sequence of moves and additions as seg_sum(v, W), so the sums are
+// bitwise those of seg_sum.
+template <int W>
+__device__ __forceinline__ void seg_sum2(double &u, double &v)
+{
+    static_assert(W >= 8 && W <= 64 && (W & (W - 1)) == 0, "group width");
+    u += dpp_move<0xB1>(u);
+    v += dpp_move<0xB1>(v);
+    u += dpp_move<0x4E>(u);
+    v += dpp_move<0x4E>(v);
+    u += dpp_move<0x141>(u);
+    v += dpp_move<0x141>(v);
+    if constexpr (W > 8) {
+        u += dpp_move<0x140>(u);
+        v += dpp_move<0x140>(v);
+    }
+    if constexpr (W > 16) {
+        u += dpp_rows<0x142, 0xA>(u);
+        v += dpp_rows<0x142, 0xA>(v);
+    }
+    if constexpr (W > 32) {
+        u += dpp_rows<0x143, 0xC>(u);
+        v += dpp_rows<0x143, 0xC>(v);
+    }
+}
+
+// The same with the width (8..64) known only at run time: branches between
+// the steps.
+__device__ __forceinline__ void seg_sum2(double &u, double &v, int width)
+{
+    u += dpp_move<0xB1>(u);
+    v += dpp_move<0xB1>(v);
+    u += dpp_move<0x4E>(u);
+    v += dpp_move<0x4E>(v);
+    u += dpp_move<0x141>(u);
+    v += dpp_move<0x141>(v);
+    if (width > 8) {
+        u += dpp_move<0x140>(u);
+        v += dpp_move<0x140>(v);
+    }
+    if (width > 16) {
+        u += dpp_rows<0x142, 0xA>(u);
+        v += dpp_rows<0x142, 0xA>(v);
+    }
+    if (width > 32) {
+        u += dpp_rows<0x143, 0xC>(u);
+        v += dpp_rows<0x143, 0xC>(v);
+    }
+}
+
 }  // namespace rtk
