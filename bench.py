@@ -135,16 +135,17 @@ def pct(v, q):
     return v[i]
 
 
-def cpu_baseline(work, seconds: float = 10.0) -> dict:
+def cpu_baseline(work, seconds: float = 10.0) -> tuple[dict, dict]:
     """The CPU oracle as it stands, timed on this host on whole solves of the
-    benchmark workload repeated for about `seconds` (all host threads)."""
+    benchmark workload repeated for about `seconds` (all host threads).
+    Returns the timing and the oracle's outputs of the last solve."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     run = oracle.solve_sublayer if work.get("sublayer") else oracle.solve
     run(work, n_threads=threads, cols=(0, 64))   # load and warm
     reps, t0 = 0, time.perf_counter()
     while True:
-        run(work, n_threads=threads)
+        ref = run(work, n_threads=threads)
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
@@ -152,10 +153,28 @@ def cpu_baseline(work, seconds: float = 10.0) -> dict:
     nbg = work["n_bins"] * work.get("n_gauss", 1)
     cb = work["n_cols"] * nbg * reps
     shape = f"{work['n_cols']}x{work['n_layers']}x{nbg}"
-    return {"value": cb / el, "unit": "column·bin solves/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{reps} whole FP64 solves of the {shape} workload in {el:.1f} s "
-                      f"on {threads} OpenMP threads"}
+    return ({"value": cb / el, "unit": "column·bin solves/s", "cores": threads,
+             "kind": "oracle",
+             "sample": f"{reps} whole FP64 solves of the {shape} workload in {el:.1f} s "
+                       f"on {threads} OpenMP threads"}, ref)
+
+
+def error_stats(got: dict, ref: dict, p_iface: np.ndarray, gravity: float = 47.0,
+                floor: float = 1e-3) -> dict:
+    """Errors of the bin-summed outputs against the oracle's, scaled as the parity
+    tests scale them: S = the column's largest gross flux F_up + F_dn + F_beam;
+    F_up, F_dn, F_beam by max(|ref|, floor S); F_net by S; heating Q by its flux
+    divergence Q dp / g over S.  Max, p99 and median over (interface or layer,
+    column)."""
+    S = (ref["F_up"] + ref["F_dn"] + ref["F_beam"]).max(axis=0)
+    e = {}
+    for k in ("F_up", "F_dn", "F_beam"):
+        e[k] = np.abs(got[k] - ref[k]) / np.maximum(np.abs(ref[k]), floor * S)
+    e["F_net"] = np.abs(got["F_net"] - ref["F_net"]) / S
+    dp = (p_iface[:-1] - p_iface[1:])
+    e["heating"] = np.abs(got["heating"] - ref["heating"]) * dp / gravity / S
+    return {k: {"max": float(v.max()), "p99": float(np.percentile(v, 99)),
+                "median": float(np.median(v))} for k, v in e.items()}
 
 
 def serving(args, torch, rt, synth) -> dict:
@@ -301,6 +320,8 @@ def main():
     kname, kname_m = KERNEL_NAMES[used] + "<false>", KERNEL_NAMES[used_m] + "<true>"
     wall, tot, per = time_path(s, inp, out, rt.RT_FP64, args.steps, args.warmup, torch, kernel,
                                pre)
+    summed = ("F_up", "F_dn", "F_beam", "F_net", "heating")
+    host = {"fp64": {k: out[k].cpu().numpy() for k in summed}}   # the last timed solve
     ms = tot / args.steps
     value = C * NB / (ms * 1e-3)
     abytes = algorithmic_bytes(C, N, NB)
@@ -327,6 +348,7 @@ def main():
         wall_m, tot_m, per_m = time_path(s, inp, out, rt.RT_MIXED, args.steps, args.warmup,
                                          torch, kernel, pre)
         ms_m = tot_m / args.steps
+        host["mixed"] = {k: out[k].cpu().numpy() for k in summed}
         ach_m = abytes / (ms_m * 1e-3) / 1e9
         line["mixed"] = {"value": C * NB / (ms_m * 1e-3), "ms_per_step": ms_m,
                          "speedup_vs_fp64": ms / ms_m,
@@ -352,7 +374,13 @@ def main():
         line["serving"] = serving(args, torch, rt, synth)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)
+        line["cpu_baseline"], ref = cpu_baseline(work, args.cpu_seconds)
+        if not work.get("sublayer"):
+            # the timed solves' errors against the oracle's result
+            line["error_vs_oracle"] = {
+                "scale": "bin sums; F_up, F_dn, F_beam over max(|ref|, 1e-3 S), F_net over S, "
+                         "heating as Q dp/g over S; S = the column's largest gross flux",
+                **{tag: error_stats(h, ref, work["p_iface"]) for tag, h in host.items()}}
     print(json.dumps(line), flush=True)
 
 
