@@ -806,9 +806,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         // Back-substitution on a padded layout: thread kk NBp + b takes lane
         // (kk, b), NBp the power of two >= NB, so a column's lanes share a
         // wavefront and the bin sums of each level are wavefront sums
-        // (seg_sum2) with no barrier.  Each lane keeps the records of its next 8
+        // (seg_sum2) with no barrier.  Each lane keeps the records of its next RD
         // layers in registers (slot k: the layer below interface i0 + k),
-        // loaded 8 steps ahead of their use; the loads are unconditional (layer
+        // loaded RD steps ahead of their use; the loads are unconditional (layer
         // index clamped, a valid lane for the padding) so no slot waits for
         // its load before it is used.  The level-0 fluxes move to the padded
         // layout through LDS; F_net follows in the pass after.
@@ -831,7 +831,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (wave_uniform(tid >> 6) * 64 < K * NBp) {
             const double2 *rp = reinterpret_cast<const double2 *>(a.scratch) +
                                 ((long long)tile * T + (yact ? yl : 0)) * 2;
-            double rG[8], rH[8], rc[8], rd[8];
+            // records in flight per lane: 8 in FP64; 4 in the mixed kernel, whose
+            // 128 VGPRs then hold the fixed-width sums of 32-lane groups below
+            constexpr int RD = MIXED ? 4 : 8;
+            double rG[RD], rH[RD], rc[RD], rd[RD];
             auto ld = [&](int j, int k) {
                 const double2 *q = rp + (long long)min(j, N - 1) * 2 * L;
                 const double2 x = q[0], y = q[1];
@@ -841,22 +844,23 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 rd[k] = y.y;
             };
 #pragma unroll
-            for (int k = 1; k < 8; ++k) ld(k - 1, k);
+            for (int k = 1; k < RD; ++k) ld(k - 1, k);
             rG[0] = rH[0] = rc[0] = rd[0] = 0.0;
             // The steps of every level.  NBW: the group width NBp of the bin
             // sums as a compile-time constant (no branches between the DPP
             // steps, so the sums of F_up and F_dn interleave), or 0 for the
-            // run-time width.  The mixed kernel keeps the run-time width: its
-            // four fixed-width copies of the loop overflow its 128 VGPRs.
+            // run-time width.  The mixed kernel fixes only the width 32 (the
+            // 30-bin grids): four fixed-width copies of the loop overflow its
+            // 128 VGPRs.
             auto levels = [&](auto NBW) {
                 constexpr int NW = decltype(NBW)::value;
-                for (int i0 = 0; i0 <= N; i0 += 8) {
+                for (int i0 = 0; i0 <= N; i0 += RD) {
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
+                    for (int k = 0; k < RD; ++k) {
                         const int i = i0 + k;
                         if (i > N) break;
                         if (yact && i > 0) back_step(rG[k], rH[k], rc[k], rd[k], Fu, Fd);
-                        ld(i + 7, k);   // the layer below interface i + 8
+                        ld(i + RD - 1, k);   // the layer below interface i + RD
                         if (yact) {
                             const long long o = (long long)i * LB + toff + yl;
                             if (a.F_up_bin) a.F_up_bin[o] = Fu;
@@ -877,7 +881,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 }
             };
             if (MIXED) {
-                levels(std::integral_constant<int, 0>{});
+                if (NBp == 32) levels(std::integral_constant<int, 32>{});
+                else levels(std::integral_constant<int, 0>{});
             } else {
                 switch (NBp) {   // 8..64 (layer_wsum)
                 case 8: levels(std::integral_constant<int, 8>{}); break;
