@@ -159,6 +159,18 @@ def cpu_baseline(work, seconds: float = 10.0) -> tuple[dict, dict]:
                        f"on {threads} OpenMP threads"}, ref)
 
 
+def column_subset(work: dict, cols: np.ndarray) -> dict:
+    """The workload restricted to some columns (columns are independent)."""
+    w = dict(work, n_cols=int(cols.size))
+    for k in ("p_iface", "T_iface"):
+        w[k] = np.ascontiguousarray(work[k][:, cols])
+    for k in ("dtau", "w0", "g0"):
+        w[k] = np.ascontiguousarray(work[k][:, cols, :])
+    for k in ("mu_star", "T_int"):
+        w[k] = np.ascontiguousarray(work[k][cols])
+    return w
+
+
 def error_stats(got: dict, ref: dict, p_iface: np.ndarray, gravity: float = 47.0,
                 floor: float = 1e-3) -> dict:
     """Errors of the bin-summed outputs against the oracle's, scaled as the parity
@@ -375,12 +387,23 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(work, args.cpu_seconds)
-        if not work.get("sublayer"):
-            # the timed solves' errors against the oracle's result
+        if not work.get("sublayer") and work.get("n_gauss", 1) == 1:
+            # the timed solves' errors against the oracle's result (all columns), and
+            # against its binary128 build on every 10th column (the FP64 oracle's own
+            # rounding reaches ~1e-10 of the gross flux at this shape)
+            import oracle
+            cols = np.arange(0, C, 10)
+            wq = column_subset(work, cols)
+            threads = line["cpu_baseline"]["cores"]
+            refq = oracle.solve(wq, n_threads=threads, extended=True)
             line["error_vs_oracle"] = {
                 "scale": "bin sums; F_up, F_dn, F_beam over max(|ref|, 1e-3 S), F_net over S, "
                          "heating as Q dp/g over S; S = the column's largest gross flux",
-                **{tag: error_stats(h, ref, work["p_iface"]) for tag, h in host.items()}}
+                "fp64_oracle_all_columns": {tag: error_stats(h, ref, work["p_iface"])
+                                            for tag, h in host.items()},
+                f"binary128_oracle_{cols.size}_columns": {
+                    tag: error_stats({k: v[:, cols] for k, v in h.items()}, refq, wq["p_iface"])
+                    for tag, h in host.items()}}
     print(json.dumps(line), flush=True)
 
 

@@ -33,3 +33,13 @@ def test_error_stats_scaling():
     got["heating"][2, 7] += 1e-6 * S[7] * 47.0 / dp
     e = bench.error_stats(got, ref, w["p_iface"])
     assert abs(e["heating"]["max"] - 1e-6) < 1e-12
+
+
+def test_column_subset_matches_whole_solve():
+    import oracle
+    w = synth.make("cfg0")
+    cols = np.arange(0, w["n_cols"], 10)
+    whole = oracle.solve(w)
+    part = oracle.solve(bench.column_subset(w, cols))
+    for k in ("F_up", "F_dn", "F_net", "heating"):
+        np.testing.assert_array_equal(part[k], whole[k][:, cols])
