@@ -766,12 +766,28 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const R *rb0 = rbuf(m);
             const uint32_t *fb0 = fbuf(m);
             const size_t ps = (size_t)PC * T;
+            // the LDS record of layer q + 1 is read while layer q is eliminated
+            // (the last read repeats layer n - 1 and is unused)
+            const R *rp0 = rb0 + tid;
+            R x0 = rp0[0], x1 = rp0[ps], x2 = rp0[2 * ps], x3 = rp0[3 * ps], x4 = rp0[4 * ps],
+              x5 = rp0[5 * ps];
+            uint32_t xf = fb0[tid];
             for (int q = 0; q < n; ++q) {
-                const R *rp = rb0 + (size_t)q * T + tid;
-                fl |= fb0[q * T + tid];
-                const BackRec rec = elim_step(st, double(rp[0]), double(rp[ps]), double(rp[2 * ps]),
-                                              double(rp[3 * ps]), double(rp[4 * ps]),
-                                              double(rp[5 * ps]));
+                const int qn = min(q + 1, n - 1);
+                const R *rp = rb0 + (size_t)qn * T + tid;
+                const R y0 = rp[0], y1 = rp[ps], y2 = rp[2 * ps], y3 = rp[3 * ps], y4 = rp[4 * ps],
+                        y5 = rp[5 * ps];
+                const uint32_t yf = fb0[qn * T + tid];
+                fl |= xf;
+                const BackRec rec = elim_step(st, double(x0), double(x1), double(x2), double(x3),
+                                              double(x4), double(x5));
+                x0 = y0;
+                x1 = y1;
+                x2 = y2;
+                x3 = y3;
+                x4 = y4;
+                x5 = y5;
+                xf = yf;
                 double2 *sp = reinterpret_cast<double2 *>(a.scratch) + ((long long)(s - 1 - q) * L + gl) * 2;
                 sp[0] = make_double2(rec.G, rec.H);
                 sp[1] = make_double2(rec.c, rec.d);
