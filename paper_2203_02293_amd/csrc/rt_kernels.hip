@@ -1152,6 +1152,9 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
         }
     }
     if (best < 0.0) return Geometry{};
+    // a multiple of four wavefronts, so that every SIMD of the compute unit
+    // holds as many (the extra threads take no items, only edge integrals)
+    g.threads = std::min(wmax, (g.threads + 255) / 256 * 256);
     // interfaces per back-substitution pass: as many as fit in the forward
     // sweep's bytes and in the threads' staging registers
     // (none with wavefront bin sums, which stage no records in LDS)
