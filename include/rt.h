@@ -135,7 +135,10 @@ rt_status rt_destroy(rt_handle *h);
  *   F_up_bin, F_dn_bin [N+1][C][NB] per-bin fluxes, or NULL
  *   flags             [C]        RT_FLAG_* bits per column, or NULL
  * Values outside their domain do not stop the solve: the column's outputs are
- * then unspecified and its flags carry RT_FLAG_INVALID.
+ * then unspecified and its flags carry RT_FLAG_INVALID.  On the stream path
+ * (rt_solve_fluxes) such conditions are reported in flags only: the call
+ * returns before the kernels run.  The serving path (rt_submit) also turns
+ * them into the request's status (rt_poll/rt_wait).
  *
  * Sub-layer grid (non-isothermal layers split at their centres, Section 2.2.1
  * and the grid figure): set T_center (and p_center).  Each layer j is then two
@@ -205,14 +208,22 @@ int32_t rt_request_kernel(rt_handle *h, const rt_request *req);
  * on the caller's), and the request's buffers must stay valid, and must not be
  * touched, until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:
  * RT_EINVAL (bad request), RT_EBUSY (max_inflight reached), RT_ENOMEM (the
- * request alone exceeds the memory budget).
+ * request alone exceeds the memory budget, or the budget's device memory
+ * could not be allocated; the handle stays usable).
  */
 rt_status rt_submit(rt_handle *h, const rt_request *req, uint64_t *ticket);
 
-/* Non-blocking: RT_PENDING, RT_OK (done, ticket retired) or an error status. */
+/*
+ * Non-blocking: RT_PENDING while the request is queued or running; once it
+ * has finished (the ticket then retires): RT_OK, or RT_EDOMAIN if a column
+ * met E <= w0 in strict mode (e_clamp = 0, Section 2.2.4), else RT_EINVAL if
+ * an input value was outside its domain (the columns' flags say which), or
+ * RT_EDEVICE if its launch failed.  The outputs are written in every case.
+ * RT_ENOTFOUND for an unknown or retired ticket.
+ */
 rt_status rt_poll(rt_handle *h, uint64_t ticket);
 
-/* Blocking variant of rt_poll. */
+/* Blocking variant of rt_poll (same results). */
 rt_status rt_wait(rt_handle *h, uint64_t ticket);
 
 /*

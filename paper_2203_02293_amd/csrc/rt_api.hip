@@ -97,6 +97,8 @@ struct Batch {
     int *h_first = nullptr;
     rtk::SolveArgs *d_args = nullptr;   // device copy read by the kernel
     int *d_first = nullptr;
+    uint32_t *d_status = nullptr;       // per request: condition bits that fail it
+    uint32_t *h_status = nullptr;       // pinned copy, read once the batch is done
     hipEvent_t done = nullptr;
     int stream = 0;
 };
@@ -305,8 +307,10 @@ extern "C" rt_status rt_destroy(rt_handle *h)
         if (b.done) (void)hipEventDestroy(b.done);
         if (b.h_args) (void)hipHostFree(b.h_args);
         if (b.h_first) (void)hipHostFree(b.h_first);
+        if (b.h_status) (void)hipHostFree(b.h_status);
         (void)hipFree(b.d_args);
         (void)hipFree(b.d_first);
+        (void)hipFree(b.d_status);
     }
     for (auto &s : h->streams)
         if (s) (void)hipStreamDestroy(s);
@@ -591,6 +595,8 @@ static rt_status ensure_serving(rt_handle *h)
             hipHostMalloc((void **)&b.h_first, sizeof(int) * kMaxBatch) != hipSuccess ||
             hipMalloc(&b.d_args, sizeof(rtk::SolveArgs) * kMaxBatch) != hipSuccess ||
             hipMalloc(&b.d_first, sizeof(int) * kMaxBatch) != hipSuccess ||
+            hipHostMalloc((void **)&b.h_status, sizeof(uint32_t) * kMaxBatch) != hipSuccess ||
+            hipMalloc(&b.d_status, sizeof(uint32_t) * kMaxBatch) != hipSuccess ||
             hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
             return fail(h, RT_ENOMEM, "serving descriptor buffers");
         b.stream = i % kStreams;
@@ -604,6 +610,19 @@ static rt_status ensure_serving(rt_handle *h)
     return RT_OK;
 }
 
+// Status of a finished request from the condition bits its columns raised:
+// strict-mode E <= w0 (RT_EDOMAIN) before out-of-domain inputs (RT_EINVAL).
+static rt_status request_status(rt_handle *h, const Job &j, uint32_t bits)
+{
+    if (bits & RT_FLAG_EDOMAIN)
+        return fail(h, RT_EDOMAIN, "ticket %llu: E <= w0 in strict mode (see flags)",
+                    (unsigned long long)j.ticket);
+    if (bits & RT_FLAG_INVALID)
+        return fail(h, RT_EINVAL, "ticket %llu: input values outside their domain (see flags)",
+                    (unsigned long long)j.ticket);
+    return RT_OK;
+}
+
 // Retire finished batches, then admit queued requests: in arrival order, by
 // device-memory footprint, grouped by (precision, tile) into batched launches.
 static void pump(rt_handle *h)
@@ -613,11 +632,11 @@ static void pump(rt_handle *h)
         if (!b.busy) continue;
         hipError_t q = hipEventQuery(b.done);
         if (q == hipErrorNotReady) continue;
-        rt_status st = (q == hipSuccess) ? RT_OK : RT_EDEVICE;
-        for (const Job &j : b.jobs) {
+        for (size_t k = 0; k < b.jobs.size(); ++k) {
+            const Job &j = b.jobs[k];
             h->arena.release(j.off, j.bytes);
             h->running.erase(j.ticket);
-            h->finished[j.ticket] = st;
+            h->finished[j.ticket] = q != hipSuccess ? RT_EDEVICE : request_status(h, j, b.h_status[k]);
         }
         b.jobs.clear();
         b.busy = false;
@@ -638,8 +657,12 @@ static void pump(rt_handle *h)
             if (!h->arena.alloc(j.bytes, &off)) return;   // head request waits for memory
             j.off = off;
             h->queued.pop_front();
-            const rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
-            hipError_t e = rtk::launch_deep(a, j.g, prec, s);
+            rtk::SolveArgs a = make_args(h, &j.req, (double *)(h->arena.base + off));
+            a.status = b.d_status;
+            hipError_t e = hipMemsetAsync(b.d_status, 0, sizeof(uint32_t), s);
+            if (e == hipSuccess) e = rtk::launch_deep(a, j.g, prec, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b.h_status, b.d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipEventRecord(b.done, s);
             if (e != hipSuccess) {
                 hip_fail(h, e, "serving launch");
@@ -670,6 +693,7 @@ static void pump(rt_handle *h)
             a.PC = j.g.PC;
             a.CH = j.g.CH;
             a.L = j.g.lanes;
+            a.status = b.d_status + b.jobs.size();
             b.h_args[b.jobs.size()] = a;
             b.h_first[b.jobs.size()] = blocks;
             blocks += j.g.blocks;
@@ -682,8 +706,11 @@ static void pump(rt_handle *h)
                                       hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b.d_first, b.h_first, sizeof(int) * n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(b.d_status, 0, sizeof(uint32_t) * n, s);
         if (e == hipSuccess)
             e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, g0, prec, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.h_status, b.d_status, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipEventRecord(b.done, s);
         if (e != hipSuccess) {
             hip_fail(h, e, "serving launch");

@@ -172,6 +172,7 @@ __host__ __device__ inline size_t back_lds(int NB, int CH)
 __device__ __forceinline__ void flags_out(const SolveArgs &a, int c, const uint32_t *s_flag)
 {
     if (threadIdx.x == 0 && a.flags && *s_flag) atomicOr(&a.flags[c], *s_flag);
+    if (threadIdx.x == 0 && a.status && status_bits(*s_flag)) atomicOr(a.status, status_bits(*s_flag));
 }
 
 // Sum of p[k * stride] for k = 0 .. n-1 in that order, the loads issued in
@@ -261,16 +262,14 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         if constexpr (MIXED) {
             const R iT = rcp(Tr);
             const R xb = a.c2_over_lam_f[rb] * iT, xa = a.c2_over_lam_f[rb + 1] * iT;
-            if (planck_narrow(xa, xb)) I = planck_gl3<R>(xa, xb);
+            if (planck_narrow(xa, xb)) {
+                const double iTd = rcp(Td);
+                I = planck_gl3(a.c2_over_lam[rb + 1] * iTd, a.c2_over_lam[rb] * iTd);
+            }
         }
         return R(kPref) * T2 * T2 * I;
     };
-    auto edge_val = [&](int e, double Tv) -> R {
-        R x;
-        if constexpr (MIXED) x = a.c2_over_lam_f[e] * rcp(float(Tv));
-        else x = a.c2_over_lam[e] * rcp(Tv);
-        return planck_edge<R>(x);
-    };
+    auto edge_val = [&](int e, double Tv) -> R { return planck_edge<R>(a.c2_over_lam[e] * rcp(Tv)); };
     const bool boa = bot == 0;
 
     for (int q0 = 0; q0 < nlev; q0 += QL) {
@@ -703,6 +702,7 @@ __global__ void __launch_bounds__(kFinalThreads) k_deep_final(const SolveArgs a)
         bad = bad || !(p0 > pm && pm > p1);
     }
     if (bad && a.flags) atomicOr(&a.flags[c], (uint32_t)F_INVALID);
+    if (bad && a.status) atomicOr(a.status, (uint32_t)F_INVALID);
     const double qh = a.o.gravity * (a.F_net[o] - a.F_net[o + C]) / dp;
     a.heat[o] = qh;
     if (a.dTdt) a.dTdt[o] = qh / a.o.cp;

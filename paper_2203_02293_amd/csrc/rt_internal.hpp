@@ -40,6 +40,9 @@ struct SolveArgs {
     // outputs
     double *F_up, *F_dn, *F_beam, *F_net, *heat, *dTdt, *F_up_toa_bin, *F_up_bin, *F_dn_bin;
     uint32_t *flags;
+    // serving: the request's status word, ORed with the condition bits that
+    // fail a request (F_INVALID, F_EDOMAIN) of any column, or NULL
+    uint32_t *status;
     // sub-layer grid: centre temperature/pressure [N/2][C], centre outputs [N/2][C]
     const double *Tc, *pc;
     double *F_up_c, *F_dn_c, *F_beam_c, *F_net_c;

@@ -94,10 +94,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
             R v = R(0);
             if (cc < C) {
                 const double T = Tsrc[off0 - q * stride + cc];
-                R x;
-                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(T));
-                else x = a.c2_over_lam[ee] / T;
-                v = planck_edge<R>(x);
+                v = planck_edge<R>(a.c2_over_lam[ee] / T);
             }
             s_pl[(q * K + kk) * (NB + 1) + ee] = v;
         }
@@ -111,7 +108,10 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
         if constexpr (MIXED) {
             const R iT = rcp(T);
             const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
-            if (planck_narrow(xa, xb)) I = planck_gl3<R>(xa, xb);
+            if (planck_narrow(xa, xb)) {
+                const double iTd = rcp(Td);
+                I = planck_gl3(a.c2_over_lam[b + 1] * iTd, a.c2_over_lam[b] * iTd);
+            }
         }
         return R(kPref) * T2 * T2 * I;
     };
@@ -181,7 +181,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
                     tau += dt;   // summed from the TOA, as the optical depth is defined
                     Fb_lo = beam_at<MIXED>(muF, tau, inv_mu);
                 }
-                const Layer<R> Ly = layer_item<MIXED, R>(dt, w, g, day, mu, inv_mu, Fb_up, Fb_lo, B,
+                const Layer<R> Ly = layer_item<MIXED, R, MIXED>(dt, w, g, day, mu, inv_mu, Fb_up, Fb_lo, B,
                                                          Bup, a.o, inv_eps2, fl);
                 const BackRec rec = elim_step(st, double(Ly.t), double(Ly.r), double(Ly.omr),
                                               double(Ly.A), double(Ly.Sup), double(Ly.Sdn));
@@ -281,7 +281,10 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
     __syncthreads();
     for (int kk = tid; kk < K; kk += bd) {
         const int cc = tile * K + kk;
-        if (cc < C && a.flags) a.flags[cc] = s_flag[kk];
+        if (cc >= C) continue;
+        if (a.flags) a.flags[cc] = s_flag[kk];
+        const uint32_t bad = status_bits(s_flag[kk]);
+        if (a.status && bad) atomicOr(a.status, bad);
     }
 }
 
@@ -475,11 +478,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
-                const double Tv = Ts[q * K + kk];
-                R x;
-                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Tv));
-                else x = a.c2_over_lam[ee] * rcp(Tv);
-                v = planck_edge<R>(x);
+                v = planck_edge<R>(a.c2_over_lam[ee] * rcp(Ts[q * K + kk]));
             }
             s_edge[(q * K + kk) * (NBR + 1) + ee] = v;
         }
@@ -493,7 +492,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if constexpr (MIXED) {
             const R iT = rcp(Tr);
             const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
-            if (planck_narrow(xa, xb)) I = planck_gl3<R>(xa, xb);
+            if (planck_narrow(xa, xb)) {
+                const double iTd = rcp(Td);
+                I = planck_gl3(a.c2_over_lam[b + 1] * iTd, a.c2_over_lam[b] * iTd);
+            }
         }
         return R(kPref) * T2 * T2 * I;
     };
@@ -616,7 +618,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         Layer<R> Ly{};
         if (icol[0]) {
             const double mu = s_mu[kk];
-            Ly = layer_item<MIXED, R>(dbuf(m)[q * T + l], w, g, mu > 0.0, mu, s_mu[K + kk],
+            Ly = layer_item<MIXED, R, MIXED>(dbuf(m)[q * T + l], w, g, mu > 0.0, mu, s_mu[K + kk],
                                       cF[q * T + l], cF[(q + 1) * T + l], cB[(q + 1) * T + l],
                                       cB[q * T + l], a.o, inv_eps2, f);
         }
@@ -719,10 +721,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             }
             R v = R(0);
             if (c0 + kk < C) {
-                R x;
-                if constexpr (MIXED) x = a.c2_over_lam_f[ee] * rcp(float(Ts[kk]));
-                else x = a.c2_over_lam[ee] * rcp(Ts[kk]);
-                v = planck_edge<R>(x);
+                v = planck_edge<R>(a.c2_over_lam[ee] * rcp(Ts[kk]));
             }
             dst[kk * (NBR + 1) + ee] = v;
         }
@@ -1054,7 +1053,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     __syncthreads();
     for (int kk = tid; kk < K; kk += W) {
         const int cc = c0 + kk;
-        if (cc < C && a.flags) a.flags[cc] = s_flag[kk];
+        if (cc >= C) continue;
+        if (a.flags) a.flags[cc] = s_flag[kk];
+        const uint32_t bad = status_bits(s_flag[kk]);
+        if (a.status && bad) atomicOr(a.status, bad);
     }
 }
 

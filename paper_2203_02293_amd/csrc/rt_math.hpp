@@ -1,6 +1,6 @@
 // rt_math.hpp -- small math kernels of the solve, host- and device-callable.
 //
-// exp_em1(x): e^x and e^x - 1 from one argument reduction (Cody-Waite
+// exp_em1(x), FP64: e^x and e^x - 1 from one argument reduction (Cody-Waite
 // reduction x = k ln2 + r with |r| <= ln2/2, Taylor polynomial of e^r - 1,
 // scaling by 2^k; Tang, ACM TOMS 15 (1989) describes the same structure).
 // The expm1 value keeps full relative accuracy near x = 0 because the
@@ -129,6 +129,53 @@ __host__ __device__ __forceinline__ ExpEm1<R> exp_em1(R x)
     out.e = ldexp(R(1) + q, ki);
     out.em1 = ldexp(q, ki) + (ldexp(R(1), ki) - R(1));
     return out;
+}
+
+// FP32: 2^(x log2 e) from the hardware base-2 exponential (within one ulp),
+// with the rounding error of the product x log2 e (an FMA residual plus the
+// low part of log2 e) applied as the first-order factor 1 + err ln 2.
+// e^x - 1: for |x| < 1/2 the Taylor polynomial x (1 + x/2 + ... + x^7/8!)
+// (next term below 6e-9 of x), else e^x - 1 itself, which is then at least
+// 0.39 in magnitude (a few ulp).  Arguments below -104 give 0 and -1; no
+// branches, so the lanes of a wavefront never diverge here.
+struct ExpTail8 {
+    static constexpr double coef(int j) { return inv_fact(j + 1); }
+};
+
+template <>
+__host__ __device__ __forceinline__ ExpEm1<float> exp_em1<float>(float x)
+{
+    constexpr float L = 1.44269502162933349609375f;                // log2 e rounded to FP32
+    constexpr float LLO = float(1.44269504088896340736 - 1.44269502162933349609375);
+    constexpr float LN2 = 0.693147180559945309f;
+    x = fminf(fmaxf(x, -104.0f), 88.0f);
+    const float y = x * L;
+    const float yl = fmaf(x, LLO, fmaf(x, L, -y));
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float e0 = __builtin_amdgcn_exp2f(y);
+#else
+    const float e0 = exp2f(y);
+#endif
+    ExpEm1<float> out;
+    out.e = fmaf(e0, yl * LN2, e0);
+    const float q = x * poly_eo<float, ExpTail8, 8>(x);
+    out.em1 = fabsf(x) < 0.5f ? q : out.e - 1.0f;
+    return out;
+}
+
+// e^x in FP32 for an FP64 argument: the FP32 exponential of the rounded
+// argument, times 1 + (its rounding error).  A large argument thus keeps the
+// relative accuracy of FP32 (an argument rounded to FP32 costs |x| 2^-24 of
+// e^x: 4e-6 at x = -70, a Wien-tail Planck edge of a cold column).
+__host__ __device__ __forceinline__ ExpEm1<float> exp_em1_f(double x)
+{
+    x = fmin(fmax(x, -104.0), 88.0);
+    const float xh = float(x);
+    const float xl = float(x - double(xh));
+    ExpEm1<float> e = exp_em1(xh);
+    e.em1 = fmaf(e.e, xl, e.em1);
+    e.e = fmaf(e.e, xl, e.e);
+    return e;
 }
 
 // 1/x: the hardware reciprocal (relative error below 5e-8 on gfx950) refined

@@ -29,6 +29,12 @@ enum : uint32_t {
     F_GUARD = 1u, F_ECLAMP = 2u, F_ETAU = 4u, F_EDOMAIN = 8u, F_INVALID = 16u, F_NONFIN = 32u
 };
 
+// The condition bits of a column that fail a serving request (its status).
+__host__ __device__ __forceinline__ uint32_t status_bits(uint32_t f)
+{
+    return f & (F_INVALID | F_EDOMAIN);
+}
+
 // ---------------------------------------------------------------------------
 // Planck bin integrals.  With x = c2/(lambda T):
 //   B_b(T) = (2 k^4 T^4 / (h^3 c^2)) * int_{x_a}^{x_b} t^3/(e^t - 1) dt.
@@ -123,11 +129,14 @@ __host__ __device__ __forceinline__ const SeriesTables &series_tables()
 }
 
 // +Q(x) for x <= XS, -P(x) otherwise: the sign bit records which tail it is.
+// x = c2/(lambda T) comes in FP64 in both precisions: FP32 takes e^-x from it
+// with the low part of the argument applied (exp_em1_f).
 template <class R>
-__host__ __device__ __forceinline__ R planck_edge(R x)
+__host__ __device__ __forceinline__ R planck_edge(double xd)
 {
     using Cfg = PCfg<R>;
     const SeriesTables &tb = series_tables();
+    const R x = R(xd);
     if (x <= Cfg::XS) {
         const R x2 = x * x;
         R pb;
@@ -142,20 +151,27 @@ __host__ __device__ __forceinline__ R planck_edge(R x)
     }
     if (!(x < Cfg::XCUT)) return R(-0.0);   // e^{-x} underflows (includes T = 0)
     // sum_{n>=1} y^n q_n, y = e^{-x}, q_n = x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4
-    const R y = exp_em1(-x).e;
+    R y;
+    if constexpr (sizeof(R) == 4) y = exp_em1_f(-xd).e;
+    else y = exp_em1(-x).e;
     if constexpr (sizeof(R) == 4) {
-        // FP32: Horner in y from the smallest term over a fixed number of terms
-        // (term NP+1 over term 1 is below e^{-NP XS}, under the last bit); no
-        // data-dependent exit, so the lanes of a wavefront stay together
+        // FP32: forward from the largest term, over the terms that reach the
+        // last bit: term n over term 1 is below y^(n-1) = e^-(n-1)x, under
+        // 2^-25 once (n-1) x > 17.3.  The term index is the same in every lane
+        // still summing, so the coefficients are constants; the wavefront
+        // stops when its last lane has its terms (short-wave edges: one or two)
         const R x2 = x * x, x3 = x2 * x;
-        R acc = R(0);
+        const int nt = int(R(17.3) * rcp(x)) + 1;
+        R yn = y, sum = R(0);
 #pragma unroll
-        for (int n = Cfg::NP; n >= 1; --n) {
+        for (int n = 1; n <= Cfg::NP; ++n) {
+            if (n > nt) break;
             const double in = 1.0 / n;
             const R q = fma(x3, R(in), fma(x2, R(3 * in * in), fma(x, R(6 * in * in * in), R(6 * in * in * in * in))));
-            acc = fma(acc, y, q);
+            sum = fma(yn, q, sum);
+            yn *= y;
         }
-        return -(y * acc);
+        return -sum;
     } else {
         // FP64: forward, stopping once term n+1 over term 1 (about e^{-nx}) is
         // below the last bit: few terms at the large x that most edges have
@@ -182,22 +198,23 @@ __host__ __device__ __forceinline__ R planck_combine(R vb, R va)
     return d;
 }
 
-// int_{xa}^{xb} t^3/(e^t-1) dt by 3-point Gauss-Legendre: used for narrow
-// bins in FP32, where the difference of two nearly equal edge integrals would
-// lose digits.  The rule's relative error is below (xb-xa)^6 * 5e-7.
-template <class R>
-__host__ __device__ __forceinline__ R planck_gl3(R xa, R xb)
+// int_{xa}^{xb} t^3/(e^t-1) dt by 3-point Gauss-Legendre in FP32: used for
+// narrow bins, where the difference of two nearly equal edge integrals would
+// lose digits.  The nodes are placed in FP64 and e^-x taken from them as in
+// planck_edge.  The rule's relative error is below (xb-xa)^6 * 5e-7.
+__host__ __device__ __forceinline__ float planck_gl3(double xa, double xb)
 {
-    const R h = R(0.5) * (xb - xa), m = R(0.5) * (xb + xa);
-    const R d = R(0.7745966692414834) * h;   // sqrt(3/5) h
-    R acc = R(0);
-    const R xs[3] = {m - d, m, m + d};
-    const R ws[3] = {R(5.0 / 9.0), R(8.0 / 9.0), R(5.0 / 9.0)};
+    const double h = 0.5 * (xb - xa), m = 0.5 * (xb + xa);
+    const double d = 0.7745966692414834 * h;   // sqrt(3/5) h
+    const double xs[3] = {m - d, m, m + d};
+    const float ws[3] = {float(5.0 / 9.0), float(8.0 / 9.0), float(5.0 / 9.0)};
+    float acc = 0.0f;
     for (int i = 0; i < 3; ++i) {
-        ExpEm1<R> e = exp_em1(-xs[i]);            // t^3 e^-t / (1 - e^-t)
-        acc += ws[i] * xs[i] * xs[i] * xs[i] * e.e * rcp(-e.em1);
+        const ExpEm1<float> e = exp_em1_f(-xs[i]);   // t^3 e^-t / (1 - e^-t)
+        const float xf = float(xs[i]);
+        acc += ws[i] * xf * xf * xf * e.e * rcp(-e.em1);
     }
-    return h * acc;
+    return float(h) * acc;
 }
 
 // Whether the FP32 difference of the two edge values of bin [xa, xb] would
@@ -337,6 +354,16 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
         R Qc = w0 * g0 * inv_eps2 * ik;
         R lm = lam * mu;
         R sb_up, sb_dn;
+        // beta = e^-(dtau/mu), the layer's beam transmission, and 1 - beta from
+        // one exponential (THIN: for every day layer; otherwise only near the
+        // resonance).  Then 1 - beta T = (1 - beta) + beta (1 - T) has no
+        // cancellation.
+        R beta = R(0), omB = R(0);
+        if constexpr (THIN) {
+            const ExpEm1<R> eb = exp_em1(-dtau * inv_mu);
+            beta = eb.e;
+            omB = -eb.em1;
+        }
         if (guard || fabs(lm - one) >= R(0.25)) {
             R Dd = guard ? R(-2) * mu : Dres;
             R P = c1 * rcp(Dd);
@@ -344,15 +371,15 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
             R Gm = -half * (P * (ik + mu) + Qc);
             // f [r G- - G+ (1 - t beta)] and f [r beta G+ - G- (beta - t)], f beta = Flo
             if constexpr (THIN) {
-                // 1 - t beta = (1 - T beta + zm^2 q) / den,
-                // beta - t = (beta - T + beta zm^2 q) / den, with
-                // beta - T = beta (1 - e^-(lambda-a)dtau) or T (e^-(a-lambda)dtau - 1)
-                const R a = inv_mu, zq = zm * zm * q;
-                const R beta = exp_em1(-dtau * a).e;
-                const R obt = -exp_em1(-(a + lam) * dtau).em1;
-                const R dl = (lam - a) * dtau;
-                const R em = exp_em1(-fabs(dl)).em1;
-                const R bmT = dl >= R(0) ? -beta * em : Tr * em;
+                // 1 - t beta = (1 - T beta + zm^2 q) / den and
+                // beta - t = (beta - T + beta zm^2 q) / den.  beta - T is
+                // formed as (1 - T) - (1 - beta) for a layer thin to the beam
+                // (beta >= 1/2) and directly otherwise: away from mu lambda = 1,
+                // |lambda - 1/mu| >= 1/(4 mu), so either form loses at most a
+                // factor of about 6 (under 3 bits) to cancellation
+                const R zq = zm * zm * q;
+                const R obt = omB + beta * omT;
+                const R bmT = beta < half ? beta - Tr : omT - omB;
                 sb_up = Fup * (r * Gm - Gp * (obt + zq) * id);
                 sb_dn = r * Gp * Flo - Gm * Fup * (bmT + beta * zq) * id;
             } else {
@@ -362,7 +389,11 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
         } else {
             // resonance-regularised: X, Yh = Y (a - lambda) are finite at mu lambda = 1
             R a = inv_mu;
-            R beta = exp_em1(-dtau * inv_mu).e;
+            if constexpr (!THIN) {
+                const ExpEm1<R> eb = exp_em1(-dtau * inv_mu);
+                beta = eb.e;
+                omB = -eb.em1;
+            }
             R i1s = rcp(one + s);
             R X = (Qc - c1 * ik * rcp(one + lm)) * i1s;
             R Yh = (Qc * (a - lam) - c1 * a * ik) * i1s;
@@ -370,7 +401,7 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
             R Z = Yh * dq * dtau;
             R rho = zm * rcp(zp);
             R iom = (zp * zp) * rcp(s * den);       // 1 / (1 - rho^2 T^2)
-            R obt = -exp_em1(-(a + lam) * dtau).em1; // 1 - beta T
+            R obt = omB + beta * omT;               // 1 - beta T
             sb_up = Fup * (rho * Tr * Z - X * obt) * iom;
             sb_dn = Fup * (rho * Tr * X * obt - Z) * iom;
         }
@@ -383,11 +414,11 @@ __host__ __device__ __forceinline__ void layer_terms(R dtau, R w0, R g0, R E, R 
 
 // Direct beam at an interface of optical depth tau below the TOA (Section
 // 2.2.1, Beer's law), mu = -mu_star > 0.  The mixed path takes the
-// exponential in FP32 of the FP64 optical depth.
+// exponential in FP32 of the FP64 argument tau/mu (exp_em1_f).
 template <bool MIXED>
 __host__ __device__ __forceinline__ double beam_at(double mu_Fstar, double tau, double inv_mu)
 {
-    if constexpr (MIXED) return mu_Fstar * double(exp_em1(float(-tau * inv_mu)).e);
+    if constexpr (MIXED) return mu_Fstar * double(exp_em1_f(-tau * inv_mu).e);
     else return mu_Fstar * exp_em1(-tau * inv_mu).e;
 }
 

@@ -178,6 +178,52 @@ def rt_wait(h: int, ticket: int) -> int:
 
 
 # ------------------------------------------------------------ torch plumbing
+def _shape_of(t) -> tuple:
+    return tuple(int(d) for d in t.shape)
+
+
+def check_request(inp: dict, out: dict, C: int, N: int, n_bins: int, n_gauss: int,
+                  sub: bool) -> None:
+    """Check every tensor of a request against the layouts of include/rt.h
+    (device, contiguous, dtype, shape) before anything reaches the library,
+    which reads and writes them as raw arrays of that size: a wrong dtype or a
+    short tensor would otherwise be read or written past its end.  Raises
+    ValueError."""
+    import torch
+    lanes = n_bins * n_gauss
+    S = 2 * N if sub else N
+    levels = 2 * N + 1 if sub else N + 1
+    want_in = {"p_iface": (N + 1, C), "T_iface": (N + 1, C), "dtau": (S, C, lanes),
+               "w0": (S, C, lanes), "g0": (S, C, lanes), "mu_star": (C,), "T_int": (C,),
+               "F_toa": (C, lanes), "T_center": (N, C), "p_center": (N, C)}
+    want_out = {"F_up": (N + 1, C), "F_dn": (N + 1, C), "F_beam": (N + 1, C),
+                "F_net": (N + 1, C), "heating": (N, C), "dTdt": (N, C),
+                "F_up_toa_bin": (C, n_bins), "F_up_bin": (levels, C, lanes),
+                "F_dn_bin": (levels, C, lanes), "flags": (C,), "F_up_center": (N, C),
+                "F_dn_center": (N, C), "F_beam_center": (N, C), "F_net_center": (N, C)}
+    for src, want in ((inp, want_in), (out, want_out)):
+        for k, shape in want.items():
+            t = src.get(k)
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor):
+                raise ValueError(f"{k} must be a torch tensor")
+            if k == "flags":
+                if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+                    raise ValueError(f"flags must be int32 or uint32 (got {t.dtype})")
+            elif t.dtype != torch.float64:
+                raise ValueError(f"{k} must be float64 (got {t.dtype})")
+            if _shape_of(t) != shape:
+                raise ValueError(f"{k} must have shape {shape} (got {_shape_of(t)})")
+    if sub and inp.get("p_center") is None:
+        raise ValueError("p_center is required with T_center")
+    for src, want in ((inp, want_in), (out, want_out)):
+        for k in want:
+            t = src.get(k)
+            if t is not None and (not t.is_cuda or not t.is_contiguous()):
+                raise ValueError(f"{k} must be a contiguous device tensor")
+
+
 OUT_NAMES = ("F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin", "flags")
 
 
@@ -249,18 +295,17 @@ class Solver:
         C = int(inp["mu_star"].shape[0])
         sub = inp.get("T_center") is not None
         N = int(inp["dtau"].shape[0]) // (2 if sub else 1)
+        check_request(inp, out, C, N, self.n_bins, self.n_gauss, sub)
         if cols_per_block is None and kernel is None:
-            kernel, cols_per_block = tuned_launch(self.n_bins * self.n_gauss, precision, C, N)
+            kernel, cols_per_block = tuned_launch(self.n_bins * self.n_gauss, precision, C, N,
+                                                  sublayer=sub, n_gauss=self.n_gauss)
         r = RtRequest()
         r.n_cols, r.n_layers, r.precision = C, N, precision
         r.cols_per_block = cols_per_block or 0
         r.kernel = kernel or RT_KERNEL_AUTO
 
         def ptr(t):
-            if t is None:
-                return None
-            assert t.is_cuda and t.is_contiguous(), "inputs must be contiguous device tensors"
-            return t.data_ptr()
+            return None if t is None else t.data_ptr()
         for k in ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int"):
             setattr(r, k, ptr(inp[k]))
         r.F_toa = ptr(inp.get("F_toa"))
@@ -352,11 +397,17 @@ TUNING_PATH = pathlib.Path(__file__).resolve().parent / "tuning.json"
 _tuning = None
 
 
-def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int) -> tuple[int, int]:
+def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int,
+                 sublayer: bool = False, n_gauss: int = 1) -> tuple[int, int]:
     """(kernel, tile width) chosen by the autotuner (``tune.py``) for the nearest
-    measured shape with the same bins and precision, if within a factor e in
-    columns and layers together; else (0, 0) = library defaults."""
+    measured shape with the same lanes per column and precision, if within a
+    factor e in columns and slabs together; else (0, 0) = library defaults.
+    The table holds plain requests only (one slab per layer, one point per
+    bin): a request on the sub-layer grid or with Gaussian points per bin
+    gets the library defaults, which pick a kernel that runs it."""
     global _tuning
+    if sublayer or n_gauss > 1:
+        return 0, 0
     if _tuning is None:
         import json
         _tuning = json.loads(TUNING_PATH.read_text())["entries"] if TUNING_PATH.exists() else []

@@ -33,7 +33,7 @@ class Args(ct.Structure):
     _fields_ = [(n, ct.c_int) for n in ('C', 'N', 'NB', 'K', 'PC', 'CH', 'sub', 'NG')] + \
         [(n, dp) for n in ('c2', 'c2f', 'F_star', 'wg', 'p', 'T', 'dtau', 'w0', 'g0', 'mu', 'Tint', 'Ftoa',
                            'F_up', 'F_dn', 'F_beam', 'F_net', 'heat', 'dTdt', 'F_up_toa_bin', 'F_up_bin',
-                           'F_dn_bin', 'flags', 'Tc', 'pc', 'F_up_c', 'F_dn_c', 'F_beam_c', 'F_net_c',
+                           'F_dn_bin', 'flags', 'status', 'Tc', 'pc', 'F_up_c', 'F_dn_c', 'F_beam_c', 'F_net_c',
                            'scratch')] + [('L', ct.c_longlong), ('o', Opts)]
 
 
@@ -121,6 +121,7 @@ def _args(w, opts, per_bin, scratch_ptr):
     out = {k: np.zeros((N + 1, C)) for k in ('F_up', 'F_dn', 'F_beam', 'F_net')}
     out['heating'] = np.zeros((N, C)); out['dTdt'] = np.zeros((N, C))
     out['F_up_toa_bin'] = np.zeros((C, NB)); out['flags'] = np.zeros(C, dtype=np.uint32)
+    out['status'] = np.zeros(1, dtype=np.uint32)
     if per_bin:
         out['F_up_bin'] = np.zeros((S + 1, C, NBG)); out['F_dn_bin'] = np.zeros((S + 1, C, NBG))
     if sub:
@@ -133,7 +134,7 @@ def _args(w, opts, per_bin, scratch_ptr):
              out['dTdt'].ctypes.data, out['F_up_toa_bin'].ctypes.data,
              out['F_up_bin'].ctypes.data if per_bin else None,
              out['F_dn_bin'].ctypes.data if per_bin else None, out['flags'].ctypes.data,
-             P(w.get('T_center')) if sub else None, P(w.get('p_center')) if sub else None,
+             out['status'].ctypes.data, P(w.get('T_center')) if sub else None, P(w.get('p_center')) if sub else None,
              out['F_up_center'].ctypes.data if sub else None, out['F_dn_center'].ctypes.data if sub else None,
              out['F_beam_center'].ctypes.data if sub else None, out['F_net_center'].ctypes.data if sub else None,
              scratch_ptr, 0, Opts(o.improved, o.noniso, o.e_clamp, 0, o.eps2, o.e_tau, o.g_guard,

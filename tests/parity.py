@@ -18,6 +18,16 @@ import numpy as np
 
 GRAV = 47.0
 
+# Relative tolerances and scale floors of the two paths (precision 0: FP64,
+# 1: mixed).  Bin-summed fluxes use the floor 1e-6 S.  Per-bin fluxes: in FP64
+# 1e-10 x 1e-6 S_cb would be below the unit roundoff of S_cb (2.2e-16), so the
+# per-bin floor is 1e-5 S_cb (1e-15 S_cb absolute, a few ulp of S_cb); the
+# mixed path's FP32 coefficients round at 6e-8 of each term, and its per-bin
+# floor is 1e-3 S_cb.
+TOL = {0: 1e-10, 1: 1e-5}
+FLOOR = {0: 1e-6, 1: 1e-6}
+FLOOR_BIN = {0: 1e-5, 1: 1e-3}
+
 
 def subset(work: dict, cols) -> dict:
     """The same workload restricted to a list of columns (columns are independent)."""

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2203_02293_amd import synth
-from tests.parity import errors
+from tests.parity import FLOOR, FLOOR_BIN, errors
 
 run = pytest.importorskip("tests.host_emu.run")
 
@@ -27,8 +27,8 @@ def check(w, mixed, ncu, opts=None):
     ref = (O.solve_sublayer if sub else O.solve)(w, opts, per_bin=True, extended=True)
     out, g = run.solve_deep(w, mixed, opts=opts, ncu=ncu)
     tol = 1e-5 if mixed else 1e-10
-    e = errors(out, ref, w["p_iface"], floor=1e-2 if mixed else 1e-3,
-               floor_bin=1.0 if mixed else 1e-3)
+    e = errors(out, ref, w["p_iface"], floor=FLOOR[int(mixed)],
+               floor_bin=FLOOR_BIN[int(mixed)])
     bad = {k: v for k, v in e.items() if not v <= tol}
     assert not bad, (g, bad)
     np.testing.assert_array_equal(out["flags"], ref["flags"])

@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 from paper_2203_02293_amd import synth
-from tests.parity import assert_close
+from tests.parity import FLOOR, FLOOR_BIN, TOL, assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +72,8 @@ def test_optics_then_solve(rt, torch):
                T_int=torch.from_numpy(atm["T_int"]).cuda())
     ropt = O.optics(atm, tab, sublayer=True)
     ref = O.solve_sublayer(dict(atm, gauss_w=gw, **ropt), per_bin=True, extended=True)
-    for prec, tol, floor, fbin in ((rt.RT_FP64, 1e-10, 1e-3, 1e-3), (rt.RT_MIXED, 1e-5, 1e-2, 1.0)):
+    for prec in (rt.RT_FP64, rt.RT_MIXED):
+        tol, floor, fbin = TOL[prec], FLOOR[prec], FLOOR_BIN[prec]
         out = s.solve(inp, precision=prec, per_bin=True)
         torch.cuda.synchronize()
         res = {k: v.cpu().numpy() for k, v in out.items()}

@@ -12,19 +12,11 @@ import pytest
 
 import oracle as O
 from paper_2203_02293_amd import synth
-from tests.parity import assert_close, errors, subset
+from tests.parity import FLOOR, FLOOR_BIN, TOL, assert_close, errors, subset
 
 pytestmark = pytest.mark.gpu
 
-FP64_TOL, MIXED_TOL = 1e-10, 1e-5
-# floor of the scale for interface fluxes (see tests/parity.py).  FP64 leaves
-# ~1e-14 S absolute, so it is held to 1e-10 relative down to 1e-3 S.  The
-# mixed path is held to its stated target, 1e-5 S on net flux and heating,
-# to 1e-5 relative down to 1e-2 S on bin-summed fluxes, and to 1e-5 S_cb on
-# per-bin fluxes: FP32 coefficient rounding (6e-8 per term, accumulated over
-# the layers) leaves ~1e-7 S_cb absolute in small deep per-bin fluxes.
-FLOOR = {0: 1e-3, 1: 1e-2}
-FLOOR_BIN = {0: 1e-3, 1: 1.0}
+FP64_TOL, MIXED_TOL = TOL[0], TOL[1]
 
 
 @pytest.fixture(scope="module")
@@ -77,6 +69,9 @@ CASES = [
     ("one_layer", dict(C=9, N=1, NB=5, seed=15)),
     ("wide_bins", dict(C=3, N=6, NB=300, seed=16)),
     ("deep", dict(C=4, N=120, NB=10, seed=17)),
+    # bin-sum group widths 8 and 64 of the layer kernel's wavefront sums
+    ("bins8", dict(C=21, N=7, NB=8, seed=18)),
+    ("bins40", dict(C=13, N=9, NB=40, seed=19)),
 ]
 
 
@@ -149,7 +144,7 @@ def test_toa_diffuse_flux(rt, torch):
 
 def edge_workload():
     """Columns built to sit on the paper's branch points."""
-    w = small(C=8, N=6, NB=4, seed=31)
+    w = small(C=11, N=6, NB=4, seed=31)
     w = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in w.items()}
     # w0 exactly at the 0.1 threshold and one ulp above it
     w["w0"][0, 0, :] = 0.1
@@ -171,6 +166,16 @@ def edge_workload():
     w["g0"][:, 5, :] = 0.95
     # night column
     w["mu_star"][6] = -0.3
+    # the terminator exactly (no beam) and a beam that is only just there
+    w["mu_star"][8] = 0.0
+    w["mu_star"][9] = 1e-300
+    # a day column whose top layers are optically very thin (below and just
+    # above e_tau): the beam sources of thin layers, where the printed forms
+    # are differences of nearly equal terms
+    w["mu_star"][10] = 0.7
+    w["dtau"][5, 10, :] = 1e-12
+    w["dtau"][4, 10, :] = 1e-6
+    w["dtau"][3, 10, :] = 2e-4
     return w
 
 
@@ -317,6 +322,7 @@ def test_sublayer_request_errors(rt, torch):
 KDIST_CASES = [
     ("kd_small", dict(C=5, N=6, NB=4, NG=5, seed=91)),
     ("kd_ragged", dict(C=13, N=9, NB=7, NG=3, seed=92)),
+    ("kd_2x20", dict(C=9, N=7, NB=2, NG=20, seed=94)),
 ]
 
 

@@ -129,3 +129,69 @@ def test_ticket_errors_and_queue_limit(rt, torch):
     t3 = s.submit(inputs[0], outs[0])
     s.close()
     torch.cuda.synchronize()
+
+
+def test_served_status_codes(rt, torch):
+    """After completion rt_wait returns RT_EINVAL for a request whose inputs
+    are outside their domain and RT_EDOMAIN for strict-mode E <= w0 (with the
+    columns' flags set), while a clean request of the same batched launch
+    returns RT_OK with the stand-alone result."""
+    reqs = request_mix(3, 30, seed=11)
+    reqs = [{k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in w.items()} for w in reqs]
+    reqs[1]["w0"][3, 0, 2] = 1.5                      # invalid albedo in column 0
+    for kernel in (rt.RT_KERNEL_LAYER, rt.RT_KERNEL_DEEP):
+        s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"])
+        inputs = [rt.to_device(w) for w in reqs]
+        clean = s.solve(inputs[0], kernel=kernel, cols_per_block=0)
+        torch.cuda.synchronize()
+        outs = [s.outputs(int(i["mu_star"].shape[0]), int(i["dtau"].shape[0])) for i in inputs]
+        tickets = [s.submit(i, o, kernel=kernel, cols_per_block=0) for i, o in zip(inputs, outs)]
+        assert s.wait(tickets[0]) == rt.RT_OK
+        with pytest.raises(rt.RtError) as e:
+            s.wait(tickets[1])
+        assert e.value.status == rt.RT_EINVAL
+        assert host(outs[1])["flags"][0] & rt.FLAG_INVALID
+        assert s.wait(tickets[2]) == rt.RT_OK
+        np.testing.assert_array_equal(host(clean)["F_net"], host(outs[0])["F_net"])
+        s.close()
+    # strict mode: a cloud column with E_fit <= w0
+    w = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in reqs[0].items()}
+    w["w0"][:, 1, :] = 0.999
+    w["g0"][:, 1, :] = 0.95
+    s = rt.Solver(w["lambda_edges"], w["F_star"], e_clamp=0)
+    inp = rt.to_device(w)
+    out = s.outputs(w["n_cols"], w["n_layers"])
+    with pytest.raises(rt.RtError) as e:
+        s.wait(s.submit(inp, out))
+    assert e.value.status == rt.RT_EDOMAIN
+    assert host(out)["flags"][1] & rt.FLAG_EDOMAIN
+    s.close()
+
+
+def test_enomem_and_recovery(rt, torch):
+    """RT_ENOMEM from the serving path: a request larger than the handle's
+    budget is refused at submission, and a budget the device cannot allocate
+    fails the first submission; the same handle's stream path still solves,
+    and a later submission under a workable budget succeeds."""
+    w = request_mix(1, 30, seed=13)[0]
+    probe = rt.Solver(w["lambda_edges"], w["F_star"])
+    need = probe.work_bytes(w["n_cols"], w["n_layers"])
+    probe.close()
+    inp = rt.to_device(w)
+    s = rt.Solver(w["lambda_edges"], w["F_star"], hbm_budget_bytes=need // 2)
+    out = s.outputs(w["n_cols"], w["n_layers"])
+    with pytest.raises(rt.RtError) as e:
+        s.submit(inp, out)
+    assert e.value.status == rt.RT_ENOMEM
+    s.close()
+    s = rt.Solver(w["lambda_edges"], w["F_star"], hbm_budget_bytes=1 << 50)   # 1 PiB
+    with pytest.raises(rt.RtError) as e:
+        s.submit(inp, out)
+    assert e.value.status == rt.RT_ENOMEM
+    ref = s.solve(inp)                      # the stream path of the same handle
+    torch.cuda.synchronize()
+    s.close()
+    s = rt.Solver(w["lambda_edges"], w["F_star"], hbm_budget_bytes=4 * need)
+    assert s.wait(s.submit(inp, out)) == rt.RT_OK
+    np.testing.assert_array_equal(host(ref)["F_net"], host(out)["F_net"])
+    s.close()
