@@ -19,6 +19,7 @@ arrays and exposes:
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as ct
 import dataclasses
 import os
@@ -105,6 +106,9 @@ class Options:
 
 
 _libs: dict = {}
+# Which build the functions below use when they are not told: FP64 (the
+# oracle) unless a test switches to the binary128 build with extended_build().
+_default = {"extended": False}
 
 
 def load(path) -> ct.CDLL:
@@ -114,8 +118,11 @@ def load(path) -> ct.CDLL:
     return L
 
 
-def lib(extended: bool = False) -> ct.CDLL:
-    """The FP64 oracle library, or its binary128 build if ``extended``."""
+def lib(extended: bool | None = None) -> ct.CDLL:
+    """The FP64 oracle library, or its binary128 build if ``extended``
+    (None: the build selected by ``extended_build``, FP64 by default)."""
+    if extended is None:
+        extended = _default["extended"]
     path = LIB_X if extended else LIB
     if path not in _libs:
         newest = max(SRC.stat().st_mtime, SRC.with_suffix(".h").stat().st_mtime)
@@ -123,6 +130,18 @@ def lib(extended: bool = False) -> ct.CDLL:
             build(force=True)
         _libs[path] = load(path)
     return _libs[path]
+
+
+@contextlib.contextmanager
+def extended_build(on: bool = True):
+    """Within the block, calls that name no build use the binary128 one (so
+    the same pin tests can run against both builds of the source)."""
+    saved = _default["extended"]
+    _default["extended"] = bool(on)
+    try:
+        yield
+    finally:
+        _default["extended"] = saved
 
 
 def _declare(L: ct.CDLL) -> None:
@@ -239,7 +258,7 @@ def column_bin(B, dtau, w0, g0, mu, Fstar, F_boa=0.0, F_toa=0.0,
 # ----------------------------------------------------------------- problem
 def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
           cols: tuple[int, int] | None = None, n_threads: int = 0,
-          F_toa: np.ndarray | None = None, extended: bool = False) -> dict:
+          F_toa: np.ndarray | None = None, extended: bool | None = None) -> dict:
     """Solve every (column, bin) of a workload dict (layouts as in ``synth``).
 
     ``cols`` restricts the solve to a column range (other outputs stay zero).
@@ -280,7 +299,7 @@ def solve(work: dict, opts: Options | None = None, per_bin: bool = False,
 
 def solve_sublayer(work: dict, opts: Options | None = None, per_bin: bool = False,
                    cols: tuple[int, int] | None = None, n_threads: int = 0,
-                   F_toa: np.ndarray | None = None, extended: bool = False) -> dict:
+                   F_toa: np.ndarray | None = None, extended: bool | None = None) -> dict:
     """Sub-layer grid of non-isothermal layers (Section 2.2.1 and the grid
     figure): layer j is split at its centre into a lower sub-layer (interface j
     to centre j) and an upper one (centre j to interface j+1).  Each sub-layer

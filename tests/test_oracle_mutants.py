@@ -2,9 +2,11 @@
 CPU build of the oracle source and check that the pins catch every one.
 
 Each mutant is the oracle's C file with one textual change, compiled with gcc
-into a temporary library and swapped in for the FP64 oracle while a set of pin
+into a temporary library and swapped in for the oracle while a set of pin
 tests runs.  A mutant that no pin rejects would mean the pins cannot tell that
-part of the oracle from a wrong version of it.
+part of the oracle from a wrong version of it.  Every mutant is built twice,
+as FP64 and as binary128 (the build the FP64 GPU path is checked against),
+and the pins must reject both.
 """
 import os
 import subprocess
@@ -58,42 +60,51 @@ def pins():
     yield "superposition", P.test_superposition
 
 
-def build_mutant(old, new, tmp):
+def build_mutant(old, new, tmp, quad=False):
     src = open(O.SRC).read()
     assert src.count(old) == 1, old
     path = os.path.join(tmp, "mut.c")
     with open(path, "w") as f:
         f.write(src.replace(old, new))
     out = os.path.join(tmp, "libmut.so")
+    extra = ["-DORC_QUAD=1"] if quad else []
     subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
-                    "-fopenmp", f"-I{O.HERE}", "-o", out, path, "-lm"], check=True)
+                    "-fopenmp", f"-I{O.HERE}", *extra, "-o", out, path, "-lquadmath", "-lm"],
+                   check=True)
     return O.load(out)
 
 
+@pytest.mark.parametrize("build", ["fp64", "binary128"])
 @pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_pins_reject_mutant(name):
+def test_pins_reject_mutant(name, build):
     old, new = MUTANTS[name]
-    O.lib()
+    quad = build == "binary128"
+    key = O.LIB_X if quad else O.LIB
+    O.lib(quad)
     with tempfile.TemporaryDirectory() as tmp:
-        mutant = build_mutant(old, new, tmp)
-        saved = O._libs[O.LIB]
-        O._libs[O.LIB] = mutant
+        mutant = build_mutant(old, new, tmp, quad)
+        saved = O._libs[key]
+        O._libs[key] = mutant
         caught = []
         try:
-            for pname, fn in pins():
-                try:
-                    with np.errstate(all="ignore"):
-                        fn()
-                except (AssertionError, ArithmeticError, ValueError, RuntimeError):
-                    caught.append(pname)
+            with O.extended_build(quad):
+                for pname, fn in pins():
+                    try:
+                        with np.errstate(all="ignore"):
+                            fn()
+                    except (AssertionError, ArithmeticError, ValueError, RuntimeError):
+                        caught.append(pname)
         finally:
-            O._libs[O.LIB] = saved
-    assert caught, f"no pin rejects mutant {name}"
-    print(f"{name}: rejected by {caught}")
+            O._libs[key] = saved
+    assert caught, f"no pin rejects mutant {name} ({build})"
+    print(f"{name} ({build}): rejected by {caught}")
 
 
-def test_pin_subset_passes_on_the_oracle():
-    """Control: the same pins all pass on the unmodified oracle."""
-    O.lib()
-    for pname, fn in pins():
-        fn()
+@pytest.mark.parametrize("build", ["fp64", "binary128"])
+def test_pin_subset_passes_on_the_oracle(build):
+    """Control: the same pins all pass on the unmodified oracle (both builds)."""
+    quad = build == "binary128"
+    O.lib(quad)
+    with O.extended_build(quad):
+        for pname, fn in pins():
+            fn()

@@ -5,6 +5,10 @@ textbook special case, an invariant of the exact solution, an independent
 numerical solution of the underlying ODE, a library solve, or the paper's
 own limiting statements.  Paper: Deitrick et al. (arXiv 2203.02293),
 Section 2.2 and Appendix B.
+
+Every test runs twice, once per build of the oracle source (FP64 and
+binary128): the binary128 build is the reference of the FP64 GPU parity
+tests, so it is pinned by the same independent checks.
 """
 import math
 
@@ -19,6 +23,14 @@ PI = math.pi
 
 def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(autouse=True, params=["fp64", "binary128"])
+def build(request):
+    """Every pin runs against both builds of the oracle source: the FP64
+    oracle and the binary128 build that the FP64 GPU path is checked against."""
+    with O.extended_build(request.param == "binary128"):
+        yield request.param
 
 
 # ---------------------------------------------------------------- E and coefficients

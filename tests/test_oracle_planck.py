@@ -12,6 +12,13 @@ H, C, K = 6.62607015e-34, 299792458.0, 1.380649e-23
 SIGMA = 2 * math.pi ** 5 * K ** 4 / (15 * H ** 3 * C ** 2)
 
 
+@pytest.fixture(autouse=True, params=["fp64", "binary128"])
+def build(request, orc):
+    """Each pin runs against both builds of the oracle source."""
+    with orc.extended_build(request.param == "binary128"):
+        yield request.param
+
+
 def planck_mp(T, l1, l2, pieces=64):
     """B_lambda integrated over [l1, l2] in wavelength, 40 digits, subdivided."""
     mp.mp.dps = 40
