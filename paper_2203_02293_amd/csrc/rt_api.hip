@@ -136,6 +136,25 @@ struct rt_handle {
     std::map<uint64_t, rt_status> finished;   // retired on first poll
 };
 
+// Device allocation that leaves no error behind: a failed hipMalloc also sets
+// the runtime's last-error state, which the caller's next unrelated HIP call
+// (or the framework around the library) would otherwise report as its own.
+static bool dev_alloc(void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+}
+
+static bool host_alloc(void **p, size_t bytes)
+{
+    if (hipHostMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+}
+
 static rt_status fail(rt_handle *h, rt_status s, const char *fmt, ...)
 {
     if (h) {
@@ -275,11 +294,10 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
         c2[e] = c2rad / cfg->lambda_edges[e];
         c2f[e] = float(c2[e]);
     }
-    hipError_t err;
-    if ((err = hipMalloc(&h->d_c2lam, sizeof(double) * (NB + 1))) != hipSuccess ||
-        (err = hipMalloc(&h->d_c2lam_f, sizeof(float) * (NB + 1))) != hipSuccess ||
-        (err = hipMalloc(&h->d_fstar, sizeof(double) * NB)) != hipSuccess ||
-        (err = hipMalloc(&h->d_gw, sizeof(double) * NG)) != hipSuccess) {
+    if (!dev_alloc((void **)&h->d_c2lam, sizeof(double) * (NB + 1)) ||
+        !dev_alloc((void **)&h->d_c2lam_f, sizeof(float) * (NB + 1)) ||
+        !dev_alloc((void **)&h->d_fstar, sizeof(double) * NB) ||
+        !dev_alloc((void **)&h->d_gw, sizeof(double) * NG)) {
         rt_destroy(h);
         return RT_ENOMEM;
     }
@@ -488,7 +506,7 @@ extern "C" rt_status rt_set_opacities(rt_handle *h, const rt_opacities *op)
     (void)hipFree(h->d_opac);
     h->d_opac = nullptr;
     h->have_opac = false;
-    if (hipMalloc(&h->d_opac, host.size() * sizeof(double)) != hipSuccess)
+    if (!dev_alloc((void **)&h->d_opac, host.size() * sizeof(double)))
         return fail(h, RT_ENOMEM, "opacity tables of %zu bytes", host.size() * sizeof(double));
     if (hipMemcpy(h->d_opac, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) !=
         hipSuccess)
@@ -558,7 +576,7 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
         (void)hipFree(h->d_scratch);
         h->d_scratch = nullptr;
         h->scratch_bytes = 0;
-        if (hipMalloc(&h->d_scratch, need) != hipSuccess)
+        if (!dev_alloc((void **)&h->d_scratch, need))
             return fail(h, RT_ENOMEM, "work buffer of %zu bytes", need);
         h->scratch_bytes = need;
     }
@@ -591,18 +609,18 @@ static rt_status ensure_serving(rt_handle *h)
             return fail(h, RT_EDEVICE, "stream creation failed");
     for (int i = 0; i < kSlots; ++i) {
         Batch &b = h->slots[i];
-        if (hipHostMalloc((void **)&b.h_args, sizeof(rtk::SolveArgs) * kMaxBatch) != hipSuccess ||
-            hipHostMalloc((void **)&b.h_first, sizeof(int) * kMaxBatch) != hipSuccess ||
-            hipMalloc(&b.d_args, sizeof(rtk::SolveArgs) * kMaxBatch) != hipSuccess ||
-            hipMalloc(&b.d_first, sizeof(int) * kMaxBatch) != hipSuccess ||
-            hipHostMalloc((void **)&b.h_status, sizeof(uint32_t) * kMaxBatch) != hipSuccess ||
-            hipMalloc(&b.d_status, sizeof(uint32_t) * kMaxBatch) != hipSuccess ||
+        if (!host_alloc((void **)&b.h_args, sizeof(rtk::SolveArgs) * kMaxBatch) ||
+            !host_alloc((void **)&b.h_first, sizeof(int) * kMaxBatch) ||
+            !dev_alloc((void **)&b.d_args, sizeof(rtk::SolveArgs) * kMaxBatch) ||
+            !dev_alloc((void **)&b.d_first, sizeof(int) * kMaxBatch) ||
+            !host_alloc((void **)&b.h_status, sizeof(uint32_t) * kMaxBatch) ||
+            !dev_alloc((void **)&b.d_status, sizeof(uint32_t) * kMaxBatch) ||
             hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
             return fail(h, RT_ENOMEM, "serving descriptor buffers");
         b.stream = i % kStreams;
     }
     size_t bytes = (size_t)h->cfg.hbm_budget_bytes;
-    if (hipMalloc(&h->arena_mem, bytes) != hipSuccess) {
+    if (!dev_alloc((void **)&h->arena_mem, bytes)) {
         h->arena_mem = nullptr;
         return fail(h, RT_ENOMEM, "serving arena of %zu bytes", bytes);
     }
