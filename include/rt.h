@@ -189,6 +189,23 @@ typedef struct {
 rt_status rt_solve_fluxes(rt_handle *h, const rt_request *req, void *hip_stream);
 
 /*
+ * rt_solve_fluxes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same request, kernels and results, with the work buffer taken from a
+ * fixed device array of the library (128 MiB per device, held from the
+ * library's first use on a device until the process ends) instead of the
+ * handle's, so the call makes no hipMalloc or hipFree and no other
+ * allocating call.  The caller still owns every input and output buffer.
+ * Errors: as rt_solve_fluxes, and RT_ENOMEM before any launch when the
+ * request needs a larger work buffer than the array (rt_work_bytes gives the
+ * need; at 2562 columns x 40 layers x 30 bins it is 98 MB).  Every call on a
+ * device shares that one array and leaves its contents behind: calls on one
+ * device that overlap (other streams, other handles, other threads) race;
+ * issue them on one stream or synchronise between them.
+ */
+rt_status rt_solve_fluxes_noalloc(rt_handle *h, const rt_request *req, void *hip_stream);
+
+/*
  * The kernel rt_solve_fluxes would run for req (RT_KERNEL_LANE, _LAYER or
  * _DEEP: AUTO resolved), checking req as rt_solve_fluxes does but launching
  * nothing; RT_EINVAL (negative) on a bad request.

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -103,6 +104,35 @@ struct Batch {
     int stream = 0;
 };
 
+// Work buffer of rt_solve_fluxes_noalloc: a file-scope device array, so that
+// entry point allocates nothing.  Each device the library runs on holds its
+// own copy from the first use of the library on it until the process ends.
+// In host code the array's name is not a device address: its address on a
+// device comes from hipGetSymbolAddress (static_scratch below).
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;   // 128 MiB
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double *g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current), looked
+// up once per device; nullptr if the lookup fails.
+double *static_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_static_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_static_ptr[dev];
+}
+
 }  // namespace
 
 struct rt_handle {
@@ -123,6 +153,7 @@ struct rt_handle {
     double *d_fstar = nullptr;
     double *d_scratch = nullptr;
     size_t scratch_bytes = 0;
+    double *static_ws = nullptr;   // this device's `scratch` (rt_solve_fluxes_noalloc)
     std::string err;
     // serving
     hipStream_t streams[kStreams] = {};
@@ -282,6 +313,12 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
         h->dev.lds = (size_t)lds;
         if (rtk::prepare_kernels(h->dev) != hipSuccess ||
             rtk::prepare_deep_kernels(h->dev) != hipSuccess) {
+            delete h;
+            return RT_EDEVICE;
+        }
+        // the allocation-free path's work buffer on this device (current here)
+        h->static_ws = static_scratch(cfg->device);
+        if (!h->static_ws) {
             delete h;
             return RT_EDEVICE;
         }
@@ -581,6 +618,26 @@ extern "C" rt_status rt_solve_fluxes(rt_handle *h, const rt_request *r, void *st
         h->scratch_bytes = need;
     }
     rtk::SolveArgs a = make_args(h, r, h->d_scratch);
+    hipError_t e = g.kernel == rtk::KERNEL_DEEP
+                       ? rtk::launch_deep(a, g, r->precision, (hipStream_t)stream)
+                       : rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(h, e, "solve launch");
+    return RT_OK;
+}
+
+extern "C" rt_status rt_solve_fluxes_noalloc(rt_handle *h, const rt_request *r, void *stream)
+{
+    if (!h) return RT_EINVAL;
+    rt_status st = validate(h, r);
+    if (st != RT_OK) return st;
+    (void)hipSetDevice(h->cfg.device);
+    const rtk::Geometry g = request_geometry(h, r);
+    if (g.scratch > kStaticScratchBytes)
+        return fail(h, RT_ENOMEM, "request needs a work buffer of %zu bytes; the static one holds %zu",
+                    g.scratch, kStaticScratchBytes);
+    // the kernels write every word of the work buffer they read later, so it
+    // needs no clearing between calls
+    rtk::SolveArgs a = make_args(h, r, h->static_ws);
     hipError_t e = g.kernel == rtk::KERNEL_DEEP
                        ? rtk::launch_deep(a, g, r->precision, (hipStream_t)stream)
                        : rtk::launch_solve(a, g, r->precision, (hipStream_t)stream);

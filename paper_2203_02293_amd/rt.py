@@ -21,7 +21,8 @@ RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER, RT_KERNEL_DEEP = 0, 1, 2, 3
 FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
 
 #: every symbol include/rt.h declares
-SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes", "rt_submit",
+SYMBOLS = ("rt_config_default", "rt_create", "rt_destroy", "rt_solve_fluxes",
+           "rt_solve_fluxes_noalloc", "rt_submit",
            "rt_poll", "rt_wait", "rt_work_bytes", "rt_last_error", "rt_status_string",
            "rt_set_opacities", "rt_optical_properties", "rt_request_kernel")
 
@@ -88,6 +89,8 @@ def lib() -> ct.CDLL:
         L.rt_destroy.restype = ct.c_int32
         L.rt_solve_fluxes.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.c_void_p]
         L.rt_solve_fluxes.restype = ct.c_int32
+        L.rt_solve_fluxes_noalloc.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.c_void_p]
+        L.rt_solve_fluxes_noalloc.restype = ct.c_int32
         L.rt_request_kernel.argtypes = [ct.c_void_p, ct.POINTER(RtRequest)]
         L.rt_request_kernel.restype = ct.c_int32
         L.rt_submit.argtypes = [ct.c_void_p, ct.POINTER(RtRequest), ct.POINTER(ct.c_uint64)]
@@ -145,6 +148,11 @@ def _check(h, st, what):
 
 def rt_solve_fluxes(h: int, req: RtRequest, stream: int | None) -> int:
     return _check(h, lib().rt_solve_fluxes(h, ct.byref(req), stream), "rt_solve_fluxes")
+
+
+def rt_solve_fluxes_noalloc(h: int, req: RtRequest, stream: int | None) -> int:
+    return _check(h, lib().rt_solve_fluxes_noalloc(h, ct.byref(req), stream),
+                  "rt_solve_fluxes_noalloc")
 
 
 def rt_request_kernel(h: int, req: RtRequest) -> int:
@@ -319,8 +327,10 @@ class Solver:
 
     def solve(self, inp: dict, precision: int = RT_FP64, per_bin: bool = False,
               out: dict | None = None, stream=None, cols_per_block: int | None = None,
-              kernel: int | None = None) -> dict:
-        """Stream-ordered solve on the current (or given) torch stream."""
+              kernel: int | None = None, noalloc: bool = False) -> dict:
+        """Stream-ordered solve on the current (or given) torch stream.
+        ``noalloc``: through rt_solve_fluxes_noalloc (pass ``out`` too, so that
+        the call allocates nothing)."""
         import torch
         sub = inp.get("T_center") is not None
         C, N = int(inp["mu_star"].shape[0]), int(inp["dtau"].shape[0]) // (2 if sub else 1)
@@ -328,7 +338,7 @@ class Solver:
             out = self.outputs(C, N, per_bin, sublayer=sub)
         req = self.request(inp, out, precision, cols_per_block, kernel)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        rt_solve_fluxes(self.h, req, s.cuda_stream)
+        (rt_solve_fluxes_noalloc if noalloc else rt_solve_fluxes)(self.h, req, s.cuda_stream)
         return out
 
     def kernel_for(self, inp: dict, out: dict, precision: int = RT_FP64,
