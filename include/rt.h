@@ -43,6 +43,10 @@ typedef int32_t rt_status;
 #define RT_MIXED 1   /* FP32 coefficients, exponentials and Planck integrals; FP64
                         predicates, optical-depth sums and Thomas elimination     */
 
+/* storage of the per-layer inputs dtau, w0, g0 (rt_request.input_dtype) */
+#define RT_F64 0     /* doubles                                                     */
+#define RT_F32 1     /* floats: RT_MIXED only (the FP64 path keeps its inputs exact) */
+
 /* Solve kernels (same results to the precision's tolerance, different launch
  * shapes).  LANE: one thread per (column, bin) runs the whole sweep of its
  * lane.  LAYER: the Planck, beam and coefficient work of a tile is spread over
@@ -122,7 +126,8 @@ rt_status rt_destroy(rt_handle *h);
  * needs the layer kernel.  Inputs (device, read only):
  *   p_iface, T_iface  [N+1][C]   Pa, K; p strictly decreasing with i, T > 0
  *   dtau, w0, g0      [N][C][NB] layer optical depth (>= 0), single-scattering
- *                                albedo in [0,1], asymmetry in (-1,1)
+ *                                albedo in [0,1], asymmetry in (-1,1); doubles,
+ *                                or floats with input_dtype = RT_F32
  *   mu_star           [C]        cosine of the stellar zenith angle; <= 0: no beam
  *   T_int             [C]        interior temperature, F_BOA = pi B_b(T_int) (K, >= 0)
  *   F_toa             [C][NB]    diffuse downward flux at TOA (W m^-2) or NULL = 0
@@ -164,9 +169,13 @@ typedef struct {
                                      kernel), K*NB <= 1024 and its LDS within the
                                      device's (layer kernel), else RT_EINVAL      */
     int32_t kernel;               /* RT_KERNEL_AUTO, _LANE, _LAYER or _DEEP */
-    int32_t reserved;             /* must be 0 */
+    int32_t input_dtype;          /* storage of dtau, w0, g0: RT_F64 (doubles), or
+                                     RT_F32 (floats; RT_MIXED only, else RT_EINVAL):
+                                     half the bytes of the largest inputs.  Each
+                                     value is used as the number it stores (the
+                                     FP64 branch decisions see the float exactly) */
     const double *p_iface, *T_iface;
-    const double *dtau, *w0, *g0;
+    const void *dtau, *w0, *g0;   /* double or float, as input_dtype says */
     const double *mu_star, *T_int;
     const double *F_toa;
     double *F_up, *F_dn, *F_beam, *F_net;

@@ -250,7 +250,8 @@ extern "C" int64_t rt_work_bytes(const rt_handle *h, int32_t n_cols, int32_t n_l
     const rtk::Geometry g =
         prefer_deep(h, n_cols, n_layers)
             ? rtk::deep_geometry(n_cols, n_layers, h->NBG, h->dev)
-            : rtk::solve_geometry(n_cols, n_layers, h->NBG, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev);
+            : rtk::solve_geometry(n_cols, n_layers, h->NBG, 0, rtk::KERNEL_AUTO, RT_FP64, h->dev,
+                                  h->NG);
     return g.threads > 0 ? (int64_t)g.scratch : -1;
 }
 
@@ -391,7 +392,7 @@ static rtk::Geometry request_geometry(const rt_handle *h, const rt_request *r)
         return rtk::deep_geometry(r->n_cols, N, h->NBG, h->dev);
     const int kernel = r->kernel == RT_KERNEL_LANE ? rtk::KERNEL_LANE : rtk::KERNEL_LAYER;
     return rtk::solve_geometry(r->n_cols, N, h->NBG, r->cols_per_block, kernel, r->precision,
-                               h->dev);
+                               h->dev, h->NG);
 }
 
 static rt_status validate(rt_handle *h, const rt_request *r)
@@ -406,7 +407,10 @@ static rt_status validate(rt_handle *h, const rt_request *r)
         return fail(h, RT_EINVAL, "kernel must be RT_KERNEL_AUTO, _LANE, _LAYER or _DEEP");
     if (r->kernel == RT_KERNEL_DEEP && r->cols_per_block != 0)
         return fail(h, RT_EINVAL, "the deep kernel takes no tile (cols_per_block must be 0)");
-    if (r->reserved != 0) return fail(h, RT_EINVAL, "reserved must be 0");
+    if (r->input_dtype != RT_F64 && r->input_dtype != RT_F32)
+        return fail(h, RT_EINVAL, "input_dtype must be RT_F64 or RT_F32");
+    if (r->input_dtype == RT_F32 && r->precision != RT_MIXED)
+        return fail(h, RT_EINVAL, "FP32 input storage needs the mixed precision (RT_MIXED)");
     if (h->NG > 1 && r->kernel == RT_KERNEL_LANE)
         return fail(h, RT_EINVAL, "Gaussian points per bin need the layer kernel");
     if (r->cols_per_block < 0) return fail(h, RT_EINVAL, "cols_per_block must be >= 0");
@@ -467,9 +471,10 @@ static rtk::SolveArgs make_args(const rt_handle *h, const rt_request *r, double 
     a.F_star = h->d_fstar;
     a.p = r->p_iface;
     a.T = r->T_iface;
-    a.dtau = r->dtau;
-    a.w0 = r->w0;
-    a.g0 = r->g0;
+    a.dtau = static_cast<const double *>(r->dtau);
+    a.w0 = static_cast<const double *>(r->w0);
+    a.g0 = static_cast<const double *>(r->g0);
+    a.in_f32 = r->input_dtype == RT_F32;
     a.mu = r->mu_star;
     a.Tint = r->T_int;
     a.Ftoa = r->F_toa;
@@ -723,6 +728,7 @@ static void pump(rt_handle *h)
         if (slot < 0) return;                       // every batch slot in flight
         Batch &b = h->slots[slot];
         const int prec = h->queued.front().req.precision;
+        const int in32 = h->queued.front().req.input_dtype;
         const rtk::Geometry g0 = h->queued.front().g;
         hipStream_t s = h->streams[b.stream];
         if (g0.kernel == rtk::KERNEL_DEEP) {
@@ -752,8 +758,10 @@ static void pump(rt_handle *h)
         }
         int blocks = 0;
         for (auto it = h->queued.begin(); it != h->queued.end() && (int)b.jobs.size() < kMaxBatch;) {
-            // one launch shape per batch: same kernel, precision, tile, threads and LDS
-            if (it->req.precision != prec || it->g.kernel != g0.kernel || it->g.K != g0.K ||
+            // one launch shape per batch: same kernel, precision, input storage, tile,
+            // threads and LDS
+            if (it->req.precision != prec || it->req.input_dtype != in32 ||
+                it->g.kernel != g0.kernel || it->g.K != g0.K ||
                 it->g.threads != g0.threads || it->g.lds != g0.lds || it->g.PC != g0.PC ||
                 it->g.CH != g0.CH) {
                 ++it;
@@ -783,7 +791,7 @@ static void pump(rt_handle *h)
             e = hipMemcpyAsync(b.d_first, b.h_first, sizeof(int) * n, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemsetAsync(b.d_status, 0, sizeof(uint32_t) * n, s);
         if (e == hipSuccess)
-            e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, g0, prec, s);
+            e = rtk::launch_solve_batch(b.d_args, b.d_first, n, blocks, g0, prec, in32, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b.h_status, b.d_status, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipEventRecord(b.done, s);

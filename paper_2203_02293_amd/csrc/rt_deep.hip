@@ -177,13 +177,15 @@ __device__ __forceinline__ void flags_out(const SolveArgs &a, int c, const uint3
 
 // Sum of p[k * stride] for k = 0 .. n-1 in that order, the loads issued in
 // groups of 8 (adding 0 past the end is exact).
-__device__ __forceinline__ double sum_strided(const double *p, long long stride, int n)
+__device__ __forceinline__ double sum_strided(const double *p, long long stride, int n, int f32 = 0,
+                                              long long i0 = 0)
 {
     double acc = 0.0;
     for (int k0 = 0; k0 < n; k0 += 8) {
         double v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = k0 + q < n ? p[(long long)(k0 + q) * stride] : 0.0;
+        for (int q = 0; q < 8; ++q)
+            v[q] = k0 + q < n ? ld_in(p, i0 + (long long)(k0 + q) * stride, f32) : 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc += v[q];
     }
@@ -202,7 +204,8 @@ __global__ void __launch_bounds__(kDeepLaneThreads) k_deep_tau(const SolveArgs a
     int top, bot;
     seg_range(a, d, s, top, bot);
     const long long l = (long long)c * a.NB + b;
-    seg_at(d, SG_TAU, s, l) = sum_strided(a.dtau + (long long)(top - 1) * d.L + l, -d.L, top - bot);
+    seg_at(d, SG_TAU, s, l) =
+        sum_strided(a.dtau, -d.L, top - bot, a.in_f32, (long long)(top - 1) * d.L + l);
 }
 
 // ---------------------------------------------------------------- k_deep_items
@@ -282,9 +285,9 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         double xdt = 0.0, xw = 0.0, xg = 0.0;
         if (slab) {
             const long long idx = (long long)ilev * d.L + lc + ib;
-            xdt = a.dtau[idx];
-            xw = a.w0[idx];
-            xg = a.g0[idx];
+            xdt = ld_in(a.dtau, idx, a.in_f32);
+            xw = ld_in(a.w0, idx, a.in_f32);
+            xg = ld_in(a.g0, idx, a.in_f32);
         }
         if (q0 == 0 && iq < QL)
             s_M[iq * NB + ib] = iq < s ? sum_strided(&seg_at(d, SG_TAU, iq, lc + ib), (long long)QL * d.L,

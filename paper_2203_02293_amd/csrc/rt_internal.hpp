@@ -29,6 +29,7 @@ struct SolveArgs {
     int K;                     // columns per workgroup
     int PC, CH;                // layer kernel: levels per chunk, interfaces per bin-sum pass
     int sub;                   // 1: sub-layer grid, N = 2 x layers slabs, levels interleaved
+    int in_f32;                // 1: dtau, w0, g0 hold floats (ld_in)
     int NG;                    // Gaussian points per bin: NB = bins x NG lanes per column
     // resident tables of the handle
     const double *c2_over_lam; // [NB/NG+1] second radiation constant / edge
@@ -52,6 +53,14 @@ struct SolveArgs {
     long long L;
     Opts o;
 };
+
+// Element i of a layer input (dtau, w0 or g0): stored as doubles, or as floats
+// when f32 (the mixed path's FP32 storage); either way the FP64 number stored.
+__host__ __device__ __forceinline__ double ld_in(const double *p, long long i, int f32)
+{
+    return f32 ? double(reinterpret_cast<const float *>(p)[i]) : p[i];
+}
+
 
 // What the launch shape depends on besides the problem: the device.
 struct DeviceLimits {
@@ -77,8 +86,9 @@ constexpr int kMaxTileLanes = 1024;    // (column, bin) lanes of one layer-kerne
 
 // kernel: KERNEL_* (AUTO picks); K: columns per workgroup (0 = default).
 // Returns threads = 0 when the shape cannot be launched (tile too large).
+// NB: lanes per column (bins x NG Gaussian points).
 Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
-                        const DeviceLimits &dev);
+                        const DeviceLimits &dev, int NG = 1);
 hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s);
 // Layer-parallel path for deep columns (several launches on stream s): K =
 // segments per column, PC = slabs per segment; scratch sized for it.
@@ -89,7 +99,7 @@ hipError_t prepare_deep_kernels(const DeviceLimits &dev);
 // device arrays d_reqs[n] (K, PC, CH, L filled in) and d_first[n] (first
 // workgroup of each).
 hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
-                              const Geometry &g, int precision, hipStream_t s);
+                              const Geometry &g, int precision, int in_f32, hipStream_t s);
 // Allow the kernels the device's full LDS per workgroup (once per device).
 hipError_t prepare_kernels(const DeviceLimits &dev);
 

@@ -57,10 +57,16 @@ __host__ __device__ inline int chunk_for(int threads, int K, int NB)
 // The solve kernel: Planck, coefficients, beam, forward elimination from the
 // TOA, back-substitution from the BOA, bin sums, net flux and heating.
 // ---------------------------------------------------------------------------
-template <bool MIXED>
+template <bool MIXED, bool IN32>
 __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int tile)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
+    // storage type of dtau, w0, g0 (FP32 on the mixed path only); loaded ahead
+    // in it and turned into FP64 where used, so no load is waited for early
+    using InT = typename std::conditional<IN32, float, double>::type;
+    const InT *const in_dt = reinterpret_cast<const InT *>(a.dtau);
+    const InT *const in_w = reinterpret_cast<const InT *>(a.w0);
+    const InT *const in_g = reinterpret_cast<const InT *>(a.g0);
     extern __shared__ double smem[];
     const int NB = a.NB, K = a.K, C = a.C, N = a.N;
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -77,9 +83,19 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
     const int nslot = PC * K * (NB + 1);
     const int front = max(3 * CH * bd, nslot);
     double *s_fnet = smem + front;                             // [K][CH+1]
-    uint32_t *s_flag = reinterpret_cast<uint32_t *>(s_fnet + K * (CH + 1));  // [K]
+    // per-bin tables in LDS (no global load inside the layer loop; see the
+    // layer kernel): c2/lambda at the edges in FP64 and FP32, F*
+    double *s_c2 = s_fnet + K * (CH + 1);                      // [NB+1]
+    double *s_fs = s_c2 + (NB + 1);                            // [NB]
+    float *s_c2f = reinterpret_cast<float *>(s_fs + NB);       // [NB+1]
+    uint32_t *s_flag = reinterpret_cast<uint32_t *>(s_c2f + (NB + 2));  // [K]
 
     for (int kk = tid; kk < K; kk += bd) s_flag[kk] = 0u;
+    for (int e = tid; e <= NB; e += bd) {
+        s_c2[e] = a.c2_over_lam[e];
+        s_c2f[e] = a.c2_over_lam_f[e];
+        if (e < NB) s_fs[e] = a.F_star[e];
+    }
     uint32_t fl = 0u;
 
     // Edge integrals of PC levels (rows q = 0..n-1 of level pointer src[q]) into LDS,
@@ -94,7 +110,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
             R v = R(0);
             if (cc < C) {
                 const double T = Tsrc[off0 - q * stride + cc];
-                v = planck_edge<R>(a.c2_over_lam[ee] / T);
+                v = planck_edge<R>(s_c2[ee] / T);
             }
             s_pl[(q * K + kk) * (NB + 1) + ee] = v;
         }
@@ -107,10 +123,10 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
         R I = planck_combine<R>(row[b], row[b + 1]);
         if constexpr (MIXED) {
             const R iT = rcp(T);
-            const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
+            const R xb = s_c2f[b] * iT, xa = s_c2f[b + 1] * iT;
             if (planck_narrow(xa, xb)) {
                 const double iTd = rcp(Td);
-                I = planck_gl3(a.c2_over_lam[b + 1] * iTd, a.c2_over_lam[b] * iTd);
+                I = planck_gl3(s_c2[b + 1] * iTd, s_c2[b] * iTd);
             }
         }
         return R(kPref) * T2 * T2 * I;
@@ -133,7 +149,7 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
     ElimState st = elim_top(0.0);
     double Fstar_b = 0.0;
     if (active) {
-        Fstar_b = a.F_star[b];
+        Fstar_b = s_fs[b];
         st = elim_top(a.Ftoa ? a.Ftoa[(long long)c * NB + b] : 0.0);
     }
     const double inv_mu = day ? 1.0 / mu : 0.0;
@@ -145,12 +161,13 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
     const long long lane_off = (long long)c * NB + b;
 
     // inputs of the next layer, loaded one layer ahead of their use
-    double nx_dt = 0.0, nx_w = 0.0, nx_g = 0.0, nx_T = 1.0;
+    InT nx_dt = InT(0), nx_w = InT(0), nx_g = InT(0);
+    double nx_T = 1.0;
     if (active) {
         const long long idx = (long long)(N - 1) * LB + lane_off;
-        nx_dt = a.dtau[idx];
-        nx_w = a.w0[idx];
-        nx_g = a.g0[idx];
+        nx_dt = in_dt[idx];
+        nx_w = in_w[idx];
+        nx_g = in_g[idx];
         nx_T = a.T[(long long)(N - 1) * C + c];
     }
     R Bup = R(0);
@@ -167,12 +184,12 @@ __device__ __forceinline__ void solve_tile_lane(const SolveArgs &a, const int ti
                 continue;
             }
             if (active) {
-                const double dt = nx_dt, w = nx_w, g = nx_g, Tl = nx_T;
+                const double dt = double(nx_dt), w = double(nx_w), g = double(nx_g), Tl = nx_T;
                 if (i > 0) {
                     const long long idx = (long long)(i - 1) * LB + lane_off;
-                    nx_dt = a.dtau[idx];
-                    nx_w = a.w0[idx];
-                    nx_g = a.g0[idx];
+                    nx_dt = in_dt[idx];
+                    nx_w = in_w[idx];
+                    nx_g = in_g[idx];
                     nx_T = a.T[(long long)(i - 1) * C + c];
                 }
                 if (!(Tl > 0.0) || !isfinite(Tl)) fl |= F_INVALID;
@@ -318,7 +335,7 @@ __host__ __device__ constexpr int layer_items_per_thread(bool) { return 1; }
 constexpr int kBackUnits = 8;
 
 struct LpLayout {
-    size_t flag, mu, wl, part, np;                     // persistent
+    size_t flag, mu, wl, tab, part, np;                // persistent
     size_t F, dt, Tl, tau, B, rec, rfl, edge, front;   // forward sweep
     size_t red, brec, back;                            // back-substitution (aliases the forward)
     size_t total;
@@ -350,6 +367,10 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     L.flag = o; o += lp_align(4 * (size_t)K);
     L.mu = o;   o += lp_align(8 * 3 * (size_t)K);              // mu, 1/mu, T_int per column
     L.wl = o;   o += lp_align(8 * (size_t)NB);                 // weight of each lane of a column
+    // per-bin tables (c2/lambda at the edges in FP64 and FP32, F*): in LDS so
+    // that no phase waits on a global load of its own (the input prefetches
+    // issued before it would drain with it: the vector-memory counter is in order)
+    L.tab = o;  o += lp_align(8 * (size_t)(NBR + 1) + 8 * (size_t)NBR + 4 * (size_t)(NBR + 1));
     // partial sums of the column sums, 2 buffers: a chunk's beam partials
     // (at most W of them) are written while the previous chunk's are summed
     size_t np = 1024;
@@ -380,10 +401,16 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     return L;
 }
 
-template <bool MIXED>
+template <bool MIXED, bool IN32>
 __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int tile)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
+    // storage type of dtau, w0, g0 (FP32 on the mixed path only); loaded ahead
+    // in it and turned into FP64 where used, so no load is waited for early
+    using InT = typename std::conditional<IN32, float, double>::type;
+    const InT *const in_dt = reinterpret_cast<const InT *>(a.dtau);
+    const InT *const in_w = reinterpret_cast<const InT *>(a.w0);
+    const InT *const in_g = reinterpret_cast<const InT *>(a.g0);
     extern __shared__ double smem[];
     char *lds = reinterpret_cast<char *>(smem);
     const int NB = a.NB, K = a.K, C = a.C, N = a.N, PC = a.PC, CH = a.CH;
@@ -395,6 +422,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     uint32_t *s_flag = reinterpret_cast<uint32_t *>(lds + Lo.flag);   // [K]
     double *s_mu = reinterpret_cast<double *>(lds + Lo.mu);           // [3][K]: mu, 1/mu, T_int
     double *s_wl = reinterpret_cast<double *>(lds + Lo.wl);           // [NB]
+    double *s_c2 = reinterpret_cast<double *>(lds + Lo.tab);          // [NBR+1] c2 / lambda edge
+    double *s_fs = s_c2 + (NBR + 1);                                  // [NBR] F* per bin
+    float *s_c2f = reinterpret_cast<float *>(s_fs + NBR);             // [NBR+1] FP32 c2 / lambda
     double *s_part = reinterpret_cast<double *>(lds + Lo.part);       // [2][np] partial column sums
     double *s_F0 = reinterpret_cast<double *>(lds + Lo.F);            // [2][PC+1][T]
     double *s_dt0 = reinterpret_cast<double *>(lds + Lo.dt);          // [2][PC][T]
@@ -458,9 +488,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // Temperature of level l and the bin-summed output slot of level l: on the
     // sub-layer grid even levels are interfaces and odd levels layer centres.
     const bool sub = a.sub != 0;
+    // the two temperature arrays as values (a per-lane choice between two
+    // argument fields would load the chosen pointer from the argument
+    // segment and wait for it, and with it for every prefetch in flight)
+    const double *const T_if = a.T, *const T_ce = sub ? a.Tc : a.T;
     auto T_at = [&](int l, int cc) -> double {
-        if (sub) return ((l & 1) ? a.Tc : a.T)[(long long)(l >> 1) * C + cc];
-        return a.T[(long long)l * C + cc];
+        const double *base = (sub && (l & 1)) ? T_ce : T_if;
+        return base[(long long)(sub ? (l >> 1) : l) * C + cc];
     };
     auto out_at = [&](double *iface, double *centre, int l, int cc) -> double * {
         if (sub) return ((l & 1) ? centre : iface) + (long long)(l >> 1) * C + cc;
@@ -478,7 +512,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int cc = c0 + kk;
             R v = R(0);
             if (cc < C) {
-                v = planck_edge<R>(a.c2_over_lam[ee] * rcp(Ts[q * K + kk]));
+                v = planck_edge<R>(s_c2[ee] * rcp(Ts[q * K + kk]));
             }
             s_edge[(q * K + kk) * (NBR + 1) + ee] = v;
         }
@@ -491,10 +525,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         R I = planck_combine<R>(row[b], row[b + 1]);
         if constexpr (MIXED) {
             const R iT = rcp(Tr);
-            const R xb = a.c2_over_lam_f[b] * iT, xa = a.c2_over_lam_f[b + 1] * iT;
+            const R xb = s_c2f[b] * iT, xa = s_c2f[b + 1] * iT;
             if (planck_narrow(xa, xb)) {
                 const double iTd = rcp(Td);
-                I = planck_gl3(a.c2_over_lam[b + 1] * iTd, a.c2_over_lam[b] * iTd);
+                I = planck_gl3(s_c2[b + 1] * iTd, s_c2[b] * iTd);
             }
         }
         return R(kPref) * T2 * T2 * I;
@@ -564,19 +598,21 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         return (long long)(ctop(m) - 1 - iq[0]) * LB + toff + il[0];
     };
     auto has_item = [&](int m) { return iq[0] < cn(m) && icol[0]; };
-    auto load_dt = [&](int m) -> double { return has_item(m) ? a.dtau[item_idx(m)] : 0.0; };
-    auto load_wg = [&](int m, double &w, double &g) {
-        w = g = 0.0;
+    auto load_dt = [&](int m) -> InT { return has_item(m) ? in_dt[item_idx(m)] : InT(0); };
+    auto load_wg = [&](int m, InT &w, InT &g) {
+        w = g = InT(0);
         if (has_item(m)) {
             const long long idx = item_idx(m);
-            w = a.w0[idx];
-            g = a.g0[idx];
+            w = in_w[idx];
+            g = in_g[idx];
         }
     };
     auto load_T = [&](int m) -> double {
         return (tq[0] < cn(m) && c0 + tkk[0] < C) ? T_at(ctop(m) - 1 - tq[0], c0 + tkk[0]) : 1.0;
     };
-    auto store_dt = [&](int m, double v) { if (iq[0] < cn(m)) dbuf(m)[iq[0] * T + il[0]] = v; };
+    auto store_dt = [&](int m, InT v) {
+        if (iq[0] < cn(m)) dbuf(m)[iq[0] * T + il[0]] = double(v);
+    };
     auto store_T = [&](int m, double v) { if (tq[0] < cn(m)) tslot(m)[tid] = v; };
 
     // V(m): the carry of chunk m-1's last level into row 0, then this thread's
@@ -599,8 +635,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const double mu = s_mu[kk];
             if (mu > 0.0) {
                 double tau = s_tau[(m & 1) * T + l];
-                for (int qq = 0; qq <= q; ++qq) tau += dt[qq * T + l];   // from the TOA down
-                Fb = beam_at<MIXED>(mu * a.F_star[rb], tau, s_mu[K + kk]);
+                // from the TOA down; the row pointer steps through the rows (a
+                // hoisted address per row would be spilled, and a spill reload
+                // waits for every global load in flight)
+                const double *dp = dt + l;
+#pragma unroll 1
+                for (int qq = 0; qq <= q; ++qq, dp += T) tau += *dp;
+                Fb = beam_at<MIXED>(mu * s_fs[rb], tau, s_mu[K + kk]);
                 if (q == n - 1) s_tau[((m + 1) & 1) * T + l] = tau;
             }
         }
@@ -608,7 +649,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         blockF(m)[(q + 1) * T + l] = Fb;
     };
     // Y(m): this thread's layer item, w0 and g0 from its registers
-    auto layer_items = [&](int m, double w, double g) {
+    auto layer_items = [&](int m, InT wr, InT gr) {
+        const double w = double(wr), g = double(gr);
         const int n = cn(m);
         if (iq[0] >= n) return;
         const int q = iq[0], l = il[0], kk = ikk[0];
@@ -665,10 +707,11 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     R *ebuf_x = s_edge0 + (size_t)2 * PC * K * (NBR + 1);   // T_int edge row
     R *ebuf_n = ebuf_x + (size_t)K * (NBR + 1);             // level N edge row
     const double ftoa = (active && a.Ftoa) ? a.Ftoa[toff + tid] : 0.0;
-    double w_c, g_c, w_n, g_n;   // w0, g0 of this thread's items of the next two Y phases
-    double dt_p, T_p;            // dtau and level temperature loaded ahead, stored later
+    InT w_c, g_c, w_n, g_n;      // w0, g0 of this thread's items of the next two Y phases
+    InT dt_p;                    // dtau loaded ahead, stored later
+    double T_p;                  // level temperature loaded ahead, stored later
     {
-        const double d0 = load_dt(0), d1 = load_dt(1);
+        const InT d0 = load_dt(0), d1 = load_dt(1);
         const double t0 = load_T(0), t1 = load_T(1), t2 = load_T(2);
         load_wg(0, w_c, g_c);
         load_wg(1, w_n, g_n);
@@ -692,6 +735,11 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             s_Ti[kk] = ti;
         }
         for (int b = tid; b < NB; b += W) s_wl[b] = NG == 1 ? 1.0 : a.wg[b % NG];
+        for (int e = tid; e <= NBR; e += W) {
+            s_c2[e] = a.c2_over_lam[e];
+            s_c2f[e] = a.c2_over_lam_f[e];
+            if (e < NBR) s_fs[e] = a.F_star[e];
+        }
         if (tid < T) s_tau[tid] = 0.0;
         store_dt(0, d0);
         store_dt(1, d1);
@@ -721,7 +769,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             }
             R v = R(0);
             if (c0 + kk < C) {
-                v = planck_edge<R>(a.c2_over_lam[ee] * rcp(Ts[kk]));
+                v = planck_edge<R>(s_c2[ee] * rcp(Ts[kk]));
             }
             dst[kk * (NBR + 1) + ee] = v;
         }
@@ -736,7 +784,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             if (!(Tv > 0.0) || !isfinite(Tv)) atomicOr(&s_flag[ikk[0]], (uint32_t)F_INVALID);
             B = bin_B(ebuf_n, 0, ikk[0], irb[0], Tv);
             const double mu = s_mu[ikk[0]];
-            if (mu > 0.0) Fb = mu * a.F_star[irb[0]];
+            if (mu > 0.0) Fb = mu * s_fs[irb[0]];
         }
         blockB(0)[tid] = B;
         blockF(0)[tid] = Fb;
@@ -751,15 +799,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     store_T(3, T_p);
     w_c = w_n;
     g_c = g_n;
+    dt_p = load_dt(3);
+    T_p = load_T(4);
     __syncthreads();
 
     ElimState st = elim_top(ftoa);
     for (int m = 0; m < NCH; ++m) {
         const int s = ctop(m), n = cn(m);
-        // loads for later phases: w0, g0 of Y(m+2), dtau of V(m+3), T of E(m+4)
-        load_wg(m + 2, w_n, g_n);
-        dt_p = load_dt(m + 3);
-        T_p = load_T(m + 4);
         // Z(m)
         if (active) {
             const R *rb0 = rbuf(m);
@@ -793,16 +839,20 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             }
         }
         beam_totals(m);
-        if (m + 1 < NCH) {
-            beam_partials(m + 1);
-            layer_items(m + 1, w_c, g_c);
-        }
-        if (m + 2 < NCH) level_items(m + 2);
+        if (m + 1 < NCH) beam_partials(m + 1);
         if (m + 3 < NCH) edges(ebuf(m + 3), tslot(m + 3), cn(m + 3));
+        if (m + 2 < NCH) level_items(m + 2);
+        // the layer items last, so that their w0, g0 (loaded at the end of the
+        // previous phase) have the rest of this phase to arrive
+        if (m + 1 < NCH) layer_items(m + 1, w_c, g_c);
         store_dt(m + 3, dt_p);   // (after this thread's Y(m+1) read of its dtau)
         store_T(m + 4, T_p);
-        w_c = w_n;
-        g_c = g_n;
+        // loads for later phases, into the registers just freed (no copies
+        // between registers, which would wait for the loads): w0, g0 of
+        // Y(m+2), dtau of V(m+4), T of E(m+5); each has the next phase to land
+        load_wg(m + 2, w_c, g_c);
+        dt_p = load_dt(m + 4);
+        T_p = load_T(m + 5);
         __syncthreads();
     }
 
@@ -1073,32 +1123,33 @@ __device__ __forceinline__ int batch_slot(const int *first, int n, int g)
     return lo;
 }
 
-template <bool MIXED>
+// MIXED: FP32 coefficients; IN32: FP32 storage of dtau, w0, g0 (mixed only)
+template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(kMaxLaneThreads) k_solve_lane(const SolveArgs a)
 {
-    solve_tile_lane<MIXED>(a, blockIdx.x);
+    solve_tile_lane<MIXED, IN32>(a, blockIdx.x);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(kMaxLaneThreads)
 k_solve_lane_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
 {
     const int r = batch_slot(first, n, blockIdx.x);
-    solve_tile_lane<MIXED>(reqs[r], blockIdx.x - first[r]);
+    solve_tile_lane<MIXED, IN32>(reqs[r], blockIdx.x - first[r]);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(layer_max_threads(MIXED)) k_solve_layer(const SolveArgs a)
 {
-    solve_tile_layer<MIXED>(a, blockIdx.x);
+    solve_tile_layer<MIXED, IN32>(a, blockIdx.x);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(layer_max_threads(MIXED))
 k_solve_layer_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
 {
     const int r = batch_slot(first, n, blockIdx.x);
-    solve_tile_layer<MIXED>(reqs[r], blockIdx.x - first[r]);
+    solve_tile_layer<MIXED, IN32>(reqs[r], blockIdx.x - first[r]);
 }
 
 int round64(int x) { return (x + 63) / 64 * 64; }
@@ -1116,17 +1167,19 @@ Geometry lane_geometry(int C, int NB, int K)
     g.lanes = (long long)g.blocks * g.threads;
     const int ch = chunk_for(g.threads, g.K, NB);
     const size_t front = std::max((size_t)3 * ch * g.threads, (size_t)PC * g.K * (NB + 1));
-    g.lds = front * 8 + (size_t)g.K * (ch + 1) * 8 + (size_t)g.K * 4;
+    g.lds = front * 8 + (size_t)g.K * (ch + 1) * 8 + (size_t)(NB + 1) * 8 + (size_t)NB * 8 +
+            (size_t)(NB + 2) * 4 + (size_t)g.K * 4;
     return g;
 }
 
 // Levels per chunk: the most work per barrier that fits LDS, with the items of
 // a chunk (PC x lanes) in at most layer_items_per_thread rounds of the
 // workgroup (each thread prefetches that many items of the next chunk).
-Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev)
+Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev, int NG)
 {
     Geometry g{};
     g.kernel = KERNEL_LAYER;
+    const int NBR = NG > 1 && NB % NG == 0 ? NB / NG : NB;   // bins (Planck edges NBR + 1)
     if (K <= 0) {
         const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
         K = (C + n_cu - 1) / n_cu;             // about one workgroup per compute unit
@@ -1141,7 +1194,7 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     const int it = layer_items_per_thread(mixed);
     for (int pc = 1; pc <= 8; ++pc) {
         if (pc * T > it * wmax) break;
-        const LpLayout lo = lp_layout(K, NB, NB, pc, 1, mixed);
+        const LpLayout lo = lp_layout(K, NB, NBR, pc, 1, mixed);
         if (lo.total > dev.lds) break;
         const int W = std::min(wmax, round64(pc * T));
         const int rounds = (pc * T + W - 1) / W;
@@ -1160,33 +1213,33 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     // interfaces per back-substitution pass: as many as fit in the forward
     // sweep's bytes and in the threads' staging registers
     // (none with wavefront bin sums, which stage no records in LDS)
-    const size_t front = lp_layout(K, NB, NB, g.PC, 1, mixed).total;
+    const size_t front = lp_layout(K, NB, NBR, g.PC, 1, mixed).total;
     const bool ws = layer_wsum(K, NB, g.threads);
     int ch = 1;
-    while (!ws && ch < 16 && lp_layout(K, NB, NB, g.PC, ch + 1, mixed).total <= front &&
+    while (!ws && ch < 16 && lp_layout(K, NB, NBR, g.PC, ch + 1, mixed).total <= front &&
            2 * (ch + 1) * T <= kBackUnits * g.threads)
         ++ch;
     g.CH = ch;
     g.K = K;
     g.blocks = (C + K - 1) / K;
     g.lanes = (long long)g.blocks * T;
-    g.lds = lp_layout(K, NB, NB, g.PC, g.CH, mixed, ws).total;
+    g.lds = lp_layout(K, NB, NBR, g.PC, g.CH, mixed, ws).total;
     return g;
 }
 
 }  // namespace
 
 Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
-                        const DeviceLimits &dev)
+                        const DeviceLimits &dev, int NG)
 {
     Geometry g = (kernel == KERNEL_LANE) ? lane_geometry(C, NB, K)
-                                         : layer_geometry(C, NB, K, precision == 1, dev);
+                                         : layer_geometry(C, NB, K, precision == 1, dev, NG);
     // the default tile of the layer kernel: narrower until its LDS fits
     if (g.threads == 0 && kernel != KERNEL_LANE && K <= 0) {
         const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
         for (int k = std::min((C + n_cu - 1) / n_cu, layer_max_threads(precision == 1) / NB) - 1;
              k >= 1 && g.threads == 0; --k)
-            g = layer_geometry(C, NB, k, precision == 1, dev);
+            g = layer_geometry(C, NB, k, precision == 1, dev, NG);
     }
     if (g.threads > 0)
         g.scratch = (size_t)N * (g.kernel == KERNEL_LANE ? 5 : 4) * (size_t)g.lanes * sizeof(double);
@@ -1196,18 +1249,25 @@ Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
 hipError_t prepare_kernels(const DeviceLimits &dev)
 {
     const int bytes = (int)dev.lds;
-    hipError_t e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer_batch<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-        return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_layer_batch<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&k_solve_layer<false>),
+        reinterpret_cast<const void *>(&k_solve_layer<true>),
+        reinterpret_cast<const void *>(&k_solve_layer<true, true>),
+        reinterpret_cast<const void *>(&k_solve_layer_batch<false>),
+        reinterpret_cast<const void *>(&k_solve_layer_batch<true>),
+        reinterpret_cast<const void *>(&k_solve_layer_batch<true, true>)};
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Kernel variant of a launch: FP64, mixed, or mixed with FP32 input storage.
+enum Variant { V_FP64, V_MIXED, V_MIXED_IN32 };
+static Variant variant(int precision, int in_f32)
+{
+    return precision != 1 ? V_FP64 : (in_f32 ? V_MIXED_IN32 : V_MIXED);
 }
 
 hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hipStream_t s)
@@ -1217,39 +1277,47 @@ hipError_t launch_solve(const SolveArgs &a, const Geometry &g, int precision, hi
     b.PC = g.PC;
     b.CH = g.CH;
     b.L = g.lanes;
-    const bool mixed = precision == 1;
-    if (g.kernel == KERNEL_LANE) {
-        if (mixed)
-            hipLaunchKernelGGL(k_solve_lane<true>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+    const dim3 grid(g.blocks), block(g.threads);
+    switch (variant(precision, a.in_f32)) {
+    case V_FP64:
+        if (g.kernel == KERNEL_LANE) hipLaunchKernelGGL(k_solve_lane<false>, grid, block, g.lds, s, b);
+        else hipLaunchKernelGGL(k_solve_layer<false>, grid, block, g.lds, s, b);
+        break;
+    case V_MIXED:
+        if (g.kernel == KERNEL_LANE) hipLaunchKernelGGL(k_solve_lane<true>, grid, block, g.lds, s, b);
+        else hipLaunchKernelGGL(k_solve_layer<true>, grid, block, g.lds, s, b);
+        break;
+    case V_MIXED_IN32:
+        if (g.kernel == KERNEL_LANE)
+            hipLaunchKernelGGL((k_solve_lane<true, true>), grid, block, g.lds, s, b);
         else
-            hipLaunchKernelGGL(k_solve_lane<false>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
-    } else {
-        if (mixed)
-            hipLaunchKernelGGL(k_solve_layer<true>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
-        else
-            hipLaunchKernelGGL(k_solve_layer<false>, dim3(g.blocks), dim3(g.threads), g.lds, s, b);
+            hipLaunchKernelGGL((k_solve_layer<true, true>), grid, block, g.lds, s, b);
+        break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n, int total_blocks,
-                              const Geometry &g, int precision, hipStream_t s)
+                              const Geometry &g, int precision, int in_f32, hipStream_t s)
 {
-    const bool mixed = precision == 1;
-    if (g.kernel == KERNEL_LANE) {
-        if (mixed)
-            hipLaunchKernelGGL(k_solve_lane_batch<true>, dim3(total_blocks), dim3(g.threads), g.lds,
-                               s, d_reqs, d_first, n);
+    const dim3 grid(total_blocks), block(g.threads);
+    const bool lane = g.kernel == KERNEL_LANE;
+    switch (variant(precision, in_f32)) {
+    case V_FP64:
+        if (lane) hipLaunchKernelGGL(k_solve_lane_batch<false>, grid, block, g.lds, s, d_reqs, d_first, n);
+        else hipLaunchKernelGGL(k_solve_layer_batch<false>, grid, block, g.lds, s, d_reqs, d_first, n);
+        break;
+    case V_MIXED:
+        if (lane) hipLaunchKernelGGL(k_solve_lane_batch<true>, grid, block, g.lds, s, d_reqs, d_first, n);
+        else hipLaunchKernelGGL(k_solve_layer_batch<true>, grid, block, g.lds, s, d_reqs, d_first, n);
+        break;
+    case V_MIXED_IN32:
+        if (lane)
+            hipLaunchKernelGGL((k_solve_lane_batch<true, true>), grid, block, g.lds, s, d_reqs, d_first, n);
         else
-            hipLaunchKernelGGL(k_solve_lane_batch<false>, dim3(total_blocks), dim3(g.threads),
-                               g.lds, s, d_reqs, d_first, n);
-    } else {
-        if (mixed)
-            hipLaunchKernelGGL(k_solve_layer_batch<true>, dim3(total_blocks), dim3(g.threads),
-                               g.lds, s, d_reqs, d_first, n);
-        else
-            hipLaunchKernelGGL(k_solve_layer_batch<false>, dim3(total_blocks), dim3(g.threads),
-                               g.lds, s, d_reqs, d_first, n);
+            hipLaunchKernelGGL((k_solve_layer_batch<true, true>), grid, block, g.lds, s, d_reqs, d_first,
+                               n);
+        break;
     }
     return hipGetLastError();
 }

@@ -17,6 +17,7 @@ LIB_PATH = pathlib.Path(__file__).resolve().parent / "librt_mi355x.so"
 RT_OK, RT_PENDING = 0, 1
 RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EDOMAIN, RT_EBUSY, RT_ENOTFOUND = -1, -2, -3, -4, -5, -6
 RT_FP64, RT_MIXED = 0, 1
+RT_F64, RT_F32 = 0, 1          # storage of dtau, w0, g0 (rt_request.input_dtype)
 RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER, RT_KERNEL_DEEP = 0, 1, 2, 3
 FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
 
@@ -41,7 +42,7 @@ class RtConfig(ct.Structure):
 class RtRequest(ct.Structure):
     _fields_ = [("n_cols", ct.c_int32), ("n_layers", ct.c_int32), ("precision", ct.c_int32),
                 ("cols_per_block", ct.c_int32), ("kernel", ct.c_int32),
-                ("reserved", ct.c_int32)] + [
+                ("input_dtype", ct.c_int32)] + [
         (n, ct.c_void_p) for n in (
             "p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "F_toa",
             "F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin",
@@ -191,13 +192,19 @@ def _shape_of(t) -> tuple:
 
 
 def check_request(inp: dict, out: dict, C: int, N: int, n_bins: int, n_gauss: int,
-                  sub: bool) -> None:
+                  sub: bool, precision: int = RT_FP64) -> int:
     """Check every tensor of a request against the layouts of include/rt.h
     (device, contiguous, dtype, shape) before anything reaches the library,
     which reads and writes them as raw arrays of that size: a wrong dtype or a
-    short tensor would otherwise be read or written past its end.  Raises
-    ValueError."""
+    short tensor would otherwise be read or written past its end.  dtau, w0
+    and g0 may be float32 together on the mixed path (FP32 storage).  Raises
+    ValueError; returns the request's input_dtype."""
     import torch
+    layer_in = ("dtau", "w0", "g0")
+    dts = {inp[k].dtype for k in layer_in if isinstance(inp.get(k), torch.Tensor)}
+    f32 = dts == {torch.float32}
+    if f32 and precision != RT_MIXED:
+        raise ValueError("float32 dtau, w0, g0 need the mixed precision (RT_MIXED)")
     lanes = n_bins * n_gauss
     S = 2 * N if sub else N
     levels = 2 * N + 1 if sub else N + 1
@@ -219,6 +226,8 @@ def check_request(inp: dict, out: dict, C: int, N: int, n_bins: int, n_gauss: in
             if k == "flags":
                 if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
                     raise ValueError(f"flags must be int32 or uint32 (got {t.dtype})")
+            elif f32 and k in layer_in:
+                pass
             elif t.dtype != torch.float64:
                 raise ValueError(f"{k} must be float64 (got {t.dtype})")
             if _shape_of(t) != shape:
@@ -230,6 +239,7 @@ def check_request(inp: dict, out: dict, C: int, N: int, n_bins: int, n_gauss: in
             t = src.get(k)
             if t is not None and (not t.is_cuda or not t.is_contiguous()):
                 raise ValueError(f"{k} must be a contiguous device tensor")
+    return RT_F32 if f32 else RT_F64
 
 
 OUT_NAMES = ("F_up", "F_dn", "F_beam", "F_net", "heating", "dTdt", "F_up_toa_bin", "flags")
@@ -303,7 +313,7 @@ class Solver:
         C = int(inp["mu_star"].shape[0])
         sub = inp.get("T_center") is not None
         N = int(inp["dtau"].shape[0]) // (2 if sub else 1)
-        check_request(inp, out, C, N, self.n_bins, self.n_gauss, sub)
+        dtype = check_request(inp, out, C, N, self.n_bins, self.n_gauss, sub, precision)
         if cols_per_block is None and kernel is None:
             kernel, cols_per_block = tuned_launch(self.n_bins * self.n_gauss, precision, C, N,
                                                   sublayer=sub, n_gauss=self.n_gauss)
@@ -311,6 +321,7 @@ class Solver:
         r.n_cols, r.n_layers, r.precision = C, N, precision
         r.cols_per_block = cols_per_block or 0
         r.kernel = kernel or RT_KERNEL_AUTO
+        r.input_dtype = dtype
 
         def ptr(t):
             return None if t is None else t.data_ptr()
@@ -434,13 +445,15 @@ def tuned_launch(n_bins: int, precision: int, n_cols: int, n_layers: int,
     return kernel, K
 
 
-def to_device(work: dict, device: int = 0) -> dict:
-    """Copy the arrays of a ``synth`` workload to device tensors."""
+def to_device(work: dict, device: int = 0, input_f32: bool = False) -> dict:
+    """Copy the arrays of a ``synth`` workload to device tensors; with
+    ``input_f32`` dtau, w0 and g0 as float32 (mixed-path FP32 storage)."""
     import torch
     dev = torch.device("cuda", device)
     keys = ("p_iface", "T_iface", "dtau", "w0", "g0", "mu_star", "T_int", "T_center", "p_center")
-    d = {k: torch.from_numpy(np.ascontiguousarray(work[k])).to(dev) for k in keys
-         if work.get(k) is not None}
+    d = {k: torch.from_numpy(np.ascontiguousarray(
+            work[k], dtype=np.float32 if input_f32 and k in ("dtau", "w0", "g0") else None)
+         ).to(dev) for k in keys if work.get(k) is not None}
     if work.get("F_toa") is not None:
         d["F_toa"] = torch.from_numpy(np.ascontiguousarray(work["F_toa"])).to(dev)
     return d

@@ -30,23 +30,23 @@ class Opts(ct.Structure):
 
 
 class Args(ct.Structure):
-    _fields_ = [(n, ct.c_int) for n in ('C', 'N', 'NB', 'K', 'PC', 'CH', 'sub', 'NG')] + \
+    _fields_ = [(n, ct.c_int) for n in ('C', 'N', 'NB', 'K', 'PC', 'CH', 'sub', 'in_f32', 'NG')] + \
         [(n, dp) for n in ('c2', 'c2f', 'F_star', 'wg', 'p', 'T', 'dtau', 'w0', 'g0', 'mu', 'Tint', 'Ftoa',
                            'F_up', 'F_dn', 'F_beam', 'F_net', 'heat', 'dTdt', 'F_up_toa_bin', 'F_up_bin',
                            'F_dn_bin', 'flags', 'status', 'Tc', 'pc', 'F_up_c', 'F_dn_c', 'F_beam_c', 'F_net_c',
                            'scratch')] + [('L', ct.c_longlong), ('o', Opts)]
 
 
-def geometry(C, NBG, K, mixed, lds=160 * 1024, ncu=256):
+def geometry(C, NBG, K, mixed, lds=160 * 1024, ncu=256, NG=1):
     v = (ct.c_int * 7)()
-    lib().emu_geometry(C, NBG, K, int(mixed), lds, ncu, v)
+    lib().emu_geometry(C, NBG, K, int(mixed), lds, ncu, v, NG)
     return dict(K=v[0], PC=v[1], CH=v[2], threads=v[3], blocks=v[4], lds=v[5], lanes=v[6])
 
 
 def solve(w, mixed, K=0, opts=None, lds=160 * 1024, ncu=256, per_bin=True):
     """The layer kernel on the host."""
     NG = int(w.get('n_gauss', 1)) if w.get('gauss_w') is not None else 1
-    g = geometry(w['n_cols'], w['n_bins'] * NG, K, mixed, lds, ncu)
+    g = geometry(w['n_cols'], w['n_bins'] * NG, K, mixed, lds, ncu, NG)
     S = 2 * w['n_layers'] if w.get('T_center') is not None and w.get('sublayer', False) else w['n_layers']
     scratch = np.full(S * 4 * g['lanes'], np.nan)
     out, a, keep = _args(w, opts, per_bin, scratch.ctypes.data)
@@ -127,7 +127,7 @@ def _args(w, opts, per_bin, scratch_ptr):
     if sub:
         for k in ('F_up_center', 'F_dn_center', 'F_beam_center', 'F_net_center'):
             out[k] = np.zeros((N, C))
-    a = Args(C, S, NBG, 0, 0, 0, int(sub), NG, P(c2), P(c2.astype(np.float32)), P(w['F_star']), P(gw),
+    a = Args(C, S, NBG, 0, 0, 0, int(sub), 0, NG, P(c2), P(c2.astype(np.float32)), P(w['F_star']), P(gw),
              P(w['p_iface']), P(w['T_iface']), P(w['dtau']), P(w['w0']), P(w['g0']), P(w['mu_star']),
              P(w['T_int']), P(w.get('F_toa')), out['F_up'].ctypes.data, out['F_dn'].ctypes.data,
              out['F_beam'].ctypes.data, out['F_net'].ctypes.data, out['heating'].ctypes.data,

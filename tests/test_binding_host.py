@@ -28,9 +28,9 @@ def host_request(C=5, N=4, NB=3, sub=False):
     return inp, out
 
 
-def rejects(inp, out, msg, C=5, N=4, NB=3, NG=1, sub=False):
+def rejects(inp, out, msg, C=5, N=4, NB=3, NG=1, sub=False, precision=rt.RT_FP64):
     with pytest.raises(ValueError, match=msg):
-        rt.check_request(inp, out, C, N, NB, NG, sub)
+        rt.check_request(inp, out, C, N, NB, NG, sub, precision)
 
 
 def test_float32_inputs_rejected():
@@ -40,6 +40,19 @@ def test_float32_inputs_rejected():
     for k in ("dtau", "w0", "g0", "p_iface", "mu_star"):
         bad = dict(inp, **{k: inp[k].float()})
         rejects(bad, out, f"{k} must be float64")
+
+
+def test_float32_storage_of_layer_inputs():
+    """dtau, w0 and g0 all float32 is the mixed path's FP32 input storage
+    (RT_F32): accepted with RT_MIXED (the host request then stops only at the
+    device check), refused with RT_FP64; one of them alone stays an error."""
+    inp, out = host_request()
+    f32 = dict(inp, **{k: inp[k].float() for k in ("dtau", "w0", "g0")})
+    rejects(f32, out, "need the mixed precision")
+    rejects(f32, out, "contiguous device tensor", precision=rt.RT_MIXED)
+    rejects(dict(f32, p_iface=inp["p_iface"].float()), out, "p_iface must be float64",
+            precision=rt.RT_MIXED)
+    rejects(dict(inp, w0=inp["w0"].float()), out, "w0 must be float64", precision=rt.RT_MIXED)
 
 
 def test_short_or_misshaped_tensors_rejected():

@@ -192,6 +192,35 @@ def test_edge_cases(rt, torch, kernel):
         np.testing.assert_array_equal(out["flags"], ref["flags"])
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_mixed_fp32_input_storage(rt, torch, kernel):
+    """input_dtype RT_F32: dtau, w0, g0 stored as floats on the mixed path.
+    The oracle solves the same stored values (each float as the double it is)
+    and the mixed bar applies; the flags match exactly, since the branch
+    decisions see the stored floats.  The FP64 path refuses float inputs."""
+    cases = [("cfg0", synth.make("cfg0")), ("edges", edge_workload()),
+             ("deep", small(C=4, N=120, NB=10, seed=17)), ("bins300", small(C=3, N=6, NB=300, seed=16))]
+    for name, w in cases:
+        print(f"\n[parity] fp32 inputs {name} kernel={kernel}", flush=True)
+        w32 = dict(w)
+        for k in ("dtau", "w0", "g0"):
+            w32[k] = np.ascontiguousarray(w[k].astype(np.float32).astype(np.float64))
+        ref = O.solve(w32, per_bin=True, extended=True)
+        s = rt.Solver(w["lambda_edges"], w["F_star"])
+        inp = rt.to_device(w, input_f32=True)
+        assert inp["dtau"].dtype == torch.float32
+        out = s.solve(inp, precision=rt.RT_MIXED, per_bin=True, kernel=kernel)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        got["flags"] = got["flags"].view(np.uint32)
+        e = assert_close(got, ref, w["p_iface"], MIXED_TOL, floor=FLOOR[1], floor_bin=FLOOR_BIN[1])
+        print(f"  errors={e}", flush=True)
+        np.testing.assert_array_equal(got["flags"], ref["flags"])
+        with pytest.raises(ValueError):
+            s.solve(inp, precision=rt.RT_FP64, kernel=kernel)
+        s.close()
+
+
 def test_strict_mode_flags_edomain(rt, torch):
     w = edge_workload()
     opts = O.Options(e_clamp=0)
