@@ -7,9 +7,12 @@ resident in HBM.  Default: FP64; the mixed-precision path is timed the same
 way and reported beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
+                  [--no-serving] [--no-cfg4]
 
-Prints ONE JSON line (see the field list in the design notes).  Only the
-``cpu_baseline`` leg runs the CPU oracle.
+Prints ONE JSON line.  Besides the headline FP64 figure and the mixed path
+beside it, the default run adds the serving mix (saturation, then p50/p99 at
+50 % and 80 % of it) and the 10242 x 80 x 300 high-resolution solve.  Only
+the ``cpu_baseline`` leg runs the CPU oracle.
 """
 from __future__ import annotations
 
@@ -70,10 +73,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _profiled(kernel: str) -> dict | None:
-    """The committed PMC summary of a kernel at 2562x40x30, if it was taken on
-    the current kernel sources."""
-    f = ROOT / "profiles" / "traffic_cfg1.json"
+def _profiled(kernel: str, workload: str = "cfg1") -> dict | None:
+    """The committed PMC summary of a kernel on a workload (2562x40x30 by
+    default), if it was taken on the current kernel sources."""
+    f = ROOT / "profiles" / f"traffic_{workload}.json"
     if not f.exists():
         return None
     d = json.loads(f.read_text())
@@ -82,9 +85,9 @@ def _profiled(kernel: str) -> dict | None:
     return d.get("kernels", {}).get(kernel)
 
 
-def traffic_from_profiles(kernel: str) -> float | None:
+def traffic_from_profiles(kernel: str, workload: str = "cfg1") -> float | None:
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size)."""
-    k = _profiled(kernel)
+    k = _profiled(kernel, workload)
     return None if k is None else float(k["bytes_per_launch"])
 
 
@@ -135,28 +138,70 @@ def pct(v, q):
     return v[i]
 
 
-def cpu_baseline(work, seconds: float = 10.0) -> tuple[dict, dict]:
-    """The CPU oracle as it stands, timed on this host on whole solves of the
-    benchmark workload repeated for about `seconds` (all host threads).
-    Returns the timing and the oracle's outputs of the last solve."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+
+
+def time_oracle(work: dict, threads: int, runs: int) -> tuple[list, dict]:
+    """Wall times of `runs` whole solves of `work` by the oracle on `threads`
+    OpenMP threads (after one warm-up on a few columns), and the last result."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     run = oracle.solve_sublayer if work.get("sublayer") else oracle.solve
-    run(work, n_threads=threads, cols=(0, 64))   # load and warm
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    run(work, n_threads=threads, cols=(0, 16))
+    times, ref = [], None
+    for _ in range(runs):
+        t0 = time.perf_counter()
         ref = run(work, n_threads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    nbg = work["n_bins"] * work.get("n_gauss", 1)
-    cb = work["n_cols"] * nbg * reps
-    shape = f"{work['n_cols']}x{work['n_layers']}x{nbg}"
-    return ({"value": cb / el, "unit": "column·bin solves/s", "cores": threads,
-             "kind": "oracle",
-             "sample": f"{reps} whole FP64 solves of the {shape} workload in {el:.1f} s "
-                       f"on {threads} OpenMP threads"}, ref)
+        times.append(time.perf_counter() - t0)
+    return times, ref
+
+
+def cpu_baseline(work, small: dict | None = None, runs: int = 5) -> tuple[dict, dict]:
+    """The CPU oracle as it stands, timed on this host's cores: the median of
+    `runs` whole FP64 solves of the benchmark workload on one thread and on all
+    host threads, and the same for the small workload `small` if given.  The
+    mixed-precision path has the same inputs and the same FP64 reference, so
+    its CPU baseline is this one.  Returns the timing block (headline value: all
+    threads on the benchmark workload) and the oracle's outputs of the last
+    all-thread solve."""
+    threads = host_threads()
+    nbg = lambda w: w["n_bins"] * w.get("n_gauss", 1)
+    shape = lambda w: f"{w['n_cols']}x{w['n_layers']}x{nbg(w)}"
+    per = {}
+    ref = None
+    for tag, w in (("small", small), ("workload", work)):
+        if w is None:
+            continue
+        entry = {"shape": shape(w)}
+        for nt in sorted({1, threads}):
+            ts, r = time_oracle(w, nt, runs)
+            med = float(np.median(ts))
+            entry[f"{nt}_threads"] = {"median_s": med, "runs_s": ts,
+                                      "value": w["n_cols"] * nbg(w) / med}
+            if tag == "workload" and nt == threads:
+                ref = r
+        per[tag] = entry
+        print(f"[bench] cpu baseline {entry['shape']}: " + ", ".join(
+            f"{k} {v['median_s']:.3f} s" for k, v in entry.items() if k != "shape"),
+            file=sys.stderr, flush=True)
+    head = per["workload"][f"{threads}_threads"]
+    return ({"value": head["value"], "unit": "column·bin solves/s", "cores": threads,
+             "kind": "oracle", "cpu_model": cpu_model(),
+             "sample": f"median of {runs} whole FP64 solves of the {per['workload']['shape']} "
+                       f"workload on {threads} OpenMP threads (the mixed path shares its "
+                       f"inputs and reference); single-thread and small-workload runs under "
+                       f"'runs'",
+             "runs": per}, ref)
 
 
 def column_subset(work: dict, cols: np.ndarray) -> dict:
@@ -191,10 +236,12 @@ def error_stats(got: dict, ref: dict, p_iface: np.ndarray, gravity: float = 47.0
 
 def serving(args, torch, rt, synth) -> dict:
     """Serving mix: uneven requests (columns U{1..4096}, layers U{20..120}, bins in
-    {30, 100, 300}, cloud fraction U[0, 0.5]) arriving as a Poisson process,
-    half FP64 and half mixed, through rt_submit/rt_poll.  Inputs stay resident
-    on the device; one handle per spectral set-up.  Latency = completion time
-    (seen by polling) minus arrival time."""
+    {30, 100, 300}, cloud fraction U[0, 0.5]) through rt_submit/rt_poll, half
+    FP64 and half mixed, inputs resident on the device, one handle per spectral
+    set-up.  First the saturation rate (every request submitted at time 0), then
+    Poisson arrivals at the stated fractions of it.  Latency = completion time
+    (seen by polling) minus arrival time.  Every output slot's last result of a
+    run is compared with the same request solved alone (bitwise)."""
     shapes = synth.serving_requests(args.serve_pool, seed=1003, max_cols=4096)
     pool, solvers = [], {}
     for k, sh in enumerate(shapes):
@@ -205,28 +252,34 @@ def serving(args, torch, rt, synth) -> dict:
                                     hbm_budget_bytes=args.serve_budget_gib << 30)
         pool.append(dict(nb=nb, inp=rt.to_device(w), C=w["n_cols"], N=w["n_layers"],
                          prec=rt.RT_FP64 if k % 2 == 0 else rt.RT_MIXED))
+        del w
     torch.cuda.synchronize()
-    # warm each request once (also gives its stand-alone latency)
+    # each request once alone (the reference of the bitwise check)
     for q in pool:
         s = solvers[q["nb"]]
         q["out"] = [s.outputs(q["C"], q["N"]) for _ in range(args.serve_copies)]
         s.solve(q["inp"], precision=q["prec"], out=q["out"][0])
-    torch.cuda.synchronize()
-    results = []
-    for rate in args.serve_rates:
-        arrivals = synth.poisson_arrivals(args.serve_requests, rate, seed=int(rate))
-        order = np.random.Generator(np.random.PCG64(int(rate) + 1)).integers(
-            0, len(pool), args.serve_requests)
+        torch.cuda.synchronize()
+        q["alone"] = {k: q["out"][0][k].cpu().numpy() for k in ("F_net", "heating")}
+        q["used"] = [False] * args.serve_copies
+
+    def run(rate):
+        """One run of serve_requests requests; rate None: all arrive at once."""
+        n = args.serve_requests
+        arrivals = (np.zeros(n) if rate is None
+                    else synth.poisson_arrivals(n, rate, seed=int(rate)))
+        order = np.random.Generator(np.random.PCG64(7 if rate is None else int(rate) + 1)
+                                    ).integers(0, len(pool), n)
         busy = [[False] * args.serve_copies for _ in pool]
         inflight, lat, cb = {}, [], 0
         t0 = time.perf_counter()
         i = 0
-        while i < len(arrivals) or inflight:
+        while i < n or inflight:
             now = time.perf_counter() - t0
-            while i < len(arrivals) and arrivals[i] <= now:
+            while i < n and arrivals[i] <= now:
                 q = pool[order[i]]
                 slot = next((m for m in range(args.serve_copies) if not busy[order[i]][m]), None)
-                if slot is None:      # all output copies of this request busy: wait
+                if slot is None:      # every output copy of this request is busy: wait
                     break
                 busy[order[i]][slot] = True
                 t = solvers[q["nb"]].submit(q["inp"], q["out"][slot], q["prec"])
@@ -238,18 +291,71 @@ def serving(args, torch, rt, synth) -> dict:
                     arr, qi, slot = inflight.pop(key)
                     lat.append(time.perf_counter() - t0 - arr)
                     busy[qi][slot] = False
+                    pool[qi]["used"][slot] = True
                     cb += pool[qi]["C"] * pool[qi]["nb"]
         el = time.perf_counter() - t0
-        results.append({"rate_hz": rate, "requests": len(lat),
-                        "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3,
-                        "solves_per_s": cb / el, "seconds": el})
-        print(f"[bench] serving rate {rate}/s: p50 {results[-1]['p50_ms']:.2f} ms "
-              f"p99 {results[-1]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        checked = equal = 0
+        for q in pool:
+            for m, used in enumerate(q["used"]):
+                if used:
+                    checked += 1
+                    equal += all(np.array_equal(q["out"][m][k].cpu().numpy(), q["alone"][k])
+                                 for k in ("F_net", "heating"))
+                q["used"][m] = False
+        return {"rate_hz": None if rate is None else rate, "requests": len(lat),
+                "requests_per_s": len(lat) / el, "p50_ms": pct(lat, 50) * 1e3,
+                "p99_ms": pct(lat, 99) * 1e3, "solves_per_s": cb / el, "seconds": el,
+                "results_checked": checked, "results_equal_alone": equal}
+
+    sat = run(None)
+    print(f"[bench] serving saturation {sat['requests_per_s']:.0f} requests/s, "
+          f"{sat['solves_per_s'] / 1e6:.0f} M solves/s", file=sys.stderr, flush=True)
+    results = []
+    for f in args.serve_load:
+        r = run(f * sat["requests_per_s"])
+        r["load"] = f
+        results.append(r)
+        print(f"[bench] serving at {f:.0%} of saturation ({r['rate_hz']:.0f}/s): p50 "
+              f"{r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms, {r['solves_per_s'] / 1e6:.0f} M "
+              f"solves/s", file=sys.stderr, flush=True)
     for s in solvers.values():
         s.close()
-    return {"pool": len(pool), "mix": "columns U{1..4096}, layers U{20..120}, bins {30,100,300}, "
-                                      "cloud fraction U[0,0.5], half FP64 / half mixed",
-            "rates": results}
+    return {"pool": len(pool),
+            "mix": "columns U{1..4096}, layers U{20..120}, bins {30,100,300}, cloud fraction "
+                   "U[0,0.5], half FP64 / half mixed",
+            "requests_per_run": args.serve_requests, "saturation": sat, "rates": results}
+
+
+def high_resolution(args, torch, rt, synth) -> dict:
+    """The 10242 x 80 x 300 workload (FP64 and mixed, the kernel and tile the
+    library picks): time per solve and the HBM roofline fraction."""
+    work = synth.make("cfg4")
+    C, N, NB = work["n_cols"], work["n_layers"], work["n_bins"]
+    s = rt.Solver(work["lambda_edges"], work["F_star"])
+    inp = rt.to_device(work)
+    del work
+    out = s.outputs(C, N)
+    steps = max(3, min(args.steps, 10))
+    res = {"workload": WORKLOADS["cfg4"], "n_cols": C, "n_layers": N, "n_bins": NB,
+           "steps": steps}
+    abytes = algorithmic_bytes(C, N, NB)
+    for prec, tag in ((rt.RT_FP64, "fp64"), (rt.RT_MIXED, "mixed")):
+        kid = s.kernel_for(inp, out, prec)
+        kname = KERNEL_NAMES[kid] + ("<true>" if prec == rt.RT_MIXED else "<false>")
+        print(f"[bench] cfg4 {tag} ({kname})", file=sys.stderr, flush=True)
+        _, tot, per = time_path(s, inp, out, prec, steps, 2, torch)
+        ms = tot / steps
+        ach = abytes / (ms * 1e-3) / 1e9
+        res[tag] = {"ms_per_step": ms, "value": C * NB / (ms * 1e-3), "kernel": kname,
+                    "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "algorithmic_bytes": abytes,
+                                 "traffic": traffic_from_profiles(kname, "cfg4")}}
+    s.close()
+    del inp, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -259,18 +365,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-runs", type=int, default=5,
+                    help="whole oracle solves per CPU timing (median reported)")
     ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=sorted(KERNEL_IDS),
                     help="solve kernel of the headline line (auto: tuned choice)")
     ap.add_argument("--compare-kernels", action="store_true",
                     help="also time both kernels at their default tiles")
-    ap.add_argument("--serving", action="store_true", help="also run the serving mix")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving mix")
+    ap.add_argument("--no-cfg4", action="store_true",
+                    help="skip the 10242 x 80 x 300 high-resolution solve")
     ap.add_argument("--serve-pool", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-copies", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=32)
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[50.0, 200.0])
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.5, 0.8],
+                    help="Poisson arrival rates as fractions of the measured saturation")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 5 device-to-device copies of this many bytes (calibrates "
                          "the HBM byte counters against a kernel of known traffic)")
@@ -381,12 +491,19 @@ def main():
                 cmp[f"{kn}:{tag}"] = t / args.steps
         line["kernels_ms"] = cmp
     s.close()
-    if args.serving:
+    del inp, out
+    torch.cuda.empty_cache()
+    default = WORKLOAD == "cfg1"
+    if default and not args.no_serving:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         line["serving"] = serving(args, torch, rt, synth)
+        torch.cuda.empty_cache()
+    if default and not args.no_cfg4:
+        line["cfg4"] = high_resolution(args, torch, rt, synth)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"], ref = cpu_baseline(work, args.cpu_seconds)
+        small = synth.make("cfg0") if default else None
+        line["cpu_baseline"], ref = cpu_baseline(work, small, args.cpu_runs)
         if not work.get("sublayer") and work.get("n_gauss", 1) == 1:
             # the timed solves' errors against the oracle's result (all columns), and
             # against its binary128 build on every 10th column (the FP64 oracle's own

@@ -8,8 +8,16 @@ from paper_2203_02293_amd import synth
 
 def test_cpu_baseline_returns_timing_and_outputs():
     w = synth.make("cfg0")
-    t, ref = bench.cpu_baseline(w, 0.2)
+    small = bench.column_subset(w, np.arange(0, w["n_cols"], 8))
+    t, ref = bench.cpu_baseline(w, small, runs=2)
     assert t["kind"] == "oracle" and t["value"] > 0 and t["cores"] >= 1
+    # single-thread and all-thread medians on both workloads
+    for tag in ("small", "workload"):
+        runs = t["runs"][tag]
+        for nt in {1, t["cores"]}:
+            r = runs[f"{nt}_threads"]
+            assert len(r["runs_s"]) == 2 and r["median_s"] == np.median(r["runs_s"])
+    assert t["value"] == t["runs"]["workload"][f"{t['cores']}_threads"]["value"]
     C, N = w["n_cols"], w["n_layers"]
     assert ref["F_net"].shape == (N + 1, C) and ref["heating"].shape == (N, C)
     np.testing.assert_array_equal(ref["F_net"], ref["F_up"] - ref["F_dn"] - ref["F_beam"])
@@ -17,7 +25,7 @@ def test_cpu_baseline_returns_timing_and_outputs():
 
 def test_error_stats_scaling():
     w = synth.make("cfg0")
-    _, ref = bench.cpu_baseline(w, 0.0)
+    _, ref = bench.cpu_baseline(w, None, runs=1)
     keys = ("F_up", "F_dn", "F_beam", "F_net", "heating")
     same = bench.error_stats({k: ref[k].copy() for k in keys}, ref, w["p_iface"])
     assert all(v == 0.0 for d in same.values() for v in d.values())
