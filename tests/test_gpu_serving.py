@@ -74,6 +74,56 @@ def test_mix_equals_alone(rt, torch, nb, precision, kernel):
     s.close()
 
 
+def test_serving_mix_shapes_equal_alone(rt, torch):
+    """The serving mix's own request shapes (columns U{1..4096}, layers
+    U{20..120}, bins in {30, 100, 300}, cloud fraction U[0, 0.5]) plus two few
+    deep-column requests that AUTO sends to the deep kernel, FP64 and mixed
+    alternating, submitted together on one handle per bin set so that they
+    overlap on the device: every result equals the same request solved alone
+    through rt_solve_fluxes, bit for bit."""
+    shapes = synth.serving_requests(8, seed=2024, max_cols=4096)
+    shapes += [dict(n_cols=3, n_layers=110, n_bins=30, cloud_fraction=0.4, seed=99),
+               dict(n_cols=60, n_layers=100, n_bins=100, cloud_fraction=0.2, seed=98)]
+    assert {sh["n_bins"] for sh in shapes} == {30, 100, 300}
+    assert max(sh["n_cols"] for sh in shapes) > 3000
+    solvers, jobs = {}, []
+    for k, sh in enumerate(shapes):
+        w = synth.make_request(sh)
+        nb = w["n_bins"]
+        if nb not in solvers:
+            solvers[nb] = rt.Solver(w["lambda_edges"], w["F_star"], max_inflight=64,
+                                    hbm_budget_bytes=16 << 30)
+        jobs.append(dict(nb=nb, inp=rt.to_device(w), C=w["n_cols"], N=w["n_layers"],
+                         prec=k % 2))
+        del w
+    kernels = set()
+    for j in jobs:
+        s = solvers[j["nb"]]
+        j["kernel"] = s.kernel_for(j["inp"], s.outputs(j["C"], j["N"]), j["prec"])
+        kernels.add(j["kernel"])
+        print(f"\n[serving] mix request {j['C']}x{j['N']}x{j['nb']} precision={j['prec']} "
+              f"kernel={j['kernel']}", flush=True)
+        o = s.solve(j["inp"], precision=j["prec"])
+        torch.cuda.synchronize()
+        j["alone"] = host(o)
+        del o
+    assert rt.RT_KERNEL_DEEP in kernels and rt.RT_KERNEL_LAYER in kernels
+    for j in jobs:
+        j["out"] = solvers[j["nb"]].outputs(j["C"], j["N"])
+    torch.cuda.synchronize()
+    for j in jobs:
+        j["ticket"] = solvers[j["nb"]].submit(j["inp"], j["out"], j["prec"])
+    for j in reversed(jobs):
+        assert solvers[j["nb"]].wait(j["ticket"]) == rt.RT_OK
+    for j in jobs:
+        b = host(j["out"])
+        for k in j["alone"]:
+            np.testing.assert_array_equal(j["alone"][k], b[k],
+                                          err_msg=f"{k} of {j['C']}x{j['N']}x{j['nb']}")
+    for s in solvers.values():
+        s.close()
+
+
 def test_small_budget_queues(rt, torch):
     """A budget that fits one request at a time: all requests still finish,
     in any order, each with the stand-alone result."""
