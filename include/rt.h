@@ -43,6 +43,12 @@ typedef int32_t rt_status;
 #define RT_MIXED 1   /* FP32 coefficients, exponentials and Planck integrals; FP64
                         predicates, optical-depth sums and Thomas elimination     */
 
+/* how the serving path (rt_submit) runs admitted requests (rt_config.serve_mode) */
+#define RT_SERVE_BATCHED    0   /* requests admitted together share one launch      */
+#define RT_SERVE_PERSISTENT 1   /* a resident worker takes tiles of any admitted
+                                   request as it frees up (layer-kernel requests
+                                   with FP64 input storage; others run batched)    */
+
 /* storage of the per-layer inputs dtau, w0, g0 (rt_request.input_dtype) */
 #define RT_F64 0     /* doubles                                                     */
 #define RT_F32 1     /* floats: RT_MIXED only (the FP64 path keeps its inputs exact) */
@@ -102,7 +108,8 @@ typedef struct {
                                      (bin, g) pair is solved with its bin's Planck
                                      function and stellar flux, and bin sums are
                                      sum_b sum_g w_g F.  NB * NG <= 768.           */
-    int32_t reserved;             /* must be 0 */
+    int32_t serve_mode;           /* serving path: RT_SERVE_BATCHED (0) or
+                                     RT_SERVE_PERSISTENT (see rt_submit)            */
     const double *gauss_weights;  /* HOST [NG] weights w_g > 0 (NULL if NG <= 1)   */
 } rt_config;
 
@@ -229,7 +236,18 @@ int32_t rt_request_kernel(rt_handle *h, const rt_request *req);
  * its request and column tile in a descriptor table), up to 64 per launch; a
  * request on the deep kernel runs as its own launch sequence; 16 batches in
  * flight on 4 library-owned streams.  Results equal those of rt_solve_fluxes
- * (same request) bit for bit.  Requests retire in any order.  The inputs must
+ * (same request) bit for bit.  With serve_mode = RT_SERVE_PERSISTENT, a
+ * request that runs on the layer kernel with FP64 input storage goes instead
+ * to a resident worker (one workgroup per compute unit, launched by the
+ * library when work is waiting and ending by itself about a millisecond after
+ * the last tile): the request's tiles are published to a ring in pinned host
+ * memory as soon as a request slot (4096 per worker lifetime), ring space
+ * (65536 tiles) and budget memory are free, and any idle workgroup takes the
+ * next tile, so tiles of different requests and precisions share the device
+ * without a launch per batch.  Its tile is the worker's (512 threads, the
+ * LDS less 256 bytes), so its results equal those of the
+ * same request on the worker, alone or in any mix, bit for bit, and those of
+ * rt_solve_fluxes to the precision's tolerance.  Requests retire in any order.  The inputs must
  * be complete on the device before the call (the library's streams do not wait
  * on the caller's), and the request's buffers must stay valid, and must not be
  * touched, until rt_poll/rt_wait returns something other than RT_PENDING.  Errors:

@@ -16,7 +16,9 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <chrono>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -85,6 +87,27 @@ struct Job {
     rt_request req;
     rtk::Geometry g;           // launch shape of this request
     size_t bytes = 0, off = 0; // reservation in the serving arena
+};
+
+// Persistent serving: ring of published tiles, ring of request slots, and the
+// worker's idle bound (polls of about 1-3 us each before it exits).  The
+// worker reads a slot with scalar loads, whose cache the host cannot
+// invalidate: so a slot is never rewritten during one worker lifetime (slots
+// are taken in sequence; a request whose slot was last used by a request
+// still running at the worker's launch waits for the next lifetime).
+constexpr int kRingCap = 1 << 16;
+constexpr int kSlotRing = 4096;
+constexpr int kIdlePolls = 400;
+
+// A request admitted to the persistent worker: its slot and its tiles
+// [first, first + ntiles) of the ring; tiles before `seen` have completed.
+struct PJob {
+    Job j;
+    uint64_t seq = 0;   // slot sequence number (slot = seq % kSlotRing)
+    int slot = 0;
+    uint64_t first = 0;
+    int ntiles = 0, seen = 0;
+    uint32_t bits = 0;
 };
 
 constexpr int kMaxBatch = 64;  // requests per batched launch
@@ -165,6 +188,24 @@ struct rt_handle {
     Batch slots[kSlots];
     std::map<uint64_t, int> running;          // ticket -> batch slot
     std::map<uint64_t, rt_status> finished;   // retired on first poll
+    // persistent serving (serve_mode RT_SERVE_PERSISTENT)
+    rtk::WorkQueueHost *wq = nullptr;         // pinned host memory: control words
+    rtk::WorkTile *wring = nullptr;           // [kRingCap]
+    rtk::SlotArgs *wslots = nullptr;          // [kSlotRing]
+    unsigned int *wdone = nullptr;            // [kRingCap] completion words
+    rtk::WorkerArgs wargs{};                  // device-side view of the above
+    unsigned long long *d_head = nullptr;     // device: tiles claimed
+    unsigned int *d_wgst = nullptr;           // device: per-workgroup condition bits
+    unsigned int *d_exiting = nullptr;        // device: the worker is idling out
+    hipStream_t wstream = nullptr;
+    hipEvent_t wevent = nullptr;              // recorded after each worker launch
+    bool wlaunched = false;
+    bool wbroken = false;                     // a worker launch failed: requests go batched
+    uint64_t wpublished = 0;                  // tiles published
+    uint64_t wseq = 0;                        // slots taken
+    uint64_t wgen = 0;                        // oldest slot the running worker may read
+    std::deque<Job> pqueued;                  // waiting for the worker
+    std::map<uint64_t, PJob> prunning;        // admitted to the worker
 };
 
 // Device allocation that leaves no error behind: a failed hipMalloc also sets
@@ -274,7 +315,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_handle **out)
         if (!(cfg->stellar_flux[b] >= 0.0) || !std::isfinite(cfg->stellar_flux[b])) return RT_EINVAL;
     if (!(cfg->eps2 > 0.0) || !(cfg->e_tau >= 0.0) || !(cfg->g_guard >= 0.0) ||
         !(cfg->gravity > 0.0) || !(cfg->cp > 0.0) || cfg->hbm_budget_bytes < 0 ||
-        cfg->max_inflight < 0 || cfg->n_gauss < 0 || cfg->reserved != 0)
+        cfg->max_inflight < 0 || cfg->n_gauss < 0 ||
+        (cfg->serve_mode != RT_SERVE_BATCHED && cfg->serve_mode != RT_SERVE_PERSISTENT))
         return RT_EINVAL;
     const int NG = cfg->n_gauss > 1 ? cfg->n_gauss : 1;
     if ((long long)NB * NG > kMaxBinPoints) return RT_EINVAL;
@@ -356,6 +398,20 @@ extern "C" rt_status rt_destroy(rt_handle *h)
 {
     if (!h) return RT_OK;
     (void)hipSetDevice(h->cfg.device);
+    if (h->wlaunched) {
+        // the worker exits once nothing is left to claim (or after its idle bound)
+        __atomic_store_n(&h->wq->stop, 1u, __ATOMIC_RELEASE);
+        (void)hipEventSynchronize(h->wevent);
+    }
+    if (h->wevent) (void)hipEventDestroy(h->wevent);
+    if (h->wstream) (void)hipStreamDestroy(h->wstream);
+    if (h->wq) (void)hipHostFree(h->wq);
+    if (h->wring) (void)hipHostFree(h->wring);
+    if (h->wslots) (void)hipHostFree(h->wslots);
+    if (h->wdone) (void)hipHostFree(h->wdone);
+    (void)hipFree(h->d_head);
+    (void)hipFree(h->d_exiting);
+    (void)hipFree(h->d_wgst);
     for (auto &s : h->streams)
         if (s) (void)hipStreamSynchronize(s);
     (void)hipDeviceSynchronize();
@@ -690,6 +746,66 @@ static rt_status ensure_serving(rt_handle *h)
     return RT_OK;
 }
 
+// Pinned host memory that the GPU reads and writes coherently; *dev is the
+// device's address of it.
+template <class T>
+static bool host_coherent(T **host, T **dev, size_t n)
+{
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sizeof(T) * n, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::memset(p, 0, sizeof(T) * n);
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p);
+        return false;
+    }
+    *host = static_cast<T *>(p);
+    *dev = static_cast<T *>(d);
+    return true;
+}
+
+// The persistent worker's buffers (once per handle).
+static rt_status ensure_worker(rt_handle *h)
+{
+    if (h->wq) return RT_OK;
+    rtk::WorkerArgs &w = h->wargs;
+    rtk::WorkQueueHost *q = nullptr, *qd = nullptr;
+    rtk::WorkTile *ring = nullptr, *ringd = nullptr;
+    rtk::SlotArgs *slots = nullptr, *slotsd = nullptr;
+    unsigned int *done = nullptr, *doned = nullptr;
+    if (!host_coherent(&q, &qd, 1)) return fail(h, RT_ENOMEM, "worker control words");
+    h->wq = q;
+    if (!host_coherent(&ring, &ringd, kRingCap)) return fail(h, RT_ENOMEM, "worker tile ring");
+    h->wring = ring;
+    if (!host_coherent(&slots, &slotsd, kSlotRing)) return fail(h, RT_ENOMEM, "worker request slots");
+    h->wslots = slots;
+    if (!host_coherent(&done, &doned, kRingCap)) return fail(h, RT_ENOMEM, "worker completion words");
+    h->wdone = done;
+    if (!dev_alloc((void **)&h->d_head, sizeof(unsigned long long)) ||
+        !dev_alloc((void **)&h->d_exiting, sizeof(unsigned int)) ||
+        !dev_alloc((void **)&h->d_wgst, sizeof(unsigned int) * (size_t)std::max(h->dev.n_cu, 1)))
+        return fail(h, RT_ENOMEM, "worker counters");
+    if (hipMemset(h->d_head, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->wstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->wevent, hipEventDisableTiming) != hipSuccess)
+        return fail(h, RT_EDEVICE, "worker stream");
+    w.q = qd;
+    w.ring = ringd;
+    w.slots = slotsd;
+    w.done = doned;
+    w.head = h->d_head;
+    w.wg_status = h->d_wgst;
+    w.exiting = h->d_exiting;
+    w.ring_cap = kRingCap;
+    w.idle_polls = kIdlePolls;
+    w.lds_top = (int)(h->dev.lds - rtk::kWorkerLdsReserve);
+    return RT_OK;
+}
+
 // Status of a finished request from the condition bits its columns raised:
 // strict-mode E <= w0 (RT_EDOMAIN) before out-of-domain inputs (RT_EINVAL).
 static rt_status request_status(rt_handle *h, const Job &j, uint32_t bits)
@@ -703,10 +819,131 @@ static rt_status request_status(rt_handle *h, const Job &j, uint32_t bits)
     return RT_OK;
 }
 
+// Persistent serving: retire requests whose tiles have all completed, admit
+// waiting requests (in arrival order, while a slot, ring space and arena memory
+// are free: arguments into the slot, tiles into the ring, then the tail
+// published), and launch the worker when unclaimed tiles exist and no worker
+// is running (it exits after its idle bound).
+static void pump_worker(rt_handle *h)
+{
+    if (!h->wq || h->wbroken) return;
+    uint64_t oldest = h->wpublished, oldest_seq = h->wseq;
+    for (auto it = h->prunning.begin(); it != h->prunning.end();) {
+        PJob &p = it->second;
+        while (p.seen < p.ntiles) {
+            const unsigned v =
+                __atomic_load_n(&h->wdone[(p.first + p.seen) & (kRingCap - 1)], __ATOMIC_ACQUIRE);
+            if (!v) break;
+            p.bits |= v & 0x7fffffffu;
+            ++p.seen;
+        }
+        if (p.seen == p.ntiles) {
+            h->arena.release(p.j.off, p.j.bytes);
+            h->finished[p.j.ticket] = request_status(h, p.j, p.bits);
+            it = h->prunning.erase(it);
+            continue;
+        }
+        oldest = std::min(oldest, p.first);
+        oldest_seq = std::min(oldest_seq, p.seq);
+        ++it;
+    }
+    bool running = false;
+    if (h->wlaunched) {
+        const hipError_t q = hipEventQuery(h->wevent);
+        running = q == hipErrorNotReady;
+        if (!running && q != hipSuccess) {
+            (void)hipGetLastError();
+            hip_fail(h, q, "serving worker");
+            for (auto &kv : h->prunning) {
+                h->arena.release(kv.second.j.off, kv.second.j.bytes);
+                h->finished[kv.first] = RT_EDEVICE;
+            }
+            h->prunning.clear();
+            for (const Job &j : h->pqueued) h->finished[j.ticket] = RT_EDEVICE;
+            h->pqueued.clear();
+            h->wlaunched = false;
+            // published tiles of the failed requests stay in the ring: no
+            // later worker may take them
+            h->wbroken = true;
+            return;
+        }
+    }
+    bool published = false, need_new_life = false;
+    while (!h->pqueued.empty()) {
+        Job &j = h->pqueued.front();
+        const int nt = j.g.blocks;
+        if (h->wpublished + nt - oldest > (uint64_t)kRingCap) break;
+        // a slot still held by a running request is never reused
+        if (h->wseq >= oldest_seq + kSlotRing) break;
+        // a slot last used by a request the running worker may have read waits
+        // for the next worker lifetime
+        if (running && h->wseq >= h->wgen + kSlotRing) {
+            need_new_life = true;
+            break;
+        }
+        size_t off;
+        if (!h->arena.alloc(j.bytes, &off)) break;   // keep arrival order under pressure
+        j.off = off;
+        PJob p;
+        p.j = j;
+        p.seq = h->wseq++;
+        p.slot = (int)(p.seq % kSlotRing);
+        p.first = h->wpublished;
+        p.ntiles = nt;
+        rtk::SlotArgs sa{};
+        sa.a = make_args(h, &j.req, (double *)(h->arena.base + off));
+        sa.a.K = j.g.K;
+        sa.a.PC = j.g.PC;
+        sa.a.CH = j.g.CH;
+        sa.a.L = j.g.lanes;
+        sa.mixed = j.req.precision == RT_MIXED;
+        h->wslots[p.slot] = sa;
+        for (int t = 0; t < nt; ++t) {
+            const uint64_t idx = (p.first + t) & (kRingCap - 1);
+            h->wdone[idx] = 0u;
+            h->wring[idx] = rtk::WorkTile{p.slot, t};
+        }
+        h->wpublished += nt;
+        h->prunning[j.ticket] = p;
+        h->pqueued.pop_front();
+        published = true;
+    }
+    if (published) __atomic_store_n(&h->wq->tail, (unsigned long long)h->wpublished, __ATOMIC_RELEASE);
+    // ask the running worker to end its lifetime once it has drained its tiles
+    __atomic_store_n(&h->wq->stop, need_new_life ? 1u : 0u, __ATOMIC_RELEASE);
+    if (running || h->prunning.empty()) return;
+    // no worker running: every tile an earlier worker claimed has completed, so
+    // the requests still running have unclaimed tiles
+    uint64_t gen = h->wseq;
+    for (const auto &kv : h->prunning) gen = std::min(gen, kv.second.seq);
+    h->wgen = gen;
+    __atomic_store_n(&h->wq->stop, 0u, __ATOMIC_RELEASE);
+    hipError_t e = hipMemsetAsync(h->d_exiting, 0, sizeof(unsigned int), h->wstream);
+    if (e == hipSuccess) e = rtk::launch_worker(h->wargs, h->dev, h->wstream);
+    if (e == hipSuccess) e = hipEventRecord(h->wevent, h->wstream);
+    if (e != hipSuccess) {
+        // no worker will take these tiles: fail what was admitted or waits
+        (void)hipGetLastError();
+        hip_fail(h, e, "serving worker launch");
+        for (auto &kv : h->prunning) {
+            h->arena.release(kv.second.j.off, kv.second.j.bytes);
+            h->finished[kv.first] = RT_EDEVICE;
+        }
+        h->prunning.clear();
+        for (const Job &j : h->pqueued) h->finished[j.ticket] = RT_EDEVICE;
+        h->pqueued.clear();
+        h->wbroken = true;
+        return;
+    }
+    h->wlaunched = true;
+    if (!h->pqueued.empty()) pump_worker(h);   // admit what waited for this lifetime
+}
+
 // Retire finished batches, then admit queued requests: in arrival order, by
 // device-memory footprint, grouped by (precision, tile) into batched launches.
 static void pump(rt_handle *h)
 {
+    pump_worker(h);
     for (int i = 0; i < kSlots; ++i) {
         Batch &b = h->slots[i];
         if (!b.busy) continue;
@@ -816,19 +1053,35 @@ extern "C" rt_status rt_submit(rt_handle *h, const rt_request *r, uint64_t *tick
     if (st != RT_OK) return st;
     (void)hipSetDevice(h->cfg.device);
     if ((st = ensure_serving(h)) != RT_OK) return st;
-    if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight) {
+    auto inflight = [&] {
+        return (int)(h->queued.size() + h->running.size() + h->pqueued.size() + h->prunning.size());
+    };
+    if (inflight() >= h->cfg.max_inflight) {
         pump(h);
-        if ((int)(h->queued.size() + h->running.size()) >= h->cfg.max_inflight)
+        if (inflight() >= h->cfg.max_inflight)
             return fail(h, RT_EBUSY, "%d requests in flight", h->cfg.max_inflight);
     }
     Job j;
     j.ticket = h->next_ticket++;
     j.req = *r;
     j.g = request_geometry(h, r);
+    // the persistent worker takes layer-kernel requests with FP64 input storage;
+    // the others (deep and lane kernels, FP32 inputs) run as batched launches
+    bool worker = false;
+    if (h->cfg.serve_mode == RT_SERVE_PERSISTENT && !h->wbroken && j.g.kernel == rtk::KERNEL_LAYER &&
+        r->input_dtype == RT_F64) {
+        const rtk::Geometry gw = rtk::worker_geometry(r->n_cols, request_slabs(r), h->NBG, r->precision,
+                                                      h->dev, h->NG);
+        if (gw.threads > 0 && gw.blocks <= kRingCap) {
+            if ((st = ensure_worker(h)) != RT_OK) return st;
+            j.g = gw;
+            worker = true;
+        }
+    }
     j.bytes = j.g.scratch;
     if (j.bytes > h->arena.size)
         return fail(h, RT_ENOMEM, "request needs %zu bytes, budget is %zu", j.bytes, h->arena.size);
-    h->queued.push_back(j);
+    (worker ? h->pqueued : h->queued).push_back(j);
     *ticket = j.ticket;
     pump(h);
     return RT_OK;
@@ -845,8 +1098,10 @@ extern "C" rt_status rt_poll(rt_handle *h, uint64_t ticket)
         h->finished.erase(f);
         return s;
     }
-    if (h->running.count(ticket)) return RT_PENDING;
+    if (h->running.count(ticket) || h->prunning.count(ticket)) return RT_PENDING;
     for (const Job &j : h->queued)
+        if (j.ticket == ticket) return RT_PENDING;
+    for (const Job &j : h->pqueued)
         if (j.ticket == ticket) return RT_PENDING;
     return fail(h, RT_ENOTFOUND, "ticket %llu", (unsigned long long)ticket);
 }
@@ -860,6 +1115,9 @@ extern "C" rt_status rt_wait(rt_handle *h, uint64_t ticket)
         auto it = h->running.find(ticket);
         if (it != h->running.end()) {
             (void)hipEventSynchronize(h->slots[it->second].done);
+        } else if (h->prunning.count(ticket) || h->pqueued.size()) {
+            // on the persistent worker: completion words in host memory
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
         } else {
             // queued behind memory or slots: wait for any batch in flight
             for (auto &b : h->slots)

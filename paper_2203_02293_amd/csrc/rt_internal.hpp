@@ -103,6 +103,52 @@ hipError_t launch_solve_batch(const SolveArgs *d_reqs, const int *d_first, int n
 // Allow the kernels the device's full LDS per workgroup (once per device).
 hipError_t prepare_kernels(const DeviceLimits &dev);
 
+// ---------------------------------------------------------------- persistent serving
+// A resident worker (one workgroup per compute unit, kWorkerThreads threads,
+// the device's whole LDS) that takes layer-kernel tiles of any queued request
+// from a ring the host fills, in either precision.  The ring, the request
+// arguments and the completion words live in pinned host memory that the GPU
+// reads and writes coherently; the claim counter lives in device memory.
+constexpr int kWorkerThreads = 512;      // both precisions in one kernel: 256 VGPRs, 2 wavefronts per SIMD
+constexpr size_t kWorkerLdsReserve = 256; // top of the LDS: the worker's own words
+
+struct WorkTile {
+    int slot;   // request slot
+    int tile;   // workgroup tile of that request
+};
+// Arguments of one admitted request (a slot), as the worker reads them (with
+// scalar loads, so each slot sits on cache lines of its own).
+struct alignas(256) SlotArgs {
+    SolveArgs a;
+    int mixed, pad_[3];
+};
+static_assert(sizeof(SlotArgs) % 8 == 0, "the worker copies SlotArgs in 8-byte words");
+// Host-written control words.
+struct WorkQueueHost {
+    unsigned long long tail;   // tiles published so far (stored with release order)
+    unsigned int stop;         // 1: exit once no tile is left to claim
+    unsigned int pad_;
+};
+struct WorkerArgs {
+    WorkQueueHost *q;             // pinned host memory
+    const WorkTile *ring;         // pinned host memory [ring_cap]
+    const SlotArgs *slots;        // pinned host memory [n_slots]
+    unsigned int *done;           // pinned host memory [ring_cap]: 0 = pending, else
+                                  // 0x80000000 | condition bits of the finished tile
+    unsigned long long *head;     // device memory: tiles claimed so far
+    unsigned int *wg_status;      // device memory [grid]: condition bits of a tile
+    unsigned int *exiting;        // device memory: set by the first workgroup that
+                                  // idles out; the others then leave when idle too
+    int ring_cap;                 // a power of two
+    int idle_polls;               // polls without work before the worker exits
+    int lds_top;                  // byte offset of the worker's own LDS words
+    int pad_;
+};
+// Geometry of a request's tiles on the worker (the layer kernel at kWorkerThreads
+// threads, within the LDS below the worker's reserve); threads = 0 if none fits.
+Geometry worker_geometry(int C, int N, int NB, int precision, const DeviceLimits &dev, int NG);
+hipError_t launch_worker(const WorkerArgs &w, const DeviceLimits &dev, hipStream_t s);
+
 // Optical properties of the slabs from the opacity tables (one launch).
 struct OpticsArgs {
     int C, S, NBG, NG;          // columns, slabs, lanes per column, Gaussian points per bin

@@ -402,7 +402,10 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
 }
 
 template <bool MIXED, bool IN32>
-__device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int tile)
+// status: where the tile ORs the condition bits that fail a request (a.status,
+// or the serving worker's word for the tile), or NULL.
+__device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int tile,
+                                                 uint32_t *const status)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
     // storage type of dtau, w0, g0 (FP32 on the mixed path only); loaded ahead
@@ -1106,7 +1109,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if (cc >= C) continue;
         if (a.flags) a.flags[cc] = s_flag[kk];
         const uint32_t bad = status_bits(s_flag[kk]);
-        if (a.status && bad) atomicOr(a.status, bad);
+        if (status && bad) atomicOr(status, bad);
     }
 }
 
@@ -1141,7 +1144,7 @@ k_solve_lane_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ f
 template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(layer_max_threads(MIXED)) k_solve_layer(const SolveArgs a)
 {
-    solve_tile_layer<MIXED, IN32>(a, blockIdx.x);
+    solve_tile_layer<MIXED, IN32>(a, blockIdx.x, a.status);
 }
 
 template <bool MIXED, bool IN32 = false>
@@ -1149,7 +1152,7 @@ __global__ void __launch_bounds__(layer_max_threads(MIXED))
 k_solve_layer_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
 {
     const int r = batch_slot(first, n, blockIdx.x);
-    solve_tile_layer<MIXED, IN32>(reqs[r], blockIdx.x - first[r]);
+    solve_tile_layer<MIXED, IN32>(reqs[r], blockIdx.x - first[r], reqs[r].status);
 }
 
 int round64(int x) { return (x + 63) / 64 * 64; }
@@ -1175,20 +1178,23 @@ Geometry lane_geometry(int C, int NB, int K)
 // Levels per chunk: the most work per barrier that fits LDS, with the items of
 // a chunk (PC x lanes) in at most layer_items_per_thread rounds of the
 // workgroup (each thread prefetches that many items of the next chunk).
-Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev, int NG)
+// force_threads > 0: a workgroup of exactly that many threads (the serving
+// worker's), else the kernel's bound for the precision.
+Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &dev, int NG,
+                        int force_threads = 0)
 {
     Geometry g{};
     g.kernel = KERNEL_LAYER;
     const int NBR = NG > 1 && NB % NG == 0 ? NB / NG : NB;   // bins (Planck edges NBR + 1)
+    const int wmax = force_threads > 0 ? force_threads : layer_max_threads(mixed);
     if (K <= 0) {
         const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
         K = (C + n_cu - 1) / n_cu;             // about one workgroup per compute unit
-        K = std::max(1, std::min(K, layer_max_threads(mixed) / NB));
+        K = std::max(1, std::min(K, wmax / NB));
     }
     if (K > C) K = C;
     const int T = K * NB;
     if (T > kMaxTileLanes) return Geometry{};
-    const int wmax = layer_max_threads(mixed);
     if (T > wmax) return Geometry{};
     double best = -1.0;
     const int it = layer_items_per_thread(mixed);
@@ -1209,7 +1215,7 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     if (best < 0.0) return Geometry{};
     // a multiple of four wavefronts, so that every SIMD of the compute unit
     // holds as many (the extra threads take no items, only edge integrals)
-    g.threads = std::min(wmax, (g.threads + 255) / 256 * 256);
+    g.threads = force_threads > 0 ? force_threads : std::min(wmax, (g.threads + 255) / 256 * 256);
     // interfaces per back-substitution pass: as many as fit in the forward
     // sweep's bytes and in the threads' staging registers
     // (none with wavefront bin sums, which stage no records in LDS)
@@ -1246,6 +1252,113 @@ Geometry solve_geometry(int C, int N, int NB, int K, int kernel, int precision,
     return g;
 }
 
+Geometry worker_geometry(int C, int N, int NB, int precision, const DeviceLimits &dev, int NG)
+{
+    DeviceLimits d = dev;
+    d.lds = dev.lds > kWorkerLdsReserve ? dev.lds - kWorkerLdsReserve : 0;
+    const int n_cu = dev.n_cu > 0 ? dev.n_cu : 256;
+    Geometry g{};
+    for (int k = std::min((C + n_cu - 1) / n_cu, kWorkerThreads / NB); k >= 1 && g.threads == 0; --k)
+        g = layer_geometry(C, NB, k, precision == 1, d, NG, kWorkerThreads);
+    if (g.threads > 0) g.scratch = (size_t)N * 4 * (size_t)g.lanes * sizeof(double);
+    return g;
+}
+
+namespace {
+
+// Persistent serving worker.  Thread 0 of a workgroup claims the next published
+// tile (compare-and-swap on the device-memory claim counter, below the
+// host-published tail); the workgroup reads that request's arguments from
+// pinned host memory, solves the tile with the layer kernel's body in the
+// request's precision, and thread 0 stores the tile's completion word.  The
+// wait for work is bounded: after idle_polls polls without a tile (or once the
+// host sets stop, or another workgroup has idled out, and nothing is left to
+// claim), the workgroup exits, so every launch ends; the host launches the
+// worker again when it publishes more work.
+__global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArgs w)
+{
+    extern __shared__ double smem[];
+    long long *s_claim = reinterpret_cast<long long *>(reinterpret_cast<char *>(smem) + w.lds_top);
+    const int tid = threadIdx.x;
+    unsigned int *const st = w.wg_status + blockIdx.x;
+    // thread 0's one region per pass (a single region, so that no path of the
+    // other threads can bypass it between two barriers): complete the previous
+    // tile, then claim the next one
+    long long prev = -1;
+    for (;;) {
+        if (tid == 0) {
+            if (prev >= 0) {
+                const unsigned bits = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the tile's outputs are visible before its completion word
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                __hip_atomic_store(w.done + (prev & (long long)(w.ring_cap - 1)), 0x80000000u | bits,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __hip_atomic_store(st, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            long long claim = -1;
+            for (int it = 0;;) {
+                const unsigned long long tail =
+                    __hip_atomic_load(&w.q->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                unsigned long long h = __hip_atomic_load(w.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < tail) {
+                    // a lost race means another workgroup claimed a tile: at most
+                    // tail - h retries before the tiles run out
+                    if (__hip_atomic_compare_exchange_strong(w.head, &h, h + 1ull, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        claim = (long long)h;
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(&w.q->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                // idle: leave together, so that the host relaunches a whole worker
+                // when work comes (workgroups still on a tile finish it first)
+                if (++it >= w.idle_polls ||
+                    __hip_atomic_load(w.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(w.exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(32);
+            }
+            *s_claim = claim;
+            prev = claim;
+        }
+        __syncthreads();
+        // the claim as a wavefront-uniform value: every branch below is uniform
+        const long long c = *s_claim;
+        const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)(unsigned long long)c);
+        const int hi = __builtin_amdgcn_readfirstlane((int)((unsigned long long)c >> 32));
+        const long long claim = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+        if (claim < 0) return;
+        // the host's ring entry and request arguments, written before it published the tail
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        const int idx = (int)(claim & (long long)(w.ring_cap - 1));
+        const unsigned long long e =
+            __hip_atomic_load(reinterpret_cast<const unsigned long long *>(w.ring) + idx, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+        const int slot = __builtin_amdgcn_readfirstlane((int)(unsigned)e);
+        const int tile = __builtin_amdgcn_readfirstlane((int)(unsigned)(e >> 32));
+        // the request's arguments, read in place like a batched launch's
+        // descriptor table (a slot's address is written once per worker
+        // lifetime, before the tail that publishes its tiles)
+        const SlotArgs &sa = w.slots[slot];
+        if (sa.mixed) solve_tile_layer<true, false>(sa.a, tile, st);
+        else solve_tile_layer<false, false>(sa.a, tile, st);
+        // every thread's outputs and condition bits of this tile precede thread
+        // 0's completion word
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_worker(const WorkerArgs &w, const DeviceLimits &dev, hipStream_t s)
+{
+    const int grid = dev.n_cu > 0 ? dev.n_cu : 256;
+    hipLaunchKernelGGL(k_serve_worker, dim3(grid), dim3(kWorkerThreads), dev.lds, s, w);
+    return hipGetLastError();
+}
+
 hipError_t prepare_kernels(const DeviceLimits &dev)
 {
     const int bytes = (int)dev.lds;
@@ -1255,7 +1368,8 @@ hipError_t prepare_kernels(const DeviceLimits &dev)
         reinterpret_cast<const void *>(&k_solve_layer<true, true>),
         reinterpret_cast<const void *>(&k_solve_layer_batch<false>),
         reinterpret_cast<const void *>(&k_solve_layer_batch<true>),
-        reinterpret_cast<const void *>(&k_solve_layer_batch<true, true>)};
+        reinterpret_cast<const void *>(&k_solve_layer_batch<true, true>),
+        reinterpret_cast<const void *>(&k_serve_worker)};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

@@ -18,6 +18,7 @@ RT_OK, RT_PENDING = 0, 1
 RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EDOMAIN, RT_EBUSY, RT_ENOTFOUND = -1, -2, -3, -4, -5, -6
 RT_FP64, RT_MIXED = 0, 1
 RT_F64, RT_F32 = 0, 1          # storage of dtau, w0, g0 (rt_request.input_dtype)
+RT_SERVE_BATCHED, RT_SERVE_PERSISTENT = 0, 1   # rt_config.serve_mode
 RT_KERNEL_AUTO, RT_KERNEL_LANE, RT_KERNEL_LAYER, RT_KERNEL_DEEP = 0, 1, 2, 3
 FLAG_GUARD, FLAG_ECLAMP, FLAG_ETAU, FLAG_EDOMAIN, FLAG_INVALID, FLAG_NONFIN = 1, 2, 4, 8, 16, 32
 
@@ -35,7 +36,7 @@ class RtConfig(ct.Structure):
                 ("e_tau", ct.c_double), ("g_guard", ct.c_double), ("gravity", ct.c_double),
                 ("cp", ct.c_double), ("hbm_budget_bytes", ct.c_int64),
                 ("max_inflight", ct.c_int32), ("device", ct.c_int32),
-                ("n_gauss", ct.c_int32), ("reserved", ct.c_int32),
+                ("n_gauss", ct.c_int32), ("serve_mode", ct.c_int32),
                 ("gauss_weights", ct.POINTER(ct.c_double))]
 
 
@@ -250,7 +251,8 @@ class Solver:
 
     def __init__(self, lambda_edges, stellar_flux, improved=1, noniso=1, e_clamp=1,
                  eps2=2.0 / 3.0, e_tau=1e-4, g_guard=1e-5, gravity=47.0, cp=12436.0,
-                 hbm_budget_bytes=0, max_inflight=0, device=0, gauss_weights=None):
+                 hbm_budget_bytes=0, max_inflight=0, device=0, gauss_weights=None,
+                 serve_mode=RT_SERVE_BATCHED):
         self._lam = np.ascontiguousarray(lambda_edges, dtype=np.float64)
         self._fs = np.ascontiguousarray(stellar_flux, dtype=np.float64)
         self._gw = None if gauss_weights is None else \
@@ -263,6 +265,7 @@ class Solver:
         cfg.eps2, cfg.e_tau, cfg.g_guard = eps2, e_tau, g_guard
         cfg.gravity, cfg.cp = gravity, cp
         cfg.hbm_budget_bytes, cfg.max_inflight, cfg.device = hbm_budget_bytes, max_inflight, device
+        cfg.serve_mode = serve_mode
         if self._gw is not None:
             cfg.n_gauss = self._gw.size
             cfg.gauss_weights = self._gw.ctypes.data_as(ct.POINTER(ct.c_double))

@@ -37,20 +37,20 @@ class Args(ct.Structure):
                            'scratch')] + [('L', ct.c_longlong), ('o', Opts)]
 
 
-def geometry(C, NBG, K, mixed, lds=160 * 1024, ncu=256, NG=1):
+def geometry(C, NBG, K, mixed, lds=160 * 1024, ncu=256, NG=1, worker=False):
     v = (ct.c_int * 7)()
-    lib().emu_geometry(C, NBG, K, int(mixed), lds, ncu, v, NG)
+    lib().emu_geometry(C, NBG, K, int(mixed), lds, ncu, v, NG, int(worker))
     return dict(K=v[0], PC=v[1], CH=v[2], threads=v[3], blocks=v[4], lds=v[5], lanes=v[6])
 
 
-def solve(w, mixed, K=0, opts=None, lds=160 * 1024, ncu=256, per_bin=True):
-    """The layer kernel on the host."""
+def solve(w, mixed, K=0, opts=None, lds=160 * 1024, ncu=256, per_bin=True, worker=False):
+    """The layer kernel on the host (worker: at the serving worker's tile)."""
     NG = int(w.get('n_gauss', 1)) if w.get('gauss_w') is not None else 1
-    g = geometry(w['n_cols'], w['n_bins'] * NG, K, mixed, lds, ncu, NG)
+    g = geometry(w['n_cols'], w['n_bins'] * NG, K, mixed, lds, ncu, NG, worker)
     S = 2 * w['n_layers'] if w.get('T_center') is not None and w.get('sublayer', False) else w['n_layers']
     scratch = np.full(S * 4 * g['lanes'], np.nan)
     out, a, keep = _args(w, opts, per_bin, scratch.ctypes.data)
-    lib().emu_solve(ct.byref(a), int(mixed), K, lds, ncu)
+    lib().emu_solve(ct.byref(a), int(mixed), K, lds, ncu, int(worker))
     return out, g
 
 

@@ -245,3 +245,102 @@ def test_enomem_and_recovery(rt, torch):
     assert s.wait(s.submit(inp, out)) == rt.RT_OK
     np.testing.assert_array_equal(host(ref)["F_net"], host(out)["F_net"])
     s.close()
+
+
+# ------------------------------------------------------------ persistent worker
+def test_persistent_mix_equals_alone(rt, torch):
+    """serve_mode RT_SERVE_PERSISTENT: uneven requests of 30, 100 and 300 bins,
+    FP64 and mixed, on the resident worker.  Each result is the same alone on
+    the worker and in the mix (bitwise), and agrees with rt_solve_fluxes to
+    the precision's tolerance (the worker's tile width differs)."""
+    solvers, jobs = {}, []
+    for k, (nb, seed) in enumerate([(30, 41), (100, 42), (300, 43), (30, 44), (100, 45)]):
+        for w in request_mix(2, nb, seed=seed):
+            if nb not in solvers:
+                solvers[nb] = rt.Solver(w["lambda_edges"], w["F_star"], max_inflight=64,
+                                        hbm_budget_bytes=8 << 30,
+                                        serve_mode=rt.RT_SERVE_PERSISTENT)
+            jobs.append(dict(nb=nb, inp=rt.to_device(w), C=w["n_cols"], N=w["n_layers"],
+                             prec=len(jobs) % 2))
+    print(f"\n[serving] persistent: {[(j['C'], j['N'], j['nb'], j['prec']) for j in jobs]}",
+          flush=True)
+    for j in jobs:
+        s = solvers[j["nb"]]
+        j["stream"] = host(s.solve(j["inp"], precision=j["prec"]))
+        o = s.outputs(j["C"], j["N"])
+        torch.cuda.synchronize()
+        assert s.wait(s.submit(j["inp"], o, j["prec"])) == rt.RT_OK
+        j["alone"] = host(o)
+    for j in jobs:
+        j["out"] = solvers[j["nb"]].outputs(j["C"], j["N"])
+    torch.cuda.synchronize()
+    for j in jobs:
+        j["ticket"] = solvers[j["nb"]].submit(j["inp"], j["out"], j["prec"])
+    for j in reversed(jobs):
+        assert solvers[j["nb"]].wait(j["ticket"]) == rt.RT_OK
+    for j in jobs:
+        b = host(j["out"])
+        tol = 1e-12 if j["prec"] == 0 else 1e-6
+        for k in j["alone"]:
+            np.testing.assert_array_equal(j["alone"][k], b[k], err_msg=f"{k} {j['C']}x{j['N']}x{j['nb']}")
+        S = (j["stream"]["F_up"] + j["stream"]["F_dn"] + j["stream"]["F_beam"]).max(axis=0)
+        for k in ("F_up", "F_dn", "F_net"):
+            err = np.abs(b[k] - j["stream"][k]) / np.maximum(S, 1e-300)
+            assert err.max() <= tol, (k, j["C"], j["N"], j["nb"], j["prec"], err.max())
+        np.testing.assert_array_equal(b["flags"], j["stream"]["flags"])
+    for s in solvers.values():
+        s.close()
+
+
+def test_persistent_worker_relaunch_and_slot_lifetimes(rt, torch):
+    """The worker ends by itself about a millisecond after its last tile; a
+    request submitted later starts a new worker.  4200 small requests take
+    more slots than one worker lifetime may use (4096), so the library also
+    ends a lifetime under load and starts the next: every request completes
+    with the stand-alone result."""
+    import time
+    w = request_mix(1, 30, seed=51)[0]
+    s = rt.Solver(w["lambda_edges"], w["F_star"], max_inflight=256,
+                  serve_mode=rt.RT_SERVE_PERSISTENT)
+    inp = rt.to_device(w)
+    ref = s.outputs(w["n_cols"], w["n_layers"])
+    torch.cuda.synchronize()
+    assert s.wait(s.submit(inp, ref)) == rt.RT_OK
+    time.sleep(0.05)                               # the worker has idled out
+    out = s.outputs(w["n_cols"], w["n_layers"])
+    torch.cuda.synchronize()
+    assert s.wait(s.submit(inp, out)) == rt.RT_OK
+    np.testing.assert_array_equal(host(ref)["F_net"], host(out)["F_net"])
+    # many small requests: one column each
+    small = synth.make(synth.Spec(name="tiny", g_level=2, n_layers=24, n_bins=30, seed=52),
+                       n_cols=8)
+    sinp = rt.to_device(small)
+    alone = s.outputs(8, 24)
+    torch.cuda.synchronize()
+    assert s.wait(s.submit(sinp, alone)) == rt.RT_OK
+    a = host(alone)["F_net"]
+    outs = [s.outputs(8, 24) for _ in range(64)]
+    torch.cuda.synchronize()
+    pending, done, n = {}, 0, 4200
+    t0 = time.perf_counter()
+    for i in range(n):
+        while len(pending) >= 64:
+            assert time.perf_counter() - t0 < 60.0, (i, done)
+            for t in list(pending):
+                st = s.poll(t)
+                if st != rt.RT_PENDING:
+                    assert st == rt.RT_OK, (t, st)
+                    slot = pending.pop(t)
+                    assert np.array_equal(host(outs[slot])["F_net"], a)
+                    done += 1
+        used = set(pending.values())
+        slot = next(k for k in range(64) if k not in used)
+        pending[s.submit(sinp, outs[slot])] = slot
+    for t, slot in pending.items():
+        assert s.wait(t) == rt.RT_OK
+        assert np.array_equal(host(outs[slot])["F_net"], a)
+        done += 1
+    print(f"\n[serving] {done} small requests on the worker in {time.perf_counter() - t0:.2f} s",
+          flush=True)
+    assert done == n
+    s.close()
