@@ -238,93 +238,119 @@ def serving(args, torch, rt, synth) -> dict:
     """Serving mix: uneven requests (columns U{1..4096}, layers U{20..120}, bins in
     {30, 100, 300}, cloud fraction U[0, 0.5]) through rt_submit/rt_poll, half
     FP64 and half mixed, inputs resident on the device, one handle per spectral
-    set-up.  First the saturation rate (every request submitted at time 0), then
-    Poisson arrivals at the stated fractions of it.  Latency = completion time
-    (seen by polling) minus arrival time.  Every output slot's last result of a
-    run is compared with the same request solved alone (bitwise)."""
+    set-up; once with batched launches, once with the persistent worker.  For
+    each: the saturation rate (every request submitted at time 0), then Poisson
+    arrivals at the stated fractions of the batched saturation rate (the same
+    arrival rates for both).  Latency = completion time (seen by polling) minus
+    arrival time.  Every output slot's last result of a run is compared with the
+    same request submitted alone on the same handle (bitwise)."""
     shapes = synth.serving_requests(args.serve_pool, seed=1003, max_cols=4096)
-    pool, solvers = [], {}
+    pool = []
     for k, sh in enumerate(shapes):
         w = synth.make_request(sh)
-        nb = w["n_bins"]
-        if nb not in solvers:
-            solvers[nb] = rt.Solver(w["lambda_edges"], w["F_star"], max_inflight=256,
-                                    hbm_budget_bytes=args.serve_budget_gib << 30)
-        pool.append(dict(nb=nb, inp=rt.to_device(w), C=w["n_cols"], N=w["n_layers"],
+        pool.append(dict(nb=w["n_bins"], lam=w["lambda_edges"], fs=w["F_star"], inp=rt.to_device(w),
+                         C=w["n_cols"], N=w["n_layers"],
                          prec=rt.RT_FP64 if k % 2 == 0 else rt.RT_MIXED))
         del w
     torch.cuda.synchronize()
-    # each request once alone (the reference of the bitwise check)
-    for q in pool:
-        s = solvers[q["nb"]]
-        q["out"] = [s.outputs(q["C"], q["N"]) for _ in range(args.serve_copies)]
-        s.solve(q["inp"], precision=q["prec"], out=q["out"][0])
-        torch.cuda.synchronize()
-        q["alone"] = {k: q["out"][0][k].cpu().numpy() for k in ("F_net", "heating")}
-        q["used"] = [False] * args.serve_copies
 
-    def run(rate):
-        """One run of serve_requests requests; rate None: all arrive at once."""
-        n = args.serve_requests
-        arrivals = (np.zeros(n) if rate is None
-                    else synth.poisson_arrivals(n, rate, seed=int(rate)))
-        order = np.random.Generator(np.random.PCG64(7 if rate is None else int(rate) + 1)
-                                    ).integers(0, len(pool), n)
-        busy = [[False] * args.serve_copies for _ in pool]
-        inflight, lat, cb = {}, [], 0
-        t0 = time.perf_counter()
-        i = 0
-        while i < n or inflight:
-            now = time.perf_counter() - t0
-            while i < n and arrivals[i] <= now:
-                q = pool[order[i]]
-                slot = next((m for m in range(args.serve_copies) if not busy[order[i]][m]), None)
-                if slot is None:      # every output copy of this request is busy: wait
-                    break
-                busy[order[i]][slot] = True
-                t = solvers[q["nb"]].submit(q["inp"], q["out"][slot], q["prec"])
-                inflight[(q["nb"], t)] = (arrivals[i], order[i], slot)
-                i += 1
-            for key in list(inflight):
-                nb, t = key
-                if solvers[nb].poll(t) == rt.RT_OK:
+    def design(mode, rates):
+        solvers = {}
+        for q in pool:
+            if q["nb"] not in solvers:
+                solvers[q["nb"]] = rt.Solver(q["lam"], q["fs"], max_inflight=256,
+                                             hbm_budget_bytes=args.serve_budget_gib << 30,
+                                             serve_mode=mode)
+        # each request once alone (the reference of the bitwise check)
+        for q in pool:
+            s = solvers[q["nb"]]
+            q["out"] = [s.outputs(q["C"], q["N"]) for _ in range(args.serve_copies)]
+            torch.cuda.synchronize()
+            if s.wait(s.submit(q["inp"], q["out"][0], q["prec"])) != rt.RT_OK:
+                raise RuntimeError("serving request failed alone")
+            q["alone"] = {k: q["out"][0][k].cpu().numpy() for k in ("F_net", "heating")}
+            q["used"] = [False] * args.serve_copies
+
+        def run(rate):
+            """One run of serve_requests requests; rate None: all arrive at once."""
+            n = args.serve_requests
+            arrivals = (np.zeros(n) if rate is None
+                        else synth.poisson_arrivals(n, rate, seed=int(rate)))
+            order = np.random.Generator(np.random.PCG64(7 if rate is None else int(rate) + 1)
+                                        ).integers(0, len(pool), n)
+            busy = [[False] * args.serve_copies for _ in pool]
+            inflight, lat, cb = {}, [], 0
+            t0 = time.perf_counter()
+            i = 0
+            while i < n or inflight:
+                now = time.perf_counter() - t0
+                while i < n and arrivals[i] <= now:
+                    q = pool[order[i]]
+                    slot = next((m for m in range(args.serve_copies) if not busy[order[i]][m]), None)
+                    if slot is None:      # every output copy of this request is busy: wait
+                        break
+                    busy[order[i]][slot] = True
+                    t = solvers[q["nb"]].submit(q["inp"], q["out"][slot], q["prec"])
+                    inflight[(q["nb"], t)] = (arrivals[i], order[i], slot)
+                    i += 1
+                for key in list(inflight):
+                    nb, t = key
+                    st = solvers[nb].poll(t)
+                    if st == rt.RT_PENDING:
+                        continue
+                    if st != rt.RT_OK:
+                        raise RuntimeError(f"serving request failed: status {st}")
                     arr, qi, slot = inflight.pop(key)
                     lat.append(time.perf_counter() - t0 - arr)
                     busy[qi][slot] = False
                     pool[qi]["used"][slot] = True
                     cb += pool[qi]["C"] * pool[qi]["nb"]
-        el = time.perf_counter() - t0
-        torch.cuda.synchronize()
-        checked = equal = 0
-        for q in pool:
-            for m, used in enumerate(q["used"]):
-                if used:
-                    checked += 1
-                    equal += all(np.array_equal(q["out"][m][k].cpu().numpy(), q["alone"][k])
-                                 for k in ("F_net", "heating"))
-                q["used"][m] = False
-        return {"rate_hz": None if rate is None else rate, "requests": len(lat),
-                "requests_per_s": len(lat) / el, "p50_ms": pct(lat, 50) * 1e3,
-                "p99_ms": pct(lat, 99) * 1e3, "solves_per_s": cb / el, "seconds": el,
-                "results_checked": checked, "results_equal_alone": equal}
+            el = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            checked = equal = 0
+            for q in pool:
+                for m, used in enumerate(q["used"]):
+                    if used:
+                        checked += 1
+                        equal += all(np.array_equal(q["out"][m][k].cpu().numpy(), q["alone"][k])
+                                     for k in ("F_net", "heating"))
+                    q["used"][m] = False
+            return {"rate_hz": None if rate is None else rate, "requests": len(lat),
+                    "requests_per_s": len(lat) / el, "p50_ms": pct(lat, 50) * 1e3,
+                    "p99_ms": pct(lat, 99) * 1e3, "solves_per_s": cb / el, "seconds": el,
+                    "results_checked": checked, "results_equal_alone": equal}
 
-    sat = run(None)
-    print(f"[bench] serving saturation {sat['requests_per_s']:.0f} requests/s, "
-          f"{sat['solves_per_s'] / 1e6:.0f} M solves/s", file=sys.stderr, flush=True)
-    results = []
-    for f in args.serve_load:
-        r = run(f * sat["requests_per_s"])
-        r["load"] = f
-        results.append(r)
-        print(f"[bench] serving at {f:.0%} of saturation ({r['rate_hz']:.0f}/s): p50 "
-              f"{r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms, {r['solves_per_s'] / 1e6:.0f} M "
-              f"solves/s", file=sys.stderr, flush=True)
-    for s in solvers.values():
-        s.close()
-    return {"pool": len(pool),
-            "mix": "columns U{1..4096}, layers U{20..120}, bins {30,100,300}, cloud fraction "
-                   "U[0,0.5], half FP64 / half mixed",
-            "requests_per_run": args.serve_requests, "saturation": sat, "rates": results}
+        name = "persistent" if mode == rt.RT_SERVE_PERSISTENT else "batched"
+        sat = run(None)
+        print(f"[bench] serving ({name}) saturation {sat['requests_per_s']:.0f} requests/s, "
+              f"{sat['solves_per_s'] / 1e6:.0f} M solves/s", file=sys.stderr, flush=True)
+        if rates is None:
+            rates = [f * sat["requests_per_s"] for f in args.serve_load]
+        results = []
+        for f, rate in zip(args.serve_load, rates):
+            r = run(rate)
+            r["load"] = f
+            results.append(r)
+            print(f"[bench] serving ({name}) at {rate:.0f}/s: p50 {r['p50_ms']:.2f} ms p99 "
+                  f"{r['p99_ms']:.2f} ms, {r['solves_per_s'] / 1e6:.0f} M solves/s",
+                  file=sys.stderr, flush=True)
+        for s in solvers.values():
+            s.close()
+        for q in pool:
+            q.pop("out", None)
+        return {"saturation": sat, "rates": results}, rates
+
+    batched, rates = design(rt.RT_SERVE_BATCHED, None)
+    persistent, _ = design(rt.RT_SERVE_PERSISTENT, rates)
+    out = {"pool": len(pool),
+           "mix": "columns U{1..4096}, layers U{20..120}, bins {30,100,300}, cloud fraction "
+                  "U[0,0.5], half FP64 / half mixed",
+           "requests_per_run": args.serve_requests,
+           "rates_from": "fractions of the batched saturation rate, the same for both designs"}
+    out.update(batched)
+    out["serve_mode"] = "batched"
+    out["persistent"] = persistent
+    return out
 
 
 def high_resolution(args, torch, rt, synth) -> dict:
@@ -376,7 +402,7 @@ def main():
     ap.add_argument("--no-cfg4", action="store_true",
                     help="skip the 10242 x 80 x 300 high-resolution solve")
     ap.add_argument("--serve-pool", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-copies", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.5, 0.8],

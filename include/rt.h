@@ -44,7 +44,9 @@ typedef int32_t rt_status;
                         predicates, optical-depth sums and Thomas elimination     */
 
 /* how the serving path (rt_submit) runs admitted requests (rt_config.serve_mode) */
-#define RT_SERVE_BATCHED    0   /* requests admitted together share one launch      */
+#define RT_SERVE_BATCHED    0   /* requests admitted together share one launch
+                                   (the default, and the faster design on MI355X
+                                   at every load measured)                          */
 #define RT_SERVE_PERSISTENT 1   /* a resident worker takes tiles of any admitted
                                    request as it frees up (layer-kernel requests
                                    with FP64 input storage; others run batched)    */

@@ -194,6 +194,7 @@ struct rt_handle {
     rtk::SlotArgs *wslots = nullptr;          // [kSlotRing]
     unsigned int *wdone = nullptr;            // [kRingCap] completion words
     rtk::WorkerArgs wargs{};                  // device-side view of the above
+    rtk::SlotArgs *d_targs = nullptr;         // device: [kRingCap] argument copies
     unsigned long long *d_head = nullptr;     // device: tiles claimed
     unsigned int *d_wgst = nullptr;           // device: per-workgroup condition bits
     unsigned int *d_exiting = nullptr;        // device: the worker is idling out
@@ -204,6 +205,7 @@ struct rt_handle {
     uint64_t wpublished = 0;                  // tiles published
     uint64_t wseq = 0;                        // slots taken
     uint64_t wgen = 0;                        // oldest slot the running worker may read
+    uint64_t wlife0 = 0;                      // first ring position it may claim
     std::deque<Job> pqueued;                  // waiting for the worker
     std::map<uint64_t, PJob> prunning;        // admitted to the worker
 };
@@ -409,6 +411,7 @@ extern "C" rt_status rt_destroy(rt_handle *h)
     if (h->wring) (void)hipHostFree(h->wring);
     if (h->wslots) (void)hipHostFree(h->wslots);
     if (h->wdone) (void)hipHostFree(h->wdone);
+    (void)hipFree(h->d_targs);
     (void)hipFree(h->d_head);
     (void)hipFree(h->d_exiting);
     (void)hipFree(h->d_wgst);
@@ -785,7 +788,8 @@ static rt_status ensure_worker(rt_handle *h)
     h->wslots = slots;
     if (!host_coherent(&done, &doned, kRingCap)) return fail(h, RT_ENOMEM, "worker completion words");
     h->wdone = done;
-    if (!dev_alloc((void **)&h->d_head, sizeof(unsigned long long)) ||
+    if (!dev_alloc((void **)&h->d_targs, sizeof(rtk::SlotArgs) * (size_t)kRingCap) ||
+        !dev_alloc((void **)&h->d_head, sizeof(unsigned long long)) ||
         !dev_alloc((void **)&h->d_exiting, sizeof(unsigned int)) ||
         !dev_alloc((void **)&h->d_wgst, sizeof(unsigned int) * (size_t)std::max(h->dev.n_cu, 1)))
         return fail(h, RT_ENOMEM, "worker counters");
@@ -797,6 +801,7 @@ static rt_status ensure_worker(rt_handle *h)
     w.ring = ringd;
     w.slots = slotsd;
     w.done = doned;
+    w.targs = h->d_targs;
     w.head = h->d_head;
     w.wg_status = h->d_wgst;
     w.exiting = h->d_exiting;
@@ -881,6 +886,12 @@ static void pump_worker(rt_handle *h)
             need_new_life = true;
             break;
         }
+        // likewise a ring position (and its argument copy) the running worker
+        // may have claimed
+        if (running && h->wpublished + nt > h->wlife0 + kRingCap) {
+            need_new_life = true;
+            break;
+        }
         size_t off;
         if (!h->arena.alloc(j.bytes, &off)) break;   // keep arrival order under pressure
         j.off = off;
@@ -917,6 +928,7 @@ static void pump_worker(rt_handle *h)
     uint64_t gen = h->wseq;
     for (const auto &kv : h->prunning) gen = std::min(gen, kv.second.seq);
     h->wgen = gen;
+    h->wlife0 = oldest;
     __atomic_store_n(&h->wq->stop, 0u, __ATOMIC_RELEASE);
     hipError_t e = hipMemsetAsync(h->d_exiting, 0, sizeof(unsigned int), h->wstream);
     if (e == hipSuccess) e = rtk::launch_worker(h->wargs, h->dev, h->wstream);

@@ -135,6 +135,9 @@ struct WorkerArgs {
     const SlotArgs *slots;        // pinned host memory [n_slots]
     unsigned int *done;           // pinned host memory [ring_cap]: 0 = pending, else
                                   // 0x80000000 | condition bits of the finished tile
+    SlotArgs *targs;              // device memory [ring_cap]: the claiming workgroup's
+                                  // copy of the tile's request arguments (the tile
+                                  // reads them there, not across the bus)
     unsigned long long *head;     // device memory: tiles claimed so far
     unsigned int *wg_status;      // device memory [grid]: condition bits of a tile
     unsigned int *exiting;        // device memory: set by the first workgroup that

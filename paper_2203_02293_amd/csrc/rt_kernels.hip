@@ -1338,10 +1338,17 @@ __global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArg
                               __HIP_MEMORY_SCOPE_SYSTEM);
         const int slot = __builtin_amdgcn_readfirstlane((int)(unsigned)e);
         const int tile = __builtin_amdgcn_readfirstlane((int)(unsigned)(e >> 32));
-        // the request's arguments, read in place like a batched launch's
-        // descriptor table (a slot's address is written once per worker
-        // lifetime, before the tail that publishes its tiles)
-        const SlotArgs &sa = w.slots[slot];
+        // the request's arguments: one read across the bus into device memory
+        // at this claim's ring position (not reused within a worker lifetime),
+        // from where the tile's many loads of them hit the caches
+        constexpr int kArgWords = (int)(sizeof(SlotArgs) / sizeof(unsigned long long));
+        static_assert(kArgWords <= kWorkerThreads, "one word per thread");
+        SlotArgs *ta = w.targs + idx;
+        if (tid < kArgWords)
+            reinterpret_cast<unsigned long long *>(ta)[tid] =
+                reinterpret_cast<const unsigned long long *>(w.slots + slot)[tid];
+        __syncthreads();
+        const SlotArgs &sa = *ta;
         if (sa.mixed) solve_tile_layer<true, false>(sa.a, tile, st);
         else solve_tile_layer<false, false>(sa.a, tile, st);
         // every thread's outputs and condition bits of this tile precede thread
