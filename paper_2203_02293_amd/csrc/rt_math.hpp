@@ -88,6 +88,28 @@ __host__ __device__ __forceinline__ R horner_y(R y)
     }
 }
 
+// FP64 sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain whose
+// coefficients are scalar operands of three-operand v_fma_f64 (materialised by
+// scalar moves, which issue beside the vector work): no coefficient occupies
+// a vector register or a vector move.
+template <class C, int J, int N>
+__host__ __device__ __forceinline__ double horner_s(double y)
+{
+    constexpr double cj = C::coef(J);
+    if constexpr (J + 1 >= N) {
+        return cj;
+    } else {
+        const double p = horner_s<C, J + 1, N>(y);
+#if defined(__HIP_DEVICE_COMPILE__)
+        double out;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(y), "s"(cj));
+        return out;
+#else
+        return fma(p, y, cj);
+#endif
+    }
+}
+
 // The polynomial by two chains in FP32 (shorter dependent chains); in FP64
 // by one (each extra FP64 constant and partial sum takes two registers, which
 // the FP64 kernel does not have to spare).

@@ -74,7 +74,6 @@ template <> struct PCfg<double> {
     static constexpr double XS = 3.0;   // series switch
     static constexpr int NQ = 28;       // Bernoulli terms: (3/2pi)^56 < 1e-18
     static constexpr int NP = 13;       // exponential terms: e^-39 < 1e-16
-    static constexpr double TAIL = 1e-17;
     static constexpr double XCUT = 745.0;
 };
 template <> struct PCfg<float> {
@@ -101,60 +100,69 @@ struct BernCoef {
     static constexpr double coef(int j) { return bern_coef(j + 1); }
 };
 
-// Series coefficient tables for FP64 (compile-time values, read with uniform
-// loads): c_k for the small-x series, 1/n for the large-x series.
-struct SeriesTables {
-    double bern[28];
-    double inv_n[14];
+// coefficients 1/n^S (n >= 1) of P_S(y) = sum_n y^n / n^S
+template <int S>
+struct InvPowCoef {
+    static constexpr double coef(int j)
+    {
+        double v = 1.0;
+        for (int i = 0; i < S; ++i) v /= double(j + 1);
+        return v;
+    }
 };
 
-constexpr SeriesTables make_series_tables()
-{
-    SeriesTables t{};
-    for (int k = 0; k < 28; ++k) t.bern[k] = bern_coef(k + 1);
-    for (int n = 0; n < 14; ++n) t.inv_n[n] = 1.0 / (n + 1);
-    return t;
-}
-
-__device__ constexpr SeriesTables kSeries = make_series_tables();
-constexpr SeriesTables kSeriesHost = make_series_tables();
-
-__host__ __device__ __forceinline__ const SeriesTables &series_tables()
+// A set of lanes' largest need as a wavefront-uniform choice: whether any
+// active lane of the wavefront has c true (every lane on the host).
+__host__ __device__ __forceinline__ bool wave_any(bool c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return kSeries;
+    return __builtin_amdgcn_ballot_w64(c) != 0;
 #else
-    return kSeriesHost;
+    return c;
 #endif
+}
+
+// FP64 large-x tail: sum_{n=1}^{M} e^{-nx} (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4)
+// = x^3 P_1(y) + 3x^2 P_2(y) + 6x P_3(y) + 6 P_4(y), y = e^{-x}, each P_S a
+// Horner chain in y (four independent chains).
+template <int M>
+__host__ __device__ __forceinline__ double planck_tail64(double x, double y)
+{
+    const double p1 = y * horner_s<InvPowCoef<1>, 0, M>(y);
+    const double p2 = y * horner_s<InvPowCoef<2>, 0, M>(y);
+    const double p3 = y * horner_s<InvPowCoef<3>, 0, M>(y);
+    const double p4 = y * horner_s<InvPowCoef<4>, 0, M>(y);
+    return fma(x * x, fma(x, p1, 3.0 * p2), fma(6.0 * x, p3, 6.0 * p4));
 }
 
 // +Q(x) for x <= XS, -P(x) otherwise: the sign bit records which tail it is.
 // x = c2/(lambda T) comes in FP64 in both precisions: FP32 takes e^-x from it
 // with the low part of the argument applied (exp_em1_f).
+// FP64: the number of series terms is the wavefront's largest need (a few
+// fixed lengths, so every branch is uniform and every coefficient a
+// compile-time constant): Q needs 15 terms up to x = 1.5 ((1.5/2pi)^30 <
+// 1e-18) and 28 up to XS; P needs n terms while e^{-nx} is above 1e-17 of
+// the first, i.e. n <= 39.1/x + 1, at most 13 above XS.
 template <class R>
 __host__ __device__ __forceinline__ R planck_edge(double xd)
 {
     using Cfg = PCfg<R>;
-    const SeriesTables &tb = series_tables();
     const R x = R(xd);
     if (x <= Cfg::XS) {
         const R x2 = x * x;
         R pb;
         if constexpr (sizeof(R) == 4) {
             pb = poly_eo<R, BernCoef, Cfg::NQ>(x2);
-        } else {   // FP64: coefficients by uniform loads from the table
-            pb = R(tb.bern[Cfg::NQ - 1]);
-#pragma unroll 4
-            for (int k = Cfg::NQ - 2; k >= 0; --k) pb = fma(pb, x2, R(tb.bern[k]));
+        } else {
+            if (wave_any(x > 1.5)) pb = horner_s<BernCoef, 0, Cfg::NQ>(x2);
+            else pb = horner_s<BernCoef, 0, 15>(x2);
         }
         return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + pb * x2);
     }
     if (!(x < Cfg::XCUT)) return R(-0.0);   // e^{-x} underflows (includes T = 0)
     // sum_{n>=1} y^n q_n, y = e^{-x}, q_n = x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4
-    R y;
-    if constexpr (sizeof(R) == 4) y = exp_em1_f(-xd).e;
-    else y = exp_em1(-x).e;
     if constexpr (sizeof(R) == 4) {
+        const R y = exp_em1_f(-xd).e;
         // FP32: forward from the largest term, over the terms that reach the
         // last bit: term n over term 1 is below y^(n-1) = e^-(n-1)x, under
         // 2^-25 once (n-1) x > 17.3.  The term index is the same in every lane
@@ -173,17 +181,13 @@ __host__ __device__ __forceinline__ R planck_edge(double xd)
         }
         return -sum;
     } else {
-        // FP64: forward, stopping once term n+1 over term 1 (about e^{-nx}) is
-        // below the last bit: few terms at the large x that most edges have
-        R yn = y, sum = R(0);
-        for (int n = 0; n < Cfg::NP; ++n) {
-            const R t = R(tb.inv_n[n]);
-            // (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4) = t (x^3 + t (3x^2 + t (6x + 6t)))
-            const R poly = t * fma(t, fma(t, R(6) * (x + t), R(3) * x * x), x * x * x);
-            sum = fma(yn, poly, sum);
-            yn *= y;
-            if (yn < R(Cfg::TAIL) * y) break;   // next term relative to the first
-        }
+        const R y = exp_em1(-x).e;
+        R sum;
+        if (wave_any(x <= 39.1 / 8)) sum = planck_tail64<Cfg::NP>(x, y);
+        else if (wave_any(x <= 39.1 / 4)) sum = planck_tail64<8>(x, y);
+        else if (wave_any(x <= 39.1 / 2)) sum = planck_tail64<4>(x, y);
+        else if (wave_any(x <= 39.1)) sum = planck_tail64<2>(x, y);
+        else sum = planck_tail64<1>(x, y);
         return -sum;
     }
 }
