@@ -1216,13 +1216,16 @@ Geometry layer_geometry(int C, int NB, int K, bool mixed, const DeviceLimits &de
     // a multiple of four wavefronts, so that every SIMD of the compute unit
     // holds as many (the extra threads take no items, only edge integrals)
     g.threads = force_threads > 0 ? force_threads : std::min(wmax, (g.threads + 255) / 256 * 256);
-    // interfaces per back-substitution pass: as many as fit in the forward
-    // sweep's bytes and in the threads' staging registers
+    // interfaces per back-substitution pass: as many as fit in the threads'
+    // staging registers and in the forward sweep's bytes, or in the device's
+    // LDS for workgroups of 768 threads and more, which hold their compute
+    // unit alone (register file) in either precision
     // (none with wavefront bin sums, which stage no records in LDS)
     const size_t front = lp_layout(K, NB, NBR, g.PC, 1, mixed).total;
+    const size_t back_cap = g.threads >= 768 ? dev.lds : front;
     const bool ws = layer_wsum(K, NB, g.threads);
     int ch = 1;
-    while (!ws && ch < 16 && lp_layout(K, NB, NBR, g.PC, ch + 1, mixed).total <= front &&
+    while (!ws && ch < 16 && lp_layout(K, NB, NBR, g.PC, ch + 1, mixed).total <= back_cap &&
            2 * (ch + 1) * T <= kBackUnits * g.threads)
         ++ch;
     g.CH = ch;
