@@ -344,3 +344,63 @@ def test_persistent_worker_relaunch_and_slot_lifetimes(rt, torch):
           flush=True)
     assert done == n
     s.close()
+
+
+def test_persistent_status_codes_and_routing(rt, torch):
+    """On the persistent worker, a request whose inputs are outside their
+    domain ends with RT_EINVAL (and its column's flag), strict-mode E <= w0
+    with RT_EDOMAIN, and the clean requests around them with RT_OK and the
+    result they have alone on the worker.  Requests the worker does not take
+    (FP32 input storage, the deep kernel) run as batched launches on the same
+    handle: their results equal those of a batched handle bit for bit."""
+    reqs = request_mix(3, 30, seed=61)
+    reqs = [{k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in w.items()} for w in reqs]
+    reqs[1]["w0"][3, 0, 2] = 1.5                      # invalid albedo in column 0
+    P = rt.RT_SERVE_PERSISTENT
+    s = rt.Solver(reqs[0]["lambda_edges"], reqs[0]["F_star"], serve_mode=P)
+    inputs = [rt.to_device(w) for w in reqs]
+    shape = lambda i: (int(i["mu_star"].shape[0]), int(i["dtau"].shape[0]))
+    alone = s.outputs(*shape(inputs[0]))
+    torch.cuda.synchronize()
+    assert s.wait(s.submit(inputs[0], alone)) == rt.RT_OK
+    outs = [s.outputs(*shape(i)) for i in inputs]
+    torch.cuda.synchronize()
+    tickets = [s.submit(i, o) for i, o in zip(inputs, outs)]
+    assert s.wait(tickets[0]) == rt.RT_OK
+    with pytest.raises(rt.RtError) as e:
+        s.wait(tickets[1])
+    assert e.value.status == rt.RT_EINVAL
+    assert host(outs[1])["flags"][0] & rt.FLAG_INVALID
+    assert s.wait(tickets[2]) == rt.RT_OK
+    np.testing.assert_array_equal(host(alone)["F_net"], host(outs[0])["F_net"])
+    s.close()
+    # strict mode: a cloud column with E_fit <= w0
+    w = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in reqs[0].items()}
+    w["w0"][:, 1, :] = 0.999
+    w["g0"][:, 1, :] = 0.95
+    s = rt.Solver(w["lambda_edges"], w["F_star"], e_clamp=0, serve_mode=P)
+    inp = rt.to_device(w)
+    out = s.outputs(w["n_cols"], w["n_layers"])
+    torch.cuda.synchronize()
+    with pytest.raises(rt.RtError) as e:
+        s.wait(s.submit(inp, out))
+    assert e.value.status == rt.RT_EDOMAIN
+    assert host(out)["flags"][1] & rt.FLAG_EDOMAIN
+    s.close()
+    # routing: FP32 storage (mixed) and the deep kernel go to batched launches
+    w = reqs[2]
+    f32 = rt.to_device(w, input_f32=True)
+    res = {}
+    for mode in (rt.RT_SERVE_BATCHED, P):
+        s = rt.Solver(w["lambda_edges"], w["F_star"], serve_mode=mode)
+        o1 = s.outputs(w["n_cols"], w["n_layers"])
+        o2 = s.outputs(w["n_cols"], w["n_layers"])
+        torch.cuda.synchronize()
+        t1 = s.submit(f32, o1, rt.RT_MIXED)
+        t2 = s.submit(inputs[2], o2, rt.RT_FP64, kernel=rt.RT_KERNEL_DEEP, cols_per_block=0)
+        assert s.wait(t2) == rt.RT_OK and s.wait(t1) == rt.RT_OK
+        res[mode] = (host(o1), host(o2))
+        s.close()
+    for k in ("F_up", "F_dn", "F_net", "heating"):
+        np.testing.assert_array_equal(res[rt.RT_SERVE_BATCHED][0][k], res[P][0][k], err_msg=f"f32 {k}")
+        np.testing.assert_array_equal(res[rt.RT_SERVE_BATCHED][1][k], res[P][1][k], err_msg=f"deep {k}")
