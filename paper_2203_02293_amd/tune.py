@@ -22,7 +22,8 @@ from . import rt, synth
 SHAPES = [  # (columns, layers, bins): GCM size, serving mix corners, high resolution,
     # few deep columns
     (2562, 40, 30), (512, 40, 30), (4096, 120, 30), (256, 80, 100), (2048, 60, 100),
-    (1024, 80, 300), (4096, 120, 300), (1, 4096, 30), (16, 1000, 30), (64, 400, 30),
+    (1024, 80, 300), (4096, 120, 300), (10242, 80, 300), (1, 4096, 30), (16, 1000, 30),
+    (64, 400, 30),
 ]
 
 
