@@ -31,7 +31,8 @@ ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+FP64_PEAK_TF = 78.6            # MI355X FP64 vector
+FP32_PEAK_TF = 157.3           # MI355X FP32 vector
 # VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles
 # (16 lanes wide), at 2.4 GHz
 VALU_ISSUE_PEAK_G = 256 * 4 / 4 * 2.4
@@ -102,6 +103,44 @@ def valu_issue(kernel: str, ms: float) -> dict | None:
             "unit": "G wave-instructions/s", "frac": rate / VALU_ISSUE_PEAK_G}
 
 
+def fp_rates(kernel: str, ms: float) -> dict | None:
+    """Floating-point rate of a launch from the committed FLOP-mix counters
+    (SQ_INSTS_VALU_{ADD,MUL,FMA}_F{32,64}, wave-instructions of 64 lanes, an FMA
+    two flops) over the launch time, against the vector peaks (FP64 78.6, FP32
+    157.3 TFLOP/s)."""
+    k = _profiled(kernel)
+    if k is None or "flops" not in k:
+        return None
+    f = k["flops"]
+    out = {}
+    for prec, peak in (("F64", FP64_PEAK_TF), ("F32", FP32_PEAK_TF)):
+        fl = 64 * (f[f"SQ_INSTS_VALU_ADD_{prec}"] + f[f"SQ_INSTS_VALU_MUL_{prec}"]
+                   + 2 * f[f"SQ_INSTS_VALU_FMA_{prec}"])
+        tf = fl / (ms * 1e-3) / 1e12
+        out[prec.lower()] = {"flops": fl, "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak}
+    return out
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 30, runs: int = 10) -> float:
+    """Device-to-device copy rate (bytes read + bytes written per second, GB/s):
+    the HBM rate a plain streaming kernel reaches on this device."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(runs):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / runs
+    del src, dst
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 KERNEL_IDS = {"auto": None, "lane": 1, "layer": 2, "deep": 3}
 KERNEL_NAMES = {1: "k_solve_lane", 2: "k_solve_layer", 3: "k_deep_*"}
 
@@ -166,20 +205,23 @@ def time_oracle(work: dict, threads: int, runs: int) -> tuple[list, dict]:
     return times, ref
 
 
-def cpu_baseline(work, small: dict | None = None, runs: int = 5) -> tuple[dict, dict]:
+def cpu_baseline(work, small: dict | None = None, runs: int = 5,
+                 cfg4_sample: dict | None = None) -> tuple[dict, dict]:
     """The CPU oracle as it stands, timed on this host's cores: the median of
     `runs` whole FP64 solves of the benchmark workload on one thread and on all
     host threads, and the same for the small workload `small` if given.  The
     mixed-precision path has the same inputs and the same FP64 reference, so
-    its CPU baseline is this one.  Returns the timing block (headline value: all
-    threads on the benchmark workload) and the oracle's outputs of the last
-    all-thread solve."""
+    its CPU baseline is this one.  With `cfg4_sample` (1 % of the columns of the
+    10242 x 80 x 300 workload) the same timings of the sample, and the whole
+    workload's time extrapolated linearly in columns (stated as such).  Returns
+    the timing block (headline value: all threads on the benchmark workload) and
+    the oracle's outputs of the last all-thread solve."""
     threads = host_threads()
     nbg = lambda w: w["n_bins"] * w.get("n_gauss", 1)
     shape = lambda w: f"{w['n_cols']}x{w['n_layers']}x{nbg(w)}"
     per = {}
     ref = None
-    for tag, w in (("small", small), ("workload", work)):
+    for tag, w in (("small", small), ("workload", work), ("cfg4_sample", cfg4_sample)):
         if w is None:
             continue
         entry = {"shape": shape(w)}
@@ -190,9 +232,14 @@ def cpu_baseline(work, small: dict | None = None, runs: int = 5) -> tuple[dict, 
                                       "value": w["n_cols"] * nbg(w) / med}
             if tag == "workload" and nt == threads:
                 ref = r
+        if tag == "cfg4_sample":
+            entry["extrapolated"] = {f"{k}_s": v["median_s"] * 10242 / w["n_cols"]
+                                     for k, v in entry.items() if k.endswith("_threads")}
+            entry["note"] = ("1 % column sample (every 100th column) of 10242 x 80 x 300; "
+                             "whole-workload times extrapolated linearly in columns")
         per[tag] = entry
         print(f"[bench] cpu baseline {entry['shape']}: " + ", ".join(
-            f"{k} {v['median_s']:.3f} s" for k, v in entry.items() if k != "shape"),
+            f"{k} {v['median_s']:.3f} s" for k, v in entry.items() if k.endswith("_threads")),
             file=sys.stderr, flush=True)
     head = per["workload"][f"{threads}_threads"]
     return ({"value": head["value"], "unit": "column·bin solves/s", "cores": threads,
@@ -353,14 +400,16 @@ def serving(args, torch, rt, synth) -> dict:
     return out
 
 
-def high_resolution(args, torch, rt, synth) -> dict:
+def high_resolution(args, torch, rt, synth) -> tuple[dict, dict]:
     """The 10242 x 80 x 300 workload (FP64 and mixed, the kernel and tile the
     library picks): time per solve and the HBM roofline fraction."""
     work = synth.make("cfg4")
     C, N, NB = work["n_cols"], work["n_layers"], work["n_bins"]
     s = rt.Solver(work["lambda_edges"], work["F_star"])
     inp = rt.to_device(work)
+    sample = column_subset(work, np.arange(0, C, 100))   # 1 % of the columns, for the CPU oracle
     del work
+    copy_gbs = copy_bandwidth(torch)
     out = s.outputs(C, N)
     steps = max(3, min(args.steps, 10))
     res = {"workload": WORKLOADS["cfg4"], "n_cols": C, "n_layers": N, "n_bins": NB,
@@ -376,12 +425,13 @@ def high_resolution(args, torch, rt, synth) -> dict:
         res[tag] = {"ms_per_step": ms, "value": C * NB / (ms * 1e-3), "kernel": kname,
                     "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "copy_gbs": copy_gbs, "frac_vs_copy": ach / copy_gbs,
                                  "algorithmic_bytes": abytes,
                                  "traffic": traffic_from_profiles(kname, "cfg4")}}
     s.close()
     del inp, out
     torch.cuda.empty_cache()
-    return res
+    return res, sample
 
 
 def main():
@@ -475,6 +525,7 @@ def main():
     abytes = algorithmic_bytes(C, N, NB)
     achieved = abytes / (ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(kname) if WORKLOAD == "cfg1" else None
+    copy_gbs = copy_bandwidth(torch)
     line = {
         "metric": METRIC, "value": value, "unit": "column·bin solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -486,11 +537,13 @@ def main():
         "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "copy_gbs": copy_gbs, "frac_vs_copy": achieved / copy_gbs,
                      "traffic": traffic, "algorithmic_bytes": abytes,
                      "kernel": kname, "kernel_ms": ms},
     }
     if WORKLOAD == "cfg1":
         line["valu_issue"] = valu_issue(kname, ms)
+        line["fp_rate"] = fp_rates(kname, ms)
     if not args.no_mixed:
         print("[bench] timing mixed", file=sys.stderr, flush=True)
         wall_m, tot_m, per_m = time_path(s, inp, out, rt.RT_MIXED, args.steps, args.warmup,
@@ -503,11 +556,13 @@ def main():
                          "latency_ms": {"p50": pct(per_m, 50), "p99": pct(per_m, 99)},
                          "roofline": {"bound": "hbm", "achieved": ach_m, "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": ach_m / HBM_PEAK_GBS,
+                                      "copy_gbs": copy_gbs, "frac_vs_copy": ach_m / copy_gbs,
                                       "traffic": (traffic_from_profiles(kname_m)
                                                   if WORKLOAD == "cfg1" else None),
                                       "kernel": kname_m}}
         if WORKLOAD == "cfg1":
             line["mixed"]["valu_issue"] = valu_issue(kname_m, ms_m)
+            line["mixed"]["fp_rate"] = fp_rates(kname_m, ms_m)
     if args.compare_kernels:
         cmp = {}
         for kid, kn in KERNEL_NAMES.items():
@@ -524,12 +579,13 @@ def main():
         print("[bench] serving mix", file=sys.stderr, flush=True)
         line["serving"] = serving(args, torch, rt, synth)
         torch.cuda.empty_cache()
+    cfg4_sample = None
     if default and not args.no_cfg4:
-        line["cfg4"] = high_resolution(args, torch, rt, synth)
+        line["cfg4"], cfg4_sample = high_resolution(args, torch, rt, synth)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         small = synth.make("cfg0") if default else None
-        line["cpu_baseline"], ref = cpu_baseline(work, small, args.cpu_runs)
+        line["cpu_baseline"], ref = cpu_baseline(work, small, args.cpu_runs, cfg4_sample)
         if not work.get("sublayer") and work.get("n_gauss", 1) == 1:
             # the timed solves' errors against the oracle's result (all columns), and
             # against its binary128 build on every 10th column (the FP64 oracle's own
