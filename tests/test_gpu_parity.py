@@ -415,3 +415,44 @@ def test_cfg4_sampled(rt, torch):
                          floor_bin=FLOOR_BIN[prec], cols=cols)
         print(f"  precision={prec} errors={e}", flush=True)
         np.testing.assert_array_equal(out["flags"][cols], ref["flags"])
+
+
+def test_request_validation_before_launch(rt, torch):
+    """Argument and shape errors of a request reach the C-ABI and return
+    RT_EINVAL from rt_solve_fluxes, rt_solve_fluxes_noalloc and rt_submit
+    before any launch (the outputs keep their sentinel), and the handle
+    solves a valid request afterwards."""
+    w = small(C=40, N=6, NB=30, seed=91)
+    s = rt.Solver(w["lambda_edges"], w["F_star"])
+    inp = rt.to_device(w)
+    out = s.outputs(w["n_cols"], w["n_layers"])
+    for v in out.values():
+        v.fill_(7.0) if v.dtype == torch.float64 else v.fill_(7)
+    torch.cuda.synchronize()
+    good = s.request(inp, out, rt.RT_FP64, 0, rt.RT_KERNEL_LAYER)
+    odd = inp["dtau"].data_ptr() + 4
+    broken = {
+        "no columns": dict(n_cols=0), "no layers": dict(n_layers=0), "too many layers": dict(n_layers=4097),
+        "precision": dict(precision=7), "kernel": dict(kernel=9),
+        "deep with a tile": dict(kernel=rt.RT_KERNEL_DEEP, cols_per_block=2),
+        "FP32 storage in FP64": dict(input_dtype=1), "negative tile": dict(cols_per_block=-1),
+        "lane tile too wide": dict(kernel=rt.RT_KERNEL_LANE, cols_per_block=20), "no dtau": dict(dtau=None),
+        "no F_net": dict(F_net=None), "centre without T_center": dict(p_center=inp["p_iface"].data_ptr()),
+        "misaligned dtau": dict(dtau=odd),
+    }
+    for name, change in broken.items():
+        req = rt.RtRequest.from_buffer_copy(good)
+        for k, v in change.items():
+            setattr(req, k, v)
+        for call in (lambda r: rt.rt_solve_fluxes(s.h, r, None),
+                     lambda r: rt.rt_solve_fluxes_noalloc(s.h, r, None),
+                     lambda r: rt.rt_submit(s.h, r)):
+            with pytest.raises(rt.RtError) as e:
+                call(req)
+            assert e.value.status == rt.RT_EINVAL, (name, e.value.status)
+    torch.cuda.synchronize()
+    assert (out["F_net"] == 7.0).all() and (out["heating"] == 7.0).all()
+    ref = s.solve(inp, out=out, kernel=rt.RT_KERNEL_LAYER, cols_per_block=0)
+    torch.cuda.synchronize()
+    assert torch.isfinite(ref["F_net"]).all()
+    s.close()
