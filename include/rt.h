@@ -241,7 +241,7 @@ int32_t rt_request_kernel(rt_handle *h, const rt_request *req);
  * (same request) bit for bit.  With serve_mode = RT_SERVE_PERSISTENT, a
  * request that runs on the layer kernel with FP64 input storage goes instead
  * to a resident worker (one workgroup per compute unit, launched by the
- * library when work is waiting and ending by itself about a millisecond after
+ * library when work is waiting and ending by itself a fraction of a millisecond after
  * the last tile): the request's tiles are published to a ring in pinned host
  * memory as soon as a request slot (4096 per worker lifetime), ring space
  * (65536 tiles) and budget memory are free, and any idle workgroup takes the

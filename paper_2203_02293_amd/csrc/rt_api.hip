@@ -97,7 +97,7 @@ struct Job {
 // still running at the worker's launch waits for the next lifetime).
 constexpr int kRingCap = 1 << 16;
 constexpr int kSlotRing = 4096;
-constexpr int kIdlePolls = 400;
+constexpr int kIdlePolls = 50;
 
 // A request admitted to the persistent worker: its slot and its tiles
 // [first, first + ntiles) of the ring; tiles before `seen` have completed.

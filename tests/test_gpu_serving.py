@@ -293,7 +293,7 @@ def test_persistent_mix_equals_alone(rt, torch):
 
 
 def test_persistent_worker_relaunch_and_slot_lifetimes(rt, torch):
-    """The worker ends by itself about a millisecond after its last tile; a
+    """The worker ends by itself a fraction of a millisecond after its last tile; a
     request submitted later starts a new worker.  4200 small requests take
     more slots than one worker lifetime may use (4096), so the library also
     ends a lifetime under load and starts the next: every request completes
