@@ -1300,6 +1300,11 @@ __global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArg
             __hip_atomic_store(st, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             long long claim = -1;
             for (int it = 0;;) {
+                // a lifetime that has begun to end takes no more tiles: a few
+                // workgroups still on a tile would otherwise keep it alive and
+                // serve later requests alone; its unclaimed tiles go to the next
+                // lifetime, which the host launches once this one has ended
+                if (__hip_atomic_load(w.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                 const unsigned long long tail =
                     __hip_atomic_load(&w.q->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
                 unsigned long long h = __hip_atomic_load(w.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1316,8 +1321,7 @@ __global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArg
                 if (__hip_atomic_load(&w.q->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
                 // idle: leave together, so that the host relaunches a whole worker
                 // when work comes (workgroups still on a tile finish it first)
-                if (++it >= w.idle_polls ||
-                    __hip_atomic_load(w.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                if (++it >= w.idle_polls) {
                     __hip_atomic_store(w.exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
