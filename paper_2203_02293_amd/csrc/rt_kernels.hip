@@ -401,19 +401,43 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     return L;
 }
 
-template <bool MIXED, bool IN32>
+// A request's arguments in the constant address space: the kernel-argument
+// segment of a single-request launch, or the descriptor table of a batched
+// launch (written by the host before the launch); both stay unchanged while
+// the kernel runs, so their fields may be read with scalar loads.
+typedef const __attribute__((address_space(4))) SolveArgs *ArgsK;
+
 // status: where the tile ORs the condition bits that fail a request (a.status,
-// or the serving worker's word for the tile), or NULL.
+// or the serving worker's word for the tile), or NULL.  KARG: ka is the same
+// arguments in the constant address space (see args() below); otherwise ka is
+// unused.
+template <bool MIXED, bool IN32, bool KARG>
 __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int tile,
-                                                 uint32_t *const status)
+                                                 uint32_t *const status, ArgsK ka)
 {
     using R = typename std::conditional<MIXED, float, double>::type;
     // storage type of dtau, w0, g0 (FP32 on the mixed path only); loaded ahead
     // in it and turned into FP64 where used, so no load is waited for early
     using InT = typename std::conditional<IN32, float, double>::type;
-    const InT *const in_dt = reinterpret_cast<const InT *>(a.dtau);
-    const InT *const in_w = reinterpret_cast<const InT *>(a.w0);
-    const InT *const in_g = reinterpret_cast<const InT *>(a.g0);
+    // The fields read inside the loops come through args().  With KARG they are
+    // read from ka through a pointer made opaque (fresh()) at the top of each
+    // pass of a loop, so that each field is loaded with a scalar load where it
+    // is used: held for the whole kernel, the request's pointers outnumber the
+    // scalar registers, and the spilled ones come back through vector-lane
+    // moves of whole 16-register groups, which issue as vector instructions.
+    // Without KARG (the serving worker, whose copy of the arguments is written
+    // inside the kernel and so is not read through the scalar cache) they are
+    // the fields of a.
+    ArgsK ap = ka;
+    auto fresh = [&]() {
+#if defined(__HIP_DEVICE_COMPILE__)
+        if constexpr (KARG) asm volatile("" : "+s"(ap));
+#endif
+    };
+    auto args = [&]() -> const SolveArgs & {
+        if constexpr (KARG) return *(const SolveArgs *)ap;
+        else return a;
+    };
     extern __shared__ double smem[];
     char *lds = reinterpret_cast<char *>(smem);
     const int NB = a.NB, K = a.K, C = a.C, N = a.N, PC = a.PC, CH = a.CH;
@@ -494,8 +518,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // the two temperature arrays as values (a per-lane choice between two
     // argument fields would load the chosen pointer from the argument
     // segment and wait for it, and with it for every prefetch in flight)
-    const double *const T_if = a.T, *const T_ce = sub ? a.Tc : a.T;
     auto T_at = [&](int l, int cc) -> double {
+        const double *const T_if = args().T, *const T_ce = sub ? args().Tc : args().T;
         const double *base = (sub && (l & 1)) ? T_ce : T_if;
         return base[(long long)(sub ? (l >> 1) : l) * C + cc];
     };
@@ -601,13 +625,15 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         return (long long)(ctop(m) - 1 - iq[0]) * LB + toff + il[0];
     };
     auto has_item = [&](int m) { return iq[0] < cn(m) && icol[0]; };
-    auto load_dt = [&](int m) -> InT { return has_item(m) ? in_dt[item_idx(m)] : InT(0); };
+    auto load_dt = [&](int m) -> InT {
+        return has_item(m) ? reinterpret_cast<const InT *>(args().dtau)[item_idx(m)] : InT(0);
+    };
     auto load_wg = [&](int m, InT &w, InT &g) {
         w = g = InT(0);
         if (has_item(m)) {
             const long long idx = item_idx(m);
-            w = in_w[idx];
-            g = in_g[idx];
+            w = reinterpret_cast<const InT *>(args().w0)[idx];
+            g = reinterpret_cast<const InT *>(args().g0)[idx];
         }
     };
     auto load_T = [&](int m) -> double {
@@ -665,7 +691,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const double mu = s_mu[kk];
             Ly = layer_item<MIXED, R, MIXED>(dbuf(m)[q * T + l], w, g, mu > 0.0, mu, s_mu[K + kk],
                                       cF[q * T + l], cF[(q + 1) * T + l], cB[(q + 1) * T + l],
-                                      cB[q * T + l], a.o, inv_eps2, f);
+                                      cB[q * T + l], args().o, inv_eps2, f);
         }
         R *rp = rbuf(m) + (size_t)q * T + l;
         const size_t ps = (size_t)PC * T;
@@ -695,7 +721,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         for (int t = rot; t < nr * K; t += W) {
             const int q = t / K, kk = t - q * K;
             if (c0 + kk < C)
-                *out_at(a.F_beam, a.F_beam_c, ctop(m) - r0 - q, c0 + kk) = colsum_total(pbuf(m), q, kk, P);
+                *out_at(args().F_beam, args().F_beam_c, ctop(m) - r0 - q, c0 + kk) = colsum_total(pbuf(m), q, kk, P);
         }
     };
 
@@ -809,6 +835,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     ElimState st = elim_top(ftoa);
     for (int m = 0; m < NCH; ++m) {
         const int s = ctop(m), n = cn(m);
+        fresh();
         // Z(m)
         if (active) {
             const R *rb0 = rbuf(m);
@@ -836,7 +863,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                 x4 = y4;
                 x5 = y5;
                 xf = yf;
-                double2 *sp = reinterpret_cast<double2 *>(a.scratch) + ((long long)(s - 1 - q) * L + gl) * 2;
+                double2 *sp = reinterpret_cast<double2 *>(args().scratch) + ((long long)(s - 1 - q) * L + gl) * 2;
                 sp[0] = make_double2(rec.G, rec.H);
                 sp[1] = make_double2(rec.c, rec.d);
             }
@@ -923,6 +950,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             auto levels = [&](auto NBW) {
                 constexpr int NW = decltype(NBW)::value;
                 for (int i0 = 0; i0 <= N; i0 += RD) {
+                    fresh();
 #pragma unroll
                     for (int k = 0; k < RD; ++k) {
                         const int i = i0 + k;
@@ -931,10 +959,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                         ld(i + RD - 1, k);   // the layer below interface i + RD
                         if (yact) {
                             const long long o = (long long)i * LB + toff + yl;
-                            if (a.F_up_bin) a.F_up_bin[o] = Fu;
-                            if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
-                            if (i == N && a.F_up_toa_bin) {
-                                if (NG == 1) a.F_up_toa_bin[toff + yl] = Fu;
+                            if (args().F_up_bin) args().F_up_bin[o] = Fu;
+                            if (args().F_dn_bin) args().F_dn_bin[o] = Fd;
+                            if (i == N && args().F_up_toa_bin) {
+                                if (NG == 1) args().F_up_toa_bin[toff + yl] = Fu;
                                 else s_part[yl] = Fu;   // TOA spectrum, below
                             }
                         }
@@ -942,8 +970,8 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                         if constexpr (NW == 0) seg_sum2(su, sd, NBp);
                         else seg_sum2<NW>(su, sd);
                         if (outc) {
-                            *out_at(a.F_up, a.F_up_c, i, c0 + yk) = su;
-                            *out_at(a.F_dn, a.F_dn_c, i, c0 + yk) = sd;
+                            *out_at(args().F_up, args().F_up_c, i, c0 + yk) = su;
+                            *out_at(args().F_dn, args().F_dn_c, i, c0 + yk) = sd;
                         }
                     }
                 }
@@ -1021,13 +1049,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     __syncthreads();
     const int P = colsum_P(2 * CH);
     for (int i0 = 0; i0 <= N; i0 += CH) {
+        fresh();
         const int nch = min(CH, N + 1 - i0);
         rec_fetch(i0 + CH);   // the next pass (clamped, unused, after the last)
         // the beam flux of this thread's first bin-sum task, read ahead
         double fbp = 0.0;
         if (tid < K * nch) {
             const int ii = tid / K, kk = tid - ii * K;
-            if (c0 + kk < C) fbp = *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk);
+            if (c0 + kk < C) fbp = *out_at(args().F_beam, args().F_beam_c, i0 + ii, c0 + kk);
         }
         for (int ii = 0; ii < nch; ++ii) {
             const int i = i0 + ii;
@@ -1037,9 +1066,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
                     back_step(gh.x, gh.y, cd.x, cd.y, Fu, Fd);
                 }
                 const long long o = (long long)i * LB + toff + tid;
-                if (a.F_up_bin) a.F_up_bin[o] = Fu;
-                if (a.F_dn_bin) a.F_dn_bin[o] = Fd;
-                if (i == N && a.F_up_toa_bin && NG == 1) a.F_up_toa_bin[toff + tid] = Fu;
+                if (args().F_up_bin) args().F_up_bin[o] = Fu;
+                if (args().F_dn_bin) args().F_dn_bin[o] = Fd;
+                if (i == N && args().F_up_toa_bin && NG == 1) args().F_up_toa_bin[toff + tid] = Fu;
             }
             if (sweep) {
                 s_red[(0 * CH + ii) * T + tid] = Fu;
@@ -1052,9 +1081,9 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         auto level_out = [&](int ii, int kk, double su, double sd, double fb) {
             const int lev = i0 + ii, cc = c0 + kk;
             const double fn = su - sd - fb;
-            *out_at(a.F_up, a.F_up_c, lev, cc) = su;
-            *out_at(a.F_dn, a.F_dn_c, lev, cc) = sd;
-            *out_at(a.F_net, a.F_net_c, lev, cc) = fn;
+            *out_at(args().F_up, args().F_up_c, lev, cc) = su;
+            *out_at(args().F_dn, args().F_dn_c, lev, cc) = sd;
+            *out_at(args().F_net, args().F_net_c, lev, cc) = fn;
             if (!isfinite(fn)) atomicOr(&s_flag[kk], (uint32_t)F_NONFIN);
         };
         // rows 0..nch-1 hold F_up, rows CH..CH+nch-1 F_dn: both as one block of
@@ -1079,7 +1108,7 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
             const int ii = task / K, kk = task - ii * K;
             if (c0 + kk >= C) continue;
             level_out(ii, kk, colsum_total(s_part, ii, kk, P), colsum_total(s_part, CH + ii, kk, P),
-                      task == tid ? fbp : *out_at(a.F_beam, a.F_beam_c, i0 + ii, c0 + kk));
+                      task == tid ? fbp : *out_at(args().F_beam, args().F_beam_c, i0 + ii, c0 + kk));
         }
     }
     }
@@ -1144,7 +1173,9 @@ k_solve_lane_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ f
 template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(layer_max_threads(MIXED)) k_solve_layer(const SolveArgs a)
 {
-    solve_tile_layer<MIXED, IN32>(a, blockIdx.x, a.status);
+    // a is the kernel's only argument: offset 0 of the kernel-argument segment
+    solve_tile_layer<MIXED, IN32, true>(a, blockIdx.x, a.status,
+                                        (ArgsK)__builtin_amdgcn_kernarg_segment_ptr());
 }
 
 template <bool MIXED, bool IN32 = false>
@@ -1152,7 +1183,7 @@ __global__ void __launch_bounds__(layer_max_threads(MIXED))
 k_solve_layer_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ first, int n)
 {
     const int r = batch_slot(first, n, blockIdx.x);
-    solve_tile_layer<MIXED, IN32>(reqs[r], blockIdx.x - first[r], reqs[r].status);
+    solve_tile_layer<MIXED, IN32, true>(reqs[r], blockIdx.x - first[r], reqs[r].status, (ArgsK)(reqs + r));
 }
 
 int round64(int x) { return (x + 63) / 64 * 64; }
@@ -1356,8 +1387,8 @@ __global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArg
                 reinterpret_cast<const unsigned long long *>(w.slots + slot)[tid];
         __syncthreads();
         const SlotArgs &sa = *ta;
-        if (sa.mixed) solve_tile_layer<true, false>(sa.a, tile, st);
-        else solve_tile_layer<false, false>(sa.a, tile, st);
+        if (sa.mixed) solve_tile_layer<true, false, false>(sa.a, tile, st, nullptr);
+        else solve_tile_layer<false, false, false>(sa.a, tile, st, nullptr);
         // every thread's outputs and condition bits of this tile precede thread
         // 0's completion word
         __syncthreads();
