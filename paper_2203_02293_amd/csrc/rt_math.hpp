@@ -62,62 +62,58 @@ __host__ __device__ __forceinline__ R poly_eo(R y)
     }
 }
 
-// sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain.  On the device in
-// FP64 each step is a three-operand v_fma_f64 with the coefficient in a
-// register pair: written as fma() with a literal coefficient it compiles to a
-// 64-bit copy of the coefficient into the accumulator and the two-operand
-// v_fmac_f64 (one extra move per step; 3 % of the FP64 solve at 2562 columns
-// x 40 layers x 30 bins).  Same operation, same rounding.
-template <class R, class C, int J, int N>
-__host__ __device__ __forceinline__ R horner_y(R y)
-{
-    constexpr double cj = C::coef(J);
-    if constexpr (J + 1 >= N) {
-        return R(cj);
-    } else {
-#if defined(__HIP_DEVICE_COMPILE__)
-        if constexpr (sizeof(R) == 8) {
-            const R p = horner_y<R, C, J + 1, N>(y);
-            const R c = R(cj);
-            R out;
-            asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(y), "v"(c));
-            return out;
-        }
-#endif
-        return fma(horner_y<R, C, J + 1, N>(y), y, R(cj));
-    }
-}
-
-// FP64 sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain whose
-// coefficients are scalar operands of three-operand v_fma_f64 (materialised by
-// scalar moves, which issue beside the vector work): no coefficient occupies
-// a vector register or a vector move.
+// FP64 sum_{j=J}^{N-1} C::coef(j) y^(j-J) as one Horner chain of three-operand
+// v_fma_f64 whose coefficients are scalar operands, so no coefficient takes a
+// vector register or a vector move (written as fma() with a literal, each step
+// compiles to a 64-bit copy of the coefficient into the accumulator and the
+// two-operand v_fmac_f64).  z is an opaque zero (opaque_zero()): each
+// coefficient is built as its two 32-bit halves XOR z, one scalar instruction
+// with a literal operand per half, at its use.  As plain constants, the
+// coefficients of the loop body's chains (about 80 distinct doubles in the
+// Planck edges alone, more than the scalar registers hold) are hoisted out of
+// the loops and spilled, and come back through vector-lane moves, which issue
+// as vector instructions.  Same operation, same rounding.
 template <class C, int J, int N>
-__host__ __device__ __forceinline__ double horner_s(double y)
+__host__ __device__ __forceinline__ double horner_s(double y, uint32_t z)
 {
     constexpr double cj = C::coef(J);
     if constexpr (J + 1 >= N) {
         return cj;
     } else {
-        const double p = horner_s<C, J + 1, N>(y);
+        const double p = horner_s<C, J + 1, N>(y, z);
 #if defined(__HIP_DEVICE_COMPILE__)
+        constexpr uint64_t b = __builtin_bit_cast(uint64_t, cj);
+        const double c = __builtin_bit_cast(double, ((uint64_t)(z ^ (uint32_t)(b >> 32)) << 32) |
+                                                        (uint64_t)(z ^ (uint32_t)b));
         double out;
-        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(y), "s"(cj));
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(y), "s"(c));
         return out;
 #else
+        (void)z;
         return fma(p, y, cj);
 #endif
     }
 }
 
-// The polynomial by two chains in FP32 (shorter dependent chains); in FP64
-// by one (each extra FP64 constant and partial sum takes two registers, which
-// the FP64 kernel does not have to spare).
+// A zero the compiler cannot see through, new at every call (so that nothing
+// computed from it is hoisted out of a loop or shared between calls).
+__host__ __device__ __forceinline__ uint32_t opaque_zero()
+{
+    uint32_t z = 0;
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(z));
+#endif
+    return z;
+}
+
+// The polynomial by two chains in FP32 (shorter dependent chains); in FP64 by
+// one (each extra FP64 partial sum takes two registers, which the FP64 kernel
+// does not have to spare), with scalar coefficients.
 template <class R, class C, int N>
 __host__ __device__ __forceinline__ R poly(R y)
 {
     if constexpr (sizeof(R) == 4) return poly_eo<R, C, N>(y);
-    else return horner_y<R, C, 0, N>(y);
+    else return horner_s<C, 0, N>(y, opaque_zero());
 }
 
 // coefficients 1/(j+1)! of (e^r - 1)/r

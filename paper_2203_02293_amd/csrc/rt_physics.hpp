@@ -124,14 +124,14 @@ __host__ __device__ __forceinline__ bool wave_any(bool c)
 
 // FP64 large-x tail: sum_{n=1}^{M} e^{-nx} (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4)
 // = x^3 P_1(y) + 3x^2 P_2(y) + 6x P_3(y) + 6 P_4(y), y = e^{-x}, each P_S a
-// Horner chain in y (four independent chains).
+// Horner chain in y (four independent chains; z: an opaque zero, see horner_s).
 template <int M>
-__host__ __device__ __forceinline__ double planck_tail64(double x, double y)
+__host__ __device__ __forceinline__ double planck_tail64(double x, double y, uint32_t z)
 {
-    const double p1 = y * horner_s<InvPowCoef<1>, 0, M>(y);
-    const double p2 = y * horner_s<InvPowCoef<2>, 0, M>(y);
-    const double p3 = y * horner_s<InvPowCoef<3>, 0, M>(y);
-    const double p4 = y * horner_s<InvPowCoef<4>, 0, M>(y);
+    const double p1 = y * horner_s<InvPowCoef<1>, 0, M>(y, z);
+    const double p2 = y * horner_s<InvPowCoef<2>, 0, M>(y, z);
+    const double p3 = y * horner_s<InvPowCoef<3>, 0, M>(y, z);
+    const double p4 = y * horner_s<InvPowCoef<4>, 0, M>(y, z);
     return fma(x * x, fma(x, p1, 3.0 * p2), fma(6.0 * x, p3, 6.0 * p4));
 }
 
@@ -154,8 +154,9 @@ __host__ __device__ __forceinline__ R planck_edge(double xd)
         if constexpr (sizeof(R) == 4) {
             pb = poly_eo<R, BernCoef, Cfg::NQ>(x2);
         } else {
-            if (wave_any(x > 1.5)) pb = horner_s<BernCoef, 0, Cfg::NQ>(x2);
-            else pb = horner_s<BernCoef, 0, 15>(x2);
+            const uint32_t z = opaque_zero();
+            if (wave_any(x > 1.5)) pb = horner_s<BernCoef, 0, Cfg::NQ>(x2, z);
+            else pb = horner_s<BernCoef, 0, 15>(x2, z);
         }
         return x2 * x * (R(1.0 / 3.0) - R(0.125) * x + pb * x2);
     }
@@ -182,12 +183,13 @@ __host__ __device__ __forceinline__ R planck_edge(double xd)
         return -sum;
     } else {
         const R y = exp_em1(-x).e;
+        const uint32_t z = opaque_zero();
         R sum;
-        if (wave_any(x <= 39.1 / 8)) sum = planck_tail64<Cfg::NP>(x, y);
-        else if (wave_any(x <= 39.1 / 4)) sum = planck_tail64<8>(x, y);
-        else if (wave_any(x <= 39.1 / 2)) sum = planck_tail64<4>(x, y);
-        else if (wave_any(x <= 39.1)) sum = planck_tail64<2>(x, y);
-        else sum = planck_tail64<1>(x, y);
+        if (wave_any(x <= 39.1 / 8)) sum = planck_tail64<Cfg::NP>(x, y, z);
+        else if (wave_any(x <= 39.1 / 4)) sum = planck_tail64<8>(x, y, z);
+        else if (wave_any(x <= 39.1 / 2)) sum = planck_tail64<4>(x, y, z);
+        else if (wave_any(x <= 39.1)) sum = planck_tail64<2>(x, y, z);
+        else sum = planck_tail64<1>(x, y, z);
         return -sum;
     }
 }
