@@ -515,9 +515,10 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // Temperature of level l and the bin-summed output slot of level l: on the
     // sub-layer grid even levels are interfaces and odd levels layer centres.
     const bool sub = a.sub != 0;
-    // the two temperature arrays as values (a per-lane choice between two
-    // argument fields would load the chosen pointer from the argument
-    // segment and wait for it, and with it for every prefetch in flight)
+    // both temperature pointers read as uniform values, then one chosen per
+    // lane (a per-lane choice between the two argument fields would load the
+    // chosen pointer with a vector load and wait for it, and with it for every
+    // prefetch in flight)
     auto T_at = [&](int l, int cc) -> double {
         const double *const T_if = args().T, *const T_ce = sub ? args().Tc : args().T;
         const double *base = (sub && (l & 1)) ? T_ce : T_if;
