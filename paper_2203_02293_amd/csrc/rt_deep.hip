@@ -272,10 +272,16 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         }
         return R(kPref) * T2 * T2 * I;
     };
-    auto edge_val = [&](int e, double Tv) -> R { return planck_edge<R>(a.c2_over_lam[e] * rcp(Tv)); };
     const bool boa = bot == 0;
+    // inside the chunk loop the arguments (A) and the work-buffer layout (dl)
+    // come from the kernel-argument segment, re-read in each chunk (ArgsK)
+    ArgsK ap = kernel_args(a);
 
     for (int q0 = 0; q0 < nlev; q0 += QL) {
+        opaque_args(ap);
+        const SolveArgs &A = *(const SolveArgs *)ap;
+        const DeepLayout dl = deep_layout(A);
+        auto edge_val = [&](int e, double Tv) -> R { return planck_edge<R>(A.c2_over_lam[e] * rcp(Tv)); };
         const int hi = top - q0, n = min(QL, nlev - q0);
         // 1: the item's slab inputs (loads first, so they overlap the edge
         // integrals), the edge integrals, the partial sums above the segment
@@ -284,23 +290,23 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         const bool slab = item && ilev < top;   // slab ilev lies above level ilev
         double xdt = 0.0, xw = 0.0, xg = 0.0;
         if (slab) {
-            const long long idx = (long long)ilev * d.L + lc + ib;
-            xdt = ld_in(a.dtau, idx, a.in_f32);
-            xw = ld_in(a.w0, idx, a.in_f32);
-            xg = ld_in(a.g0, idx, a.in_f32);
+            const long long idx = (long long)ilev * dl.L + lc + ib;
+            xdt = ld_in(A.dtau, idx, A.in_f32);
+            xw = ld_in(A.w0, idx, A.in_f32);
+            xg = ld_in(A.g0, idx, A.in_f32);
         }
         if (q0 == 0 && iq < QL)
-            s_M[iq * NB + ib] = iq < s ? sum_strided(&seg_at(d, SG_TAU, iq, lc + ib), (long long)QL * d.L,
+            s_M[iq * NB + ib] = iq < s ? sum_strided(&seg_at(dl, SG_TAU, iq, lc + ib), (long long)QL * dl.L,
                                                      (s - iq + QL - 1) / QL)
                                        : 0.0;
         for (int e = tid; e < n * (NBR + 1); e += W) {
             const int q = e / (NBR + 1), k = e - q * (NBR + 1);
-            const double Tv = T_level(a, hi - q, c);
+            const double Tv = T_level(A, hi - q, c);
             if (k == 0 && (!(Tv > 0.0) || !isfinite(Tv))) fl |= F_INVALID;
             s_edge[q * (NBR + 1) + k] = edge_val(k, Tv);
         }
         if (boa && q0 == 0)
-            for (int e = tid; e <= NBR; e += W) s_edge[QL * (NBR + 1) + e] = edge_val(e, a.Tint[c]);
+            for (int e = tid; e <= NBR; e += W) s_edge[QL * (NBR + 1) + e] = edge_val(e, A.Tint[c]);
         if (item) s_tau[iq * NB + ib] = xdt;
         __syncthreads();
         // 2: optical depth down the lane: the segments above (first chunk),
@@ -317,26 +323,26 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
         // 3: level items
         for (int it = tid; it < n * NB; it += W) {
             const int q = it / NB, b = it - q * NB, lev = hi - q;
-            const double Tv = T_level(a, lev, c);
+            const double Tv = T_level(A, lev, c);
             const R B = bin_B(s_edge + q * (NBR + 1), b / NG, Tv);
             double Fb = 0.0;
             if (day) {
-                const double muF = mu * a.F_star[b / NG];
-                Fb = lev == a.N ? muF : beam_at<MIXED>(muF, s_tau[q * NB + b], inv_mu);
+                const double muF = mu * A.F_star[b / NG];
+                Fb = lev == A.N ? muF : beam_at<MIXED>(muF, s_tau[q * NB + b], inv_mu);
             }
             s_B[(q + 1) * NB + b] = B;
             s_Fb[(q + 1) * NB + b] = Fb;
-            if (lev > bot || boa) d.fb[(long long)lev * d.L + lc + b] = Fb;   // each level once
+            if (lev > bot || boa) dl.fb[(long long)lev * dl.L + lc + b] = Fb;   // each level once
         }
         if (boa && q0 == 0 && lane_thr)
-            d.lane[lc + tid] = double(kPI) * double(bin_B(s_edge + QL * (NBR + 1), tid / NG, a.Tint[c]));
+            dl.lane[lc + tid] = double(kPI) * double(bin_B(s_edge + QL * (NBR + 1), tid / NG, A.Tint[c]));
         __syncthreads();
         // 4: layer items, layer ilev between level ilev+1 (row iq) and level ilev (row iq+1)
         if (slab) {
             const int q = iq, b = ib;
             const Layer<R> Ly = layer_item<MIXED, R, MIXED>(xdt, xw, xg, day, mu, inv_mu,
                                                             s_Fb[q * NB + b], s_Fb[(q + 1) * NB + b],
-                                                            s_B[(q + 1) * NB + b], s_B[q * NB + b], a.o,
+                                                            s_B[(q + 1) * NB + b], s_B[q * NB + b], A.o,
                                                             inv_eps2, fl);
             // t and 1 - r from whichever of a value and its complement is the
             // smaller (both relatively exact): thin layers keep 1 - t and r to
@@ -345,16 +351,16 @@ __global__ void __launch_bounds__(deep_items_max_threads(MIXED)) k_deep_items(co
             const double t = Ly.t < R(0.5) ? double(Ly.t) : 1.0 - double(Ly.omt);
             const double r = double(Ly.r);
             const double omr = Ly.r < R(0.5) ? 1.0 - r : double(Ly.omr);
-            const double A = double(Ly.A);
-            double *cp = d.coef + (long long)ilev * 6 * d.L + lc + b;
+            const double At = double(Ly.A);
+            double *cp = dl.coef + (long long)ilev * 6 * dl.L + lc + b;
             cp[0] = t;
-            cp[d.L] = r;
-            cp[2 * d.L] = omr;
-            cp[3 * d.L] = A;
-            cp[4 * d.L] = double(Ly.Sup);
-            cp[5 * d.L] = double(Ly.Sdn);
+            cp[dl.L] = r;
+            cp[2 * dl.L] = omr;
+            cp[3 * dl.L] = At;
+            cp[4 * dl.L] = double(Ly.Sup);
+            cp[5 * dl.L] = double(Ly.Sdn);
             double *mp = s_M + q * 4 * NB + b;
-            const double rt = r * omr + t * t, at = A * (omr + t);
+            const double rt = r * omr + t * t, at = At * (omr + t);
             mp[0] = rt;
             mp[NB] = r;
             mp[2 * NB] = at;

@@ -61,6 +61,41 @@ __host__ __device__ __forceinline__ double ld_in(const double *p, long long i, i
     return f32 ? double(reinterpret_cast<const float *>(p)[i]) : p[i];
 }
 
+// A request's arguments in the constant address space: the kernel-argument
+// segment of a single-request launch, or the descriptor table of a batched
+// launch (written by the host before the launch); both stay unchanged while
+// the kernel runs, so their fields may be read with scalar loads.  The solve
+// kernels read the fields they use inside their loops through such a pointer,
+// made opaque (opaque_args) at the top of each loop pass, so that each field
+// is loaded with a scalar load where it is used: held for the whole kernel,
+// the request's pointers outnumber the scalar registers, and the spilled ones
+// come back through vector-lane moves of whole 16-register groups, which
+// issue as vector instructions.
+typedef const __attribute__((address_space(4))) SolveArgs *ArgsK;
+
+// The arguments of a kernel whose only argument is the SolveArgs a: its
+// kernel-argument segment (a at offset 0) on the GPU; a itself in the CPU
+// builds of the kernels.
+__host__ __device__ __forceinline__ ArgsK kernel_args(const SolveArgs &a)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    (void)a;
+    return (ArgsK)__builtin_amdgcn_kernarg_segment_ptr();
+#else
+    return (ArgsK)&a;
+#endif
+}
+
+// p, unchanged, as a value the compiler cannot follow past this point.
+__host__ __device__ __forceinline__ void opaque_args(ArgsK &p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(p));
+#else
+    (void)p;
+#endif
+}
+
 
 // What the launch shape depends on besides the problem: the device.
 struct DeviceLimits {

@@ -401,12 +401,6 @@ __host__ __device__ inline LpLayout lp_layout(int K, int NB, int NBR, int PC, in
     return L;
 }
 
-// A request's arguments in the constant address space: the kernel-argument
-// segment of a single-request launch, or the descriptor table of a batched
-// launch (written by the host before the launch); both stay unchanged while
-// the kernel runs, so their fields may be read with scalar loads.
-typedef const __attribute__((address_space(4))) SolveArgs *ArgsK;
-
 // status: where the tile ORs the condition bits that fail a request (a.status,
 // or the serving worker's word for the tile), or NULL.  KARG: ka is the same
 // arguments in the constant address space (see args() below); otherwise ka is
@@ -419,20 +413,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // storage type of dtau, w0, g0 (FP32 on the mixed path only); loaded ahead
     // in it and turned into FP64 where used, so no load is waited for early
     using InT = typename std::conditional<IN32, float, double>::type;
-    // The fields read inside the loops come through args().  With KARG they are
-    // read from ka through a pointer made opaque (fresh()) at the top of each
-    // pass of a loop, so that each field is loaded with a scalar load where it
-    // is used: held for the whole kernel, the request's pointers outnumber the
-    // scalar registers, and the spilled ones come back through vector-lane
-    // moves of whole 16-register groups, which issue as vector instructions.
-    // Without KARG (the serving worker, whose copy of the arguments is written
-    // inside the kernel and so is not read through the scalar cache) they are
-    // the fields of a.
+    // The fields read inside the loops come through args(): with KARG from ka
+    // (ArgsK), made opaque (fresh()) at the top of each pass of a loop; without
+    // KARG (the serving worker, whose copy of the arguments is written inside
+    // the kernel and so is not read through the scalar cache) from a.
     ArgsK ap = ka;
     auto fresh = [&]() {
-#if defined(__HIP_DEVICE_COMPILE__)
-        if constexpr (KARG) asm volatile("" : "+s"(ap));
-#endif
+        if constexpr (KARG) opaque_args(ap);
     };
     auto args = [&]() -> const SolveArgs & {
         if constexpr (KARG) return *(const SolveArgs *)ap;
@@ -1174,9 +1161,7 @@ k_solve_lane_batch(const SolveArgs *__restrict__ reqs, const int *__restrict__ f
 template <bool MIXED, bool IN32 = false>
 __global__ void __launch_bounds__(layer_max_threads(MIXED)) k_solve_layer(const SolveArgs a)
 {
-    // a is the kernel's only argument: offset 0 of the kernel-argument segment
-    solve_tile_layer<MIXED, IN32, true>(a, blockIdx.x, a.status,
-                                        (ArgsK)__builtin_amdgcn_kernarg_segment_ptr());
+    solve_tile_layer<MIXED, IN32, true>(a, blockIdx.x, a.status, kernel_args(a));
 }
 
 template <bool MIXED, bool IN32 = false>
