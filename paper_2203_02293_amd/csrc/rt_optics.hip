@@ -7,10 +7,12 @@
 // means of centre and interface values), Appendix C (Rayleigh cross
 // sections of H2 and He).
 //
-// One thread per output (slab, column, bin x Gaussian point), the point index
-// fastest: consecutive threads read consecutive k-table entries of the same
-// (T, p) cell and write consecutive outputs.  FP64 throughout; the work is a
-// few dozen operations per output, bound by the output writes.
+// One wavefront per (slab, column) cell: the cell's k-table bracket (grid
+// cell and interpolation weights in temperature and log pressure) is the same
+// for all of the cell's outputs (bin x Gaussian point) and is found once, as
+// wavefront-uniform values; the lanes then take the outputs 64 at a time, the
+// point index fastest, so consecutive lanes read consecutive k-table entries
+// of the same (T, p) cell and write consecutive outputs.  FP64 throughout.
 #include "rt_internal.hpp"
 
 #include <cmath>
@@ -37,15 +39,30 @@ struct Props {
     double kext, w0, g0;   // extinction per unit mass, albedo, asymmetry
 };
 
-__device__ __forceinline__ Props props_at(const OpticsArgs &a, double T, double p, int bg, int b)
+// A (T, p) point's k-table cell: lower corner (i, j) and weights (t, u).
+struct Cell {
+    int i, j;
+    double t, u;
+};
+
+__device__ __forceinline__ Cell cell_at(const OpticsArgs &a, double T, double p)
 {
     double x = T, y = log10(p);
-    const int i = bracket(a.temp, a.nT, x);
-    const int j = bracket(a.log10p, a.nP, y);
-    const double t = (x - a.temp[i]) / (a.temp[i + 1] - a.temp[i]);
-    const double u = (y - a.log10p[j]) / (a.log10p[j + 1] - a.log10p[j]);
+    Cell q;
+    q.i = bracket(a.temp, a.nT, x);
+    q.j = bracket(a.log10p, a.nP, y);
+    q.t = (x - a.temp[q.i]) / (a.temp[q.i + 1] - a.temp[q.i]);
+    q.u = (y - a.log10p[q.j]) / (a.log10p[q.j + 1] - a.log10p[q.j]);
+    return q;
+}
+
+// Properties of output bg (bin b) in the k-table cell q: bilinear opacity, then
+// the mixing of gas and condensate extinction and scattering.
+__device__ __forceinline__ Props props_at(const OpticsArgs &a, const Cell &q, int bg, int b)
+{
+    const double t = q.t, u = q.u;
     const long long row = (long long)a.nT * a.NBG;
-    const double *k0 = a.kappa + (long long)j * row + (long long)i * a.NBG + bg;
+    const double *k0 = a.kappa + (long long)q.j * row + (long long)q.i * a.NBG + bg;
     const double k00 = k0[0], k10 = k0[a.NBG], k01 = k0[row], k11 = k0[row + a.NBG];
     const double kap = (1 - t) * (1 - u) * k00 + t * (1 - u) * k10 + (1 - t) * u * k01 + t * u * k11;
     const double sg = a.sig_gas[b], sa = a.sig_cl_abs[b], ss = a.sig_cl_scat[b];
@@ -58,19 +75,18 @@ __device__ __forceinline__ Props props_at(const OpticsArgs &a, double T, double 
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_optics(const OpticsArgs a)
+constexpr int kOpticsThreads = 64;
+
+__global__ void __launch_bounds__(kOpticsThreads) k_optics(const OpticsArgs a)
 {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)a.C * a.NBG;
-    if (e >= (long long)a.S * per) return;
-    const int s = (int)(e / per);
-    const long long rem = e - (long long)s * per;
-    const int c = (int)(rem / a.NBG), bg = (int)(rem - (long long)c * a.NBG);
-    const int b = bg / a.NG;
+    const long long cell = blockIdx.x;   // s C + c
+    const int s = (int)(cell / a.C), c = (int)(cell - (long long)s * a.C);
+    // the cell's values: uniform across the wavefront
+    Cell q0, q1;
     double dp;
-    Props P;
     if (!a.sub) {
-        P = props_at(a, a.Tc[(long long)s * a.C + c], a.pc[(long long)s * a.C + c], bg, b);
+        q0 = cell_at(a, a.Tc[(long long)s * a.C + c], a.pc[(long long)s * a.C + c]);
+        q1 = q0;
         dp = a.p[(long long)s * a.C + c] - a.p[(long long)(s + 1) * a.C + c];
     } else {
         // sub-layer s between levels s and s+1: even levels interfaces, odd ones centres
@@ -82,15 +98,26 @@ __global__ void __launch_bounds__(256) k_optics(const OpticsArgs a)
         double T0, p0, T1, p1;
         lev(s, T0, p0);
         lev(s + 1, T1, p1);
-        const Props A = props_at(a, T0, p0, bg, b), B = props_at(a, T1, p1, bg, b);
-        P.kext = 0.5 * (A.kext + B.kext);
-        P.w0 = 0.5 * (A.w0 + B.w0);
-        P.g0 = 0.5 * (A.g0 + B.g0);
+        q0 = cell_at(a, T0, p0);
+        q1 = cell_at(a, T1, p1);
         dp = p0 - p1;
     }
-    a.dtau[e] = P.kext * dp / a.gravity;
-    a.w0[e] = P.w0;
-    a.g0[e] = P.g0;
+    for (int bg = threadIdx.x; bg < a.NBG; bg += kOpticsThreads) {
+        const int b = bg / a.NG;
+        Props P;
+        if (!a.sub) {
+            P = props_at(a, q0, bg, b);
+        } else {
+            const Props A = props_at(a, q0, bg, b), B = props_at(a, q1, bg, b);
+            P.kext = 0.5 * (A.kext + B.kext);
+            P.w0 = 0.5 * (A.w0 + B.w0);
+            P.g0 = 0.5 * (A.g0 + B.g0);
+        }
+        const long long e = cell * a.NBG + bg;
+        a.dtau[e] = P.kext * dp / a.gravity;
+        a.w0[e] = P.w0;
+        a.g0[e] = P.g0;
+    }
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
@@ -164,11 +191,10 @@ double rayleigh_bin_average(double lam_lo, double lam_hi, double x_h2, double x_
 
 hipError_t launch_optics(const OpticsArgs &a, hipStream_t s)
 {
-    const long long n = (long long)a.S * a.C * a.NBG;
-    if (n == 0) return hipSuccess;
-    const int threads = 256;
-    const long long blocks = (n + threads - 1) / threads;
-    hipLaunchKernelGGL(k_optics, dim3((unsigned)blocks), dim3(threads), 0, s, a);
+    const long long cells = (long long)a.S * a.C;
+    if (cells == 0 || a.NBG == 0) return hipSuccess;
+    if (cells > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_optics, dim3((unsigned)cells), dim3(kOpticsThreads), 0, s, a);
     return hipGetLastError();
 }
 
