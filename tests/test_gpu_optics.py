@@ -44,11 +44,13 @@ def device_atm(torch, atm):
             for k in ("p_iface", "T_iface", "p_center", "T_center")}
 
 
-@pytest.mark.parametrize("NG", [1, 4])
+# lanes per column (bins x points): within one wavefront pass (6, 24), three
+# passes with a ragged last (143), and the paper-like 30 x 20 (ten passes)
+@pytest.mark.parametrize("NB,NG", [(6, 1), (6, 4), (13, 11), (30, 20)])
 @pytest.mark.parametrize("sublayer", [False, True])
-def test_optics_elementwise(rt, torch, NG, sublayer):
-    atm, tab, gw, s = setup(rt, C=37, N=11, NB=6, NG=NG, seed=300 + NG)
-    print(f"\n[optics] NG={NG} sublayer={sublayer}", flush=True)
+def test_optics_elementwise(rt, torch, NB, NG, sublayer):
+    atm, tab, gw, s = setup(rt, C=37, N=11, NB=NB, NG=NG, seed=300 + NG)
+    print(f"\n[optics] NB={NB} NG={NG} sublayer={sublayer}", flush=True)
     out = s.optical_properties(device_atm(torch, atm), sublayer=sublayer)
     torch.cuda.synchronize()
     ref = O.optics(atm, tab, sublayer=sublayer)
