@@ -425,6 +425,23 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
         if constexpr (KARG) return *(const SolveArgs *)ap;
         else return a;
     };
+    // the layer inputs: without KARG their pointers are taken once, here (a
+    // read of a's fields after the kernel's own stores is a load again)
+    const InT *const in_dt0 = reinterpret_cast<const InT *>(a.dtau);
+    const InT *const in_w0 = reinterpret_cast<const InT *>(a.w0);
+    const InT *const in_g0 = reinterpret_cast<const InT *>(a.g0);
+    auto in_dt = [&]() -> const InT * {
+        if constexpr (KARG) return reinterpret_cast<const InT *>(args().dtau);
+        else return in_dt0;
+    };
+    auto in_w = [&]() -> const InT * {
+        if constexpr (KARG) return reinterpret_cast<const InT *>(args().w0);
+        else return in_w0;
+    };
+    auto in_g = [&]() -> const InT * {
+        if constexpr (KARG) return reinterpret_cast<const InT *>(args().g0);
+        else return in_g0;
+    };
     extern __shared__ double smem[];
     char *lds = reinterpret_cast<char *>(smem);
     const int NB = a.NB, K = a.K, C = a.C, N = a.N, PC = a.PC, CH = a.CH;
@@ -506,8 +523,13 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     // lane (a per-lane choice between the two argument fields would load the
     // chosen pointer with a vector load and wait for it, and with it for every
     // prefetch in flight)
+    const double *const T_if0 = a.T, *const T_ce0 = sub ? a.Tc : a.T;
     auto T_at = [&](int l, int cc) -> double {
-        const double *const T_if = args().T, *const T_ce = sub ? args().Tc : args().T;
+        const double *T_if = T_if0, *T_ce = T_ce0;
+        if constexpr (KARG) {
+            T_if = args().T;
+            T_ce = sub ? args().Tc : args().T;
+        }
         const double *base = (sub && (l & 1)) ? T_ce : T_if;
         return base[(long long)(sub ? (l >> 1) : l) * C + cc];
     };
@@ -614,14 +636,14 @@ __device__ __forceinline__ void solve_tile_layer(const SolveArgs &a, const int t
     };
     auto has_item = [&](int m) { return iq[0] < cn(m) && icol[0]; };
     auto load_dt = [&](int m) -> InT {
-        return has_item(m) ? reinterpret_cast<const InT *>(args().dtau)[item_idx(m)] : InT(0);
+        return has_item(m) ? in_dt()[item_idx(m)] : InT(0);
     };
     auto load_wg = [&](int m, InT &w, InT &g) {
         w = g = InT(0);
         if (has_item(m)) {
             const long long idx = item_idx(m);
-            w = reinterpret_cast<const InT *>(args().w0)[idx];
-            g = reinterpret_cast<const InT *>(args().g0)[idx];
+            w = in_w()[idx];
+            g = in_g()[idx];
         }
     };
     auto load_T = [&](int m) -> double {
