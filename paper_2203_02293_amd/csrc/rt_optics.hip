@@ -77,9 +77,8 @@ __device__ __forceinline__ Props props_at(const OpticsArgs &a, const Cell &q, in
 
 constexpr int kOpticsThreads = 64;
 
-__global__ void __launch_bounds__(kOpticsThreads) k_optics(const OpticsArgs a)
+__device__ __forceinline__ void optics_cell(const OpticsArgs &a, const long long cell)
 {
-    const long long cell = blockIdx.x;   // s C + c
     const int s = (int)(cell / a.C), c = (int)(cell - (long long)s * a.C);
     // the cell's values: uniform across the wavefront
     Cell q0, q1;
@@ -118,6 +117,13 @@ __global__ void __launch_bounds__(kOpticsThreads) k_optics(const OpticsArgs a)
         a.w0[e] = P.w0;
         a.g0[e] = P.g0;
     }
+}
+
+__global__ void __launch_bounds__(kOpticsThreads) k_optics(const OpticsArgs a)
+{
+    // cell = s C + c, over a grid of rows of gridDim.x workgroups
+    const long long cell = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    if (cell < (long long)a.S * a.C) optics_cell(a, cell);
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
@@ -193,8 +199,10 @@ hipError_t launch_optics(const OpticsArgs &a, hipStream_t s)
 {
     const long long cells = (long long)a.S * a.C;
     if (cells == 0 || a.NBG == 0) return hipSuccess;
-    if (cells > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_optics, dim3((unsigned)cells), dim3(kOpticsThreads), 0, s, a);
+    // one workgroup per cell: rows of up to 2^30 workgroups
+    const long long row = cells < (1LL << 30) ? cells : (1LL << 30);
+    const long long rows = (cells + row - 1) / row;
+    hipLaunchKernelGGL(k_optics, dim3((unsigned)row, (unsigned)rows), dim3(kOpticsThreads), 0, s, a);
     return hipGetLastError();
 }
 
