@@ -1313,10 +1313,10 @@ namespace {
 // host-published tail); the workgroup reads that request's arguments from
 // pinned host memory, solves the tile with the layer kernel's body in the
 // request's precision, and thread 0 stores the tile's completion word.  The
-// wait for work is bounded: after idle_polls polls without a tile (or once the
-// host sets stop, or another workgroup has idled out, and nothing is left to
-// claim), the workgroup exits, so every launch ends; the host launches the
-// worker again when it publishes more work.
+// wait for work is bounded: a workgroup exits after idle_polls polls without a
+// tile, or once the host has set stop and nothing is left to claim, or at its
+// next claim once another workgroup of the launch has idled out; so every
+// launch ends, and the host launches the worker again for the work left.
 __global__ void __launch_bounds__(kWorkerThreads) k_serve_worker(const WorkerArgs w)
 {
     extern __shared__ double smem[];
