@@ -6,7 +6,8 @@ replay is checked bit for bit against the eager solve, with the outputs
 overwritten by eager work and the device synchronised between replays, in both
 precisions: the layer kernel with wavefront bin sums, the deep kernel (seven
 launches), k-distribution bins (the layer kernel's LDS-staged
-back-substitution) and the sub-layer grid (centre outputs as well)."""
+back-substitution), the sub-layer grid (centre outputs as well), and on the
+mixed path FP32 storage of the layer inputs."""
 import numpy as np
 import pytest
 
@@ -47,17 +48,21 @@ def workload(synth, kind):
     return synth.make_sublayer(spec, n_cols=50), "layer"
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("kind", ["layer", "deep", "kdist", "sublayer"])
-def test_graph_replays_match_eager(rt, torch, precision, kind):
+# (kind, precision); in32: the layer request with dtau, w0, g0 stored as floats
+# (mixed path only)
+CASES = [(k, p) for k in ("layer", "deep", "kdist", "sublayer") for p in (0, 1)] + [("in32", 1)]
+
+
+@pytest.mark.parametrize("kind,precision", CASES, ids=[f"{k}-{p}" for k, p in CASES])
+def test_graph_replays_match_eager(rt, torch, kind, precision):
     from paper_2203_02293_amd import synth
-    w, kname = workload(synth, kind)
+    w, kname = workload(synth, "layer" if kind == "in32" else kind)
     kid = rt.RT_KERNEL_LAYER if kname == "layer" else rt.RT_KERNEL_DEEP
     C, N = w["n_cols"], w["n_layers"]
     sub = kind == "sublayer"
     print(f"graph case {kind} precision={precision} shape={C}x{N}x{w['n_bins']}", flush=True)
     s = rt.Solver(w["lambda_edges"], w["F_star"], gauss_weights=w.get("gauss_w"))
-    inp = rt.to_device(w)
+    inp = rt.to_device(w, input_f32=kind == "in32")
     kw = dict(precision=precision, kernel=kid, cols_per_block=0, noalloc=True)
     ref_out = s.outputs(C, N, sublayer=sub)
     s.solve(inp, out=ref_out, **kw)
